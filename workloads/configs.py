@@ -1,0 +1,114 @@
+"""Named synthetic workloads.
+
+The paper measures on curvilinear tetrahedral sphere meshes that are not
+available; these periodic curvilinear quadrilateral workloads stand in for
+them with the shapes that matter to the sweep: degree N = 3 (the paper's
+central degree), isoparametric curved elements with a Jacobian that varies
+inside every element, smooth or heterogeneous c^2, upwind fluxes, LSRK(5,4)
+steps at a fixed CFL number, and many independent time slices advanced
+together.
+
+  heat64   1D periodic heat equation, 64-point second-order differences,
+           T = 0.1, 16 slices x 25 steps, 8 seeded Fourier modes (seed 1).
+  wadg4    2D acoustic WADG, 4x4 elements, N=3, eps=0.05, c^2=1, tau=1,
+           T=0.1 over S=16 slices, 1 step per slice (dt = 6.25e-3), 8 modes
+           (seed 1); slice s starts from the exact solution at t_s.
+  wadg64   64x64 elements (256x256 nodes per field), N=3, eps=0.05, c^2=1,
+           tau=1, T=1 over S=64 slices of 32 steps (dt = 1/2048), 32 modes
+           (seed 2); slice s starts from the exact solution at t_s.
+  wadg128  128x128 elements (512x512 nodes per field), N=3, eps=0.05,
+           c^2 = 1 + 0.5 sin(2 pi x) sin(4 pi y), tau=1, S=256 slices of 10
+           steps (dt = 0.5/256/10); slice s starts from nodal p ~ U[-0.1,0.1]
+           with seed 3+s and u = 0.
+"""
+
+from dataclasses import dataclass, field
+from typing import Callable, Optional
+
+import numpy as np
+
+from .mesh import periodic_quad_mesh, QuadMesh
+from .fields import (smooth_pressure, uniform_pressure, c2_constant, c2_layered,
+                     pack_state, heat_initial)
+
+
+CONFIGS = {
+    "heat64": dict(kind="heat", n=64, T=0.1, slices=16, steps_per_slice=25, modes=8, seed=1),
+    "wadg4": dict(kind="wadg", K1D=4, N=3, eps=0.05, c2="const", tau=1.0, T=0.1,
+                  S=16, steps_per_slice=1, modes=8, seed=1, init="exact"),
+    "wadg64": dict(kind="wadg", K1D=64, N=3, eps=0.05, c2="const", tau=1.0, T=1.0,
+                   S=64, steps_per_slice=32, modes=32, seed=2, init="exact"),
+    "wadg128": dict(kind="wadg", K1D=128, N=3, eps=0.05, c2="layered", tau=1.0, T=0.5,
+                    S=256, steps_per_slice=10, seed=3, init="uniform"),
+}
+
+
+@dataclass
+class Problem:
+    name: str
+    mesh: QuadMesh
+    c2: Callable
+    tau_p: float
+    tau_u: float
+    nq1: int
+    S: int
+    dt: float
+    nsteps: int                 # steps per slice
+    slices: np.ndarray          # which slice indices Q0 holds
+    Q0: np.ndarray              # [len(slices)][3][Np][K] float64 start states
+    exact: Optional[object] = None
+    t_starts: Optional[np.ndarray] = None
+    params: dict = field(default_factory=dict)
+
+    @property
+    def N(self):
+        return self.mesh.N
+
+    @property
+    def K(self):
+        return self.mesh.K
+
+
+def make_problem(name, slices=None, nq1=None, **overrides):
+    """Build workload ``name`` (see module docstring).  ``slices`` selects a
+    subset of slice start states (default: all).  ``overrides`` replace config
+    entries (e.g. K1D, S, N, eps) for reduced variants used by tests."""
+    cfg = dict(CONFIGS[name])
+    cfg.update(overrides)
+    if cfg["kind"] != "wadg":
+        raise ValueError(f"{name} is not a WADG workload")
+    N, K1D = cfg["N"], cfg["K1D"]
+    mesh = periodic_quad_mesh(K1D, N, eps=cfg["eps"], rotate_seed=cfg.get("rotate_seed"))
+    c2 = c2_constant(1.0) if cfg["c2"] == "const" else c2_layered
+    S = cfg["S"]
+    dT = cfg["T"] / S
+    nsteps = cfg["steps_per_slice"]
+    dt = dT / nsteps
+    sl = np.arange(S) if slices is None else np.asarray(slices, dtype=np.int64)
+    Np = (N + 1) ** 2
+    fields = np.zeros((len(sl), 3, mesh.K, Np))
+    exact = None
+    t_starts = sl * dT
+    if cfg["init"] == "exact":
+        exact = smooth_pressure(mesh, cfg["modes"], cfg["seed"])
+        for i, t in enumerate(t_starts):
+            p, u, v = exact(mesh.x, mesh.y, t)
+            fields[i, 0], fields[i, 1], fields[i, 2] = p, u, v
+    elif cfg["init"] == "uniform":
+        for i, s in enumerate(sl):
+            fields[i, 0] = uniform_pressure(mesh, cfg["seed"] + int(s))
+    else:
+        raise ValueError(cfg["init"])
+    return Problem(name=name, mesh=mesh, c2=c2, tau_p=cfg["tau"], tau_u=cfg["tau"],
+                   nq1=(N + 2) if nq1 is None else nq1, S=S, dt=dt, nsteps=nsteps,
+                   slices=sl, Q0=pack_state(fields), exact=exact, t_starts=t_starts,
+                   params=cfg)
+
+
+def make_heat_problem(name="heat64"):
+    cfg = CONFIGS[name]
+    y0, amps, phases = heat_initial(cfg["n"], cfg["modes"], cfg["seed"])
+    total_steps = cfg["slices"] * cfg["steps_per_slice"]
+    return dict(y0=y0, amps=amps, phases=phases, n=cfg["n"], T=cfg["T"],
+                slices=cfg["slices"], steps_per_slice=cfg["steps_per_slice"],
+                dt=cfg["T"] / total_steps)
