@@ -1,0 +1,179 @@
+/*
+ * wadg.h -- C ABI of the MI355X (gfx950) weight-adjusted discontinuous
+ * Galerkin (WADG) sweep for the acoustic wave equation on curvilinear
+ * quadrilateral meshes.
+ *
+ * Method (Chan, Hewett, Warburton, "Weight-adjusted discontinuous Galerkin
+ * methods: curvilinear meshes"):
+ *   - semi-discrete system  M dQ/dt = A_h Q  with M block diagonal,
+ *     blocks M_{J^k}  (Section 4, opening);
+ *   - A_h Q is the strong-weak DG form of the first-order acoustic system,
+ *     rho = 1, penalties tau_p, tau_u (Section 4.1, equations of the
+ *     strong-weak formulation; Section 5.4 for its volume/surface terms);
+ *   - the mass inverse is replaced by the weight-adjusted approximation
+ *       M_{J}^{-1}     ~ Mhat^{-1} M_{1/J}   Mhat^{-1}   (velocity),
+ *       M_{J/c2}^{-1}  ~ Mhat^{-1} M_{c2/J}  Mhat^{-1}   (pressure),
+ *     applied matrix-free as P_q diag(w_q) V_q  (Section 4; Section 5.2,
+ *     equation of the matrix-free product; Section 6 for heterogeneous c2);
+ *   - time stepping by the low-storage five-stage fourth-order Runge-Kutta
+ *     scheme (Section 4.2.1).
+ * The system is autonomous, so no start time is needed: a slice is advanced
+ * by nsteps steps of size dt from the state it holds.
+ *
+ * Discretisation on the boundary:
+ *   reference square [-1,1]^2, tensor space Q^N; nodal basis at the
+ *   (N+1)^2 Gauss-Lobatto-Legendre (GLL) points, local node
+ *   n = a + (N+1) b (a along r, b along s); nq1-point Gauss-Legendre rule
+ *   per direction for volume integrals and per face for surface integrals.
+ *   Faces: 0: s=-1 (parameter r), 1: r=+1 (s), 2: s=+1 (r), 3: r=-1 (s).
+ *
+ * State layout (device, caller-owned, float64, C-contiguous), tiled by
+ * groups of 64 elements:
+ *   Q[s][g][f][n][l]   slice s in [0,S), element group g in [0,G) with
+ *                      G = ceil(K/64), field f in {p, u, v}, node n in
+ *                      [0,(N+1)^2), lane l in [0,64); element k = 64 g + l.
+ * One slice holds G*3*(N+1)^2*64 doubles; entries with 64 g + l >= K are
+ * padding: never read as state, ignored by the reductions, unspecified on
+ * output.
+ * wadg_state_doubles() gives the per-slice count.
+ *
+ * Errors: every int-returning call returns WADG_OK (0) or a negative code.
+ * Arguments are validated before any HIP call.  wadg_last_error() gives a
+ * thread-local message for the last failure.  Nothing throws across the ABI.
+ *
+ * Threading: a context may be used from one host thread at a time.  Calls
+ * on one context that run on different streams must not overlap in time.
+ */
+#ifndef WADG_H
+#define WADG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WADG_OK 0
+#define WADG_E_INVALID (-1)     /* null pointer, bad size or range          */
+#define WADG_E_GEOMETRY (-2)    /* J <= 0, non-finite or non-conforming mesh */
+#define WADG_E_UNSUPPORTED (-3) /* degree / quadrature not compiled in      */
+#define WADG_E_DEVICE (-4)      /* HIP runtime error (see wadg_last_error)  */
+#define WADG_E_NONFINITE (-5)   /* a result contains Inf or NaN             */
+
+#define WADG_MAX_N 4            /* degrees 1..4 are compiled in            */
+
+typedef struct wadg_ctx_s* wadg_ctx;
+
+/* Mesh and problem description.  All pointers are host memory, read during
+ * the call only (the library copies what it needs).
+ *   N        polynomial degree, 1 <= N <= WADG_MAX_N.
+ *   nq1      Gauss points per direction and per face, N+1 <= nq1 <= N+3.
+ *            (N+1 points are exact to degree 2N+1 in each variable, the
+ *            degree prescribed in Section 4; the default of the workloads
+ *            is N+2, see the design notes.)
+ *   K        number of elements, K >= 1.
+ *   x, y     [K][(N+1)^2] physical coordinates of each element's GLL nodes;
+ *            the element map is their degree-N interpolant (isoparametric).
+ *   etoe     [K][4] neighbour element across each local face.
+ *   etof     [K][4] neighbour's local face | (flip << 2); flip = 1 when the
+ *            neighbour parametrises the shared face in the opposite
+ *            direction.  Periodic meshes are allowed: matched face points
+ *            must coincide up to an integer translation.
+ *   c2q      [K][nq1*nq1] c^2 at the volume quadrature points q = i + nq1 j
+ *            (obtain their coordinates with wadg_quadrature_points), or NULL
+ *            for c^2 = 1.  Must be finite and > 0.
+ *   tau_p, tau_u  flux penalties >= 0 (1: upwind, 0: central; Section 4.1).
+ */
+typedef struct {
+  int32_t N;
+  int32_t nq1;
+  int32_t K;
+  const double* x;
+  const double* y;
+  const int32_t* etoe;
+  const int32_t* etof;
+  const double* c2q;
+  double tau_p;
+  double tau_u;
+} wadg_mesh;
+
+/* Host-only: physical coordinates of the volume quadrature points,
+ * xq, yq: caller-owned host arrays [K][nq1*nq1].  No GPU needed.
+ * Ignores mesh->c2q.  Returns WADG_E_INVALID / WADG_E_UNSUPPORTED on bad
+ * input. */
+int wadg_quadrature_points(const wadg_mesh* mesh, double* xq, double* yq);
+
+/* Host-only: the per-element geometric data the device kernels stream
+ * (Section 5.4: geometric factors at quadrature points; Section 5.2: 1/J at
+ * quadrature points; Section 6: c2/J), returned untiled.  Caller-owned host
+ * arrays:
+ *   vol  [6][nq1*nq1][K]: W ys, -W xs, -W yr, W xr (quadrature weight W
+ *        times J times r_x, r_y, s_x, s_y), c2/J, 1/J;
+ *   face [3][4][nq1][K]: outward unit normal n_x, n_y and w sJ (face
+ *        quadrature weight times surface Jacobian).
+ * Either pointer may be NULL.  Returns WADG_E_GEOMETRY if J <= 0 anywhere,
+ * a value is non-finite or the faces do not conform.  No GPU needed. */
+int wadg_geometry(const wadg_mesh* mesh, double* vol, double* face);
+
+/* Build a context on HIP device `device` (-1: the current device): validates
+ * the mesh, builds reference operators and geometry on the host and copies
+ * them to library-owned device memory.  On success *out holds the context;
+ * on failure *out is NULL. */
+int wadg_create(const wadg_mesh* mesh, int32_t device, wadg_ctx* out);
+
+/* Release the context and its device memory.  NULL is accepted. */
+void wadg_destroy(wadg_ctx ctx);
+
+/* Doubles in one slice of the tiled state layout: ceil(K/64)*3*(N+1)^2*64. */
+int wadg_state_doubles(wadg_ctx ctx, size_t* count);
+
+/* Bytes of caller-owned device workspace wadg_integrate needs for S slices
+ * (one residual array and one second state buffer: 2 * S * 8 *
+ * wadg_state_doubles). */
+int wadg_workspace_bytes(wadg_ctx ctx, int32_t S, size_t* bytes);
+
+/* One evaluation of the right-hand side dQ/dt = Mtilde^{-1} A_h Q for S
+ * slices (Section 4, opening; the WADG inverse of Section 5.2).
+ *   Q     device, S slices in the tiled state layout; input, not modified.
+ *   dQdt  device, same layout; output; must not alias Q.
+ *   stream  hipStream_t or NULL (the null stream).  Asynchronous. */
+int wadg_rhs(wadg_ctx ctx, const double* Q, double* dQdt, int32_t S, void* stream);
+
+/* Advance each of S independent slice states by nsteps LSRK(5,4) steps of
+ * size dt (Section 4.2.1), all slices concurrently.
+ *   Q     device, S slices in the tiled state layout; in: start states,
+ *         out: end states.
+ *   work  device workspace of wadg_workspace_bytes(S) bytes, 256-B aligned,
+ *         not aliasing Q; its contents on entry are ignored.
+ *   dt > 0 and finite, nsteps >= 0.  Asynchronous on `stream`. */
+int wadg_integrate(wadg_ctx ctx, double* Q, double* work, int32_t S, double dt,
+                   int32_t nsteps, void* stream);
+
+/* Per-slice reductions (the norms the convergence checks use):
+ *   out[s][0] = ||A_s - B_s||_2,  out[s][1] = ||B_s||_2,
+ *   out[s][2] = max |A_s - B_s|,  out[s][3] = 1 if every A_s entry is finite
+ *   else 0, over the 3*(N+1)^2*K state entries of slice s (padding is
+ *   skipped).  B may be NULL (treated as zero: out[s][0] = ||A_s||,
+ *   out[s][1] = 0).
+ *   A, B  device, S slices in the tiled state layout;  out: host [S][4].
+ * Synchronises `stream`.  Deterministic: fixed reduction order.  Returns
+ * WADG_E_NONFINITE (after filling out) if some A entry is not finite. */
+int wadg_norms(wadg_ctx ctx, const double* A, const double* B, int32_t S, double* out,
+               void* stream);
+
+/* Tuning: slices processed back to back on one element group (geometry
+ * reuse in L2).  g >= 1; default 8. */
+int wadg_set_slice_group(wadg_ctx ctx, int32_t g);
+
+/* Static description of a status code; never NULL. */
+const char* wadg_status_string(int status);
+
+/* Thread-local detail of the last failure on this thread ("" if none). */
+const char* wadg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WADG_H */

@@ -1,0 +1,228 @@
+"""Thin ctypes binding of ``libwadg.so`` (the C ABI in ``include/wadg.h``).
+
+Functions carry the C names and only marshal arguments: every step of the
+sweep runs in the HIP kernels of the library.  Device arrays may be passed
+as torch tensors (contiguous, float64, on a HIP device) or as raw integer
+device addresses; streams as ``torch.cuda.Stream`` objects, raw handles or
+``None`` (the current torch stream).
+
+The library must have been built (``python -m paper_1608_03836_amd.build``);
+importing this module without it raises immediately -- there is no
+fallback implementation.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libwadg.so")
+
+WADG_OK = 0
+WADG_E_INVALID = -1
+WADG_E_GEOMETRY = -2
+WADG_E_UNSUPPORTED = -3
+WADG_E_DEVICE = -4
+WADG_E_NONFINITE = -5
+WADG_MAX_N = 4
+TILE_LANES = 64
+
+_c_double_p = ctypes.POINTER(ctypes.c_double)
+_c_int32_p = ctypes.POINTER(ctypes.c_int32)
+
+
+class WadgError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+class wadg_mesh(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("nq1", ctypes.c_int32), ("K", ctypes.c_int32),
+                ("x", _c_double_p), ("y", _c_double_p),
+                ("etoe", _c_int32_p), ("etof", _c_int32_p), ("c2q", _c_double_p),
+                ("tau_p", ctypes.c_double), ("tau_u", ctypes.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1608_03836_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    sig = {
+        "wadg_quadrature_points": (ctypes.c_int, [ctypes.POINTER(wadg_mesh), _c_double_p, _c_double_p]),
+        "wadg_geometry": (ctypes.c_int, [ctypes.POINTER(wadg_mesh), _c_double_p, _c_double_p]),
+        "wadg_create": (ctypes.c_int, [ctypes.POINTER(wadg_mesh), ctypes.c_int32, ctypes.POINTER(vp)]),
+        "wadg_destroy": (None, [vp]),
+        "wadg_state_doubles": (ctypes.c_int, [vp, ctypes.POINTER(sz)]),
+        "wadg_workspace_bytes": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.POINTER(sz)]),
+        "wadg_rhs": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, vp]),
+        "wadg_integrate": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, ctypes.c_double,
+                                          ctypes.c_int32, vp]),
+        "wadg_norms": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, _c_double_p, vp]),
+        "wadg_set_slice_group": (ctypes.c_int, [vp, ctypes.c_int32]),
+        "wadg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "wadg_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+LIB = _load()
+EXPORTED = ("wadg_quadrature_points", "wadg_geometry", "wadg_create", "wadg_destroy",
+            "wadg_state_doubles", "wadg_workspace_bytes", "wadg_rhs", "wadg_integrate",
+            "wadg_norms", "wadg_set_slice_group", "wadg_status_string", "wadg_last_error")
+
+
+def _check(status):
+    if status != WADG_OK:
+        msg = LIB.wadg_last_error().decode() or LIB.wadg_status_string(status).decode()
+        raise WadgError(status, msg)
+
+
+# ----------------------------------------------------------------- marshalling
+class MeshDesc:
+    """Owns the host arrays behind a ``wadg_mesh`` struct.
+
+    ``x, y``: [K][(N+1)^2] GLL node coordinates; ``etoe, etof``: [K][4];
+    ``c2q``: [K][nq1^2] or None.
+    """
+
+    def __init__(self, N, nq1, x, y, etoe, etof, c2q=None, tau_p=1.0, tau_u=1.0):
+        self.x = np.ascontiguousarray(x, dtype=np.float64)
+        self.y = np.ascontiguousarray(y, dtype=np.float64)
+        self.etoe = np.ascontiguousarray(etoe, dtype=np.int32)
+        self.etof = np.ascontiguousarray(etof, dtype=np.int32)
+        self.c2q = None if c2q is None else np.ascontiguousarray(c2q, dtype=np.float64)
+        self.N, self.nq1, self.K = int(N), int(nq1), int(self.x.shape[0])
+        self.tau_p, self.tau_u = float(tau_p), float(tau_u)
+
+    def struct(self):
+        return wadg_mesh(
+            self.N, self.nq1, self.K,
+            self.x.ctypes.data_as(_c_double_p), self.y.ctypes.data_as(_c_double_p),
+            self.etoe.ctypes.data_as(_c_int32_p), self.etof.ctypes.data_as(_c_int32_p),
+            None if self.c2q is None else self.c2q.ctypes.data_as(_c_double_p),
+            self.tau_p, self.tau_u)
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, int):
+        return a
+    if hasattr(a, "data_ptr"):
+        if not a.is_contiguous():
+            raise ValueError("device tensors must be contiguous")
+        return a.data_ptr()
+    raise TypeError(f"cannot pass {type(a)} as a device pointer")
+
+
+def _stream(stream):
+    if stream is None:
+        try:
+            import torch
+            return torch.cuda.current_stream().cuda_stream
+        except Exception:   # no torch / no device: the null stream
+            return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ------------------------------------------------------------------ C names
+def wadg_quadrature_points(mesh):
+    Nq = mesh.nq1 * mesh.nq1
+    xq = np.empty((mesh.K, Nq))
+    yq = np.empty((mesh.K, Nq))
+    m = mesh.struct()
+    _check(LIB.wadg_quadrature_points(ctypes.byref(m), xq.ctypes.data_as(_c_double_p),
+                                      yq.ctypes.data_as(_c_double_p)))
+    return xq, yq
+
+
+def wadg_geometry(mesh):
+    Nq = mesh.nq1 * mesh.nq1
+    vol = np.empty((6, Nq, mesh.K))
+    face = np.empty((3, 4, mesh.nq1, mesh.K))
+    m = mesh.struct()
+    _check(LIB.wadg_geometry(ctypes.byref(m), vol.ctypes.data_as(_c_double_p),
+                             face.ctypes.data_as(_c_double_p)))
+    return vol, face
+
+
+def wadg_create(mesh, device=-1):
+    h = ctypes.c_void_p()
+    m = mesh.struct()
+    _check(LIB.wadg_create(ctypes.byref(m), int(device), ctypes.byref(h)))
+    return h
+
+
+def wadg_destroy(ctx):
+    LIB.wadg_destroy(ctx)
+
+
+def wadg_state_doubles(ctx):
+    n = ctypes.c_size_t()
+    _check(LIB.wadg_state_doubles(ctx, ctypes.byref(n)))
+    return n.value
+
+
+def wadg_workspace_bytes(ctx, S):
+    n = ctypes.c_size_t()
+    _check(LIB.wadg_workspace_bytes(ctx, int(S), ctypes.byref(n)))
+    return n.value
+
+
+def wadg_rhs(ctx, Q, dQdt, S, stream=None):
+    _check(LIB.wadg_rhs(ctx, _ptr(Q), _ptr(dQdt), int(S), _stream(stream)))
+
+
+def wadg_integrate(ctx, Q, work, S, dt, nsteps, stream=None):
+    _check(LIB.wadg_integrate(ctx, _ptr(Q), _ptr(work), int(S), float(dt), int(nsteps),
+                              _stream(stream)))
+
+
+def wadg_norms(ctx, A, B, S, stream=None, check_finite=True):
+    out = np.empty((int(S), 4))
+    st = LIB.wadg_norms(ctx, _ptr(A), _ptr(B), int(S), out.ctypes.data_as(_c_double_p),
+                        _stream(stream))
+    if st == WADG_E_NONFINITE and not check_finite:
+        return out
+    _check(st)
+    return out
+
+
+def wadg_set_slice_group(ctx, g):
+    _check(LIB.wadg_set_slice_group(ctx, int(g)))
+
+
+def wadg_status_string(status):
+    return LIB.wadg_status_string(int(status)).decode()
+
+
+def wadg_last_error():
+    return LIB.wadg_last_error().decode()
+
+
+# --------------------------------------------------------------- layout
+def tile_state(Qn):
+    """Natural layout [..., 3, Np, K] -> tiled [..., G, 3, Np, 64] (padding 0)."""
+    Qn = np.asarray(Qn, dtype=np.float64)
+    *lead, F, Np, K = Qn.shape
+    G = (K + TILE_LANES - 1) // TILE_LANES
+    pad = np.zeros(tuple(lead) + (F, Np, G * TILE_LANES))
+    pad[..., :K] = Qn
+    t = pad.reshape(tuple(lead) + (F, Np, G, TILE_LANES))
+    return np.ascontiguousarray(np.moveaxis(t, -2, -4))
+
+
+def untile_state(Qt, K):
+    """Tiled [..., G, 3, Np, 64] (or flat per slice) -> natural [..., 3, Np, K]."""
+    Qt = np.asarray(Qt)
+    *lead, G, F, Np, L = Qt.shape
+    n = np.moveaxis(Qt, -4, -2).reshape(tuple(lead) + (F, Np, G * L))
+    return np.ascontiguousarray(n[..., :K])

@@ -1,0 +1,353 @@
+// C ABI of the WADG sweep (declared in include/wadg.h): validation, host
+// setup, device memory of the context, and the stage loop.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "wadg.h"
+#include "wadg_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+// LSRK(5,4) 2N-storage coefficients (Carpenter & Kennedy 1994), the
+// integrator of the paper's experiments (Section 4.2.1).
+const double kRkA[5] = {0.0,
+                        -567301805773.0 / 1357537059087.0,
+                        -2404267990393.0 / 2016746695238.0,
+                        -3550918686646.0 / 2091501179385.0,
+                        -1275806237668.0 / 842570457699.0};
+const double kRkB[5] = {1432997174477.0 / 9575080441755.0,
+                        5161836677717.0 / 13612068292357.0,
+                        1720146321549.0 / 2090206949498.0,
+                        3134564353537.0 / 4481467310338.0,
+                        2277821191437.0 / 14882151754819.0};
+
+constexpr int kNormBlocks = 64;
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) return;
+    ok = (dev == prev) || hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+int check_mesh(const wadg_mesh* m) {
+  if (!m) return fail(WADG_E_INVALID, "mesh is NULL");
+  if (m->N < 1 || m->N > WADG_MAX_N)
+    return fail(WADG_E_UNSUPPORTED, "degree N must be in [1, " + std::to_string(WADG_MAX_N) + "]");
+  if (m->nq1 < m->N + 1 || m->nq1 > m->N + 3)
+    return fail(WADG_E_UNSUPPORTED, "nq1 must be in [N+1, N+3]");
+  if (m->K < 1) return fail(WADG_E_INVALID, "K must be >= 1");
+  if (!m->x || !m->y || !m->etoe || !m->etof)
+    return fail(WADG_E_INVALID, "mesh arrays must not be NULL");
+  if (!(m->tau_p >= 0.0) || !(m->tau_u >= 0.0) || !std::isfinite(m->tau_p) ||
+      !std::isfinite(m->tau_u))
+    return fail(WADG_E_INVALID, "tau_p and tau_u must be finite and >= 0");
+  // one slice of the tiled state must be addressable with 31-bit byte offsets
+  const long long groups = ((long long)m->K + wadg::kWave - 1) / wadg::kWave;
+  if (groups * 3 * (m->N + 1) * (m->N + 1) * wadg::kWave * 8 >= (1LL << 31))
+    return fail(WADG_E_INVALID, "K too large: one slice must stay below 2 GiB");
+  return WADG_OK;
+}
+
+wadg::MeshIn mesh_in(const wadg_mesh* m) {
+  return wadg::MeshIn{m->N, m->nq1, m->K, m->x, m->y, m->etoe, m->etof, m->c2q};
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = static_cast<const char*>(a);
+  const char* pb = static_cast<const char*>(b);
+  return pa < pb + nb && pb < pa + na;
+}
+
+}  // namespace
+
+struct wadg_ctx_s {
+  int device = 0;
+  int N = 0, nq1 = 0, K = 0;
+  double tau_p = 1.0, tau_u = 1.0;
+  int group = 8;
+  double* d_vol = nullptr;
+  double* d_face = nullptr;
+  int32_t* d_nbr = nullptr;
+  double* d_partials = nullptr;  // norms scratch, grown on demand
+  double* d_out = nullptr;
+  int32_t norms_cap = 0;
+  int groups() const { return (K + wadg::kWave - 1) / wadg::kWave; }
+  size_t tile() const { return (size_t)3 * (N + 1) * (N + 1) * wadg::kWave; }
+  size_t slice_doubles() const { return (size_t)groups() * tile(); }
+  size_t state_doubles(int32_t S) const { return (size_t)S * slice_doubles(); }
+};
+
+namespace {
+
+void free_ctx(wadg_ctx c) {
+  if (!c) return;
+  if (c->d_vol) (void)hipFree(c->d_vol);
+  if (c->d_face) (void)hipFree(c->d_face);
+  if (c->d_nbr) (void)hipFree(c->d_nbr);
+  if (c->d_partials) (void)hipFree(c->d_partials);
+  if (c->d_out) (void)hipFree(c->d_out);
+  delete c;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(WADG_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define WADG_HIP(call)                                  \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);   \
+  } while (0)
+
+int check_slices(wadg_ctx c, int32_t S) {
+  if (!c) return fail(WADG_E_INVALID, "context is NULL");
+  if (S < 1) return fail(WADG_E_INVALID, "S must be >= 1");
+  const long long nEG = (c->K + wadg::kWave - 1) / wadg::kWave;
+  if (nEG * (long long)S >= (1LL << 31)) return fail(WADG_E_INVALID, "too many slices");
+  return WADG_OK;
+}
+
+wadg::StageParams base_params(wadg_ctx c, int32_t S) {
+  wadg::StageParams p{};
+  p.vol = c->d_vol;
+  p.face = c->d_face;
+  p.nbr = c->d_nbr;
+  p.K = c->K;
+  p.S = S;
+  p.group = c->group < S ? c->group : S;
+  p.nEG = (c->K + wadg::kWave - 1) / wadg::kWave;
+  p.tau_p = c->tau_p;
+  p.tau_u = c->tau_u;
+  return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+int wadg_quadrature_points(const wadg_mesh* mesh, double* xq, double* yq) {
+  int st = check_mesh(mesh);
+  if (st) return st;
+  if (!xq || !yq) return fail(WADG_E_INVALID, "output arrays must not be NULL");
+  wadg::RefOps ops;
+  std::string err;
+  if (!wadg::build_ref_ops(mesh->N, mesh->nq1, &ops, &err)) return fail(WADG_E_UNSUPPORTED, err);
+  wadg::quadrature_points(mesh_in(mesh), ops, xq, yq);
+  return WADG_OK;
+}
+
+int wadg_geometry(const wadg_mesh* mesh, double* vol, double* face) {
+  int st = check_mesh(mesh);
+  if (st) return st;
+  wadg::RefOps ops;
+  std::string err;
+  if (!wadg::build_ref_ops(mesh->N, mesh->nq1, &ops, &err)) return fail(WADG_E_UNSUPPORTED, err);
+  std::vector<double> v, f;
+  int g = wadg::build_geometry(mesh_in(mesh), ops, &v, &f, nullptr, &err);
+  if (g) return fail(g == -1 ? WADG_E_INVALID : WADG_E_GEOMETRY, err);
+  if (vol) std::memcpy(vol, v.data(), v.size() * sizeof(double));
+  if (face) std::memcpy(face, f.data(), f.size() * sizeof(double));
+  return WADG_OK;
+}
+
+int wadg_create(const wadg_mesh* mesh, int32_t device, wadg_ctx* out) {
+  if (!out) return fail(WADG_E_INVALID, "out is NULL");
+  *out = nullptr;
+  int st = check_mesh(mesh);
+  if (st) return st;
+  if (!wadg::stage_supported(mesh->N, mesh->nq1))
+    return fail(WADG_E_UNSUPPORTED, "degree / quadrature not compiled in");
+  wadg::RefOps ops;
+  std::string err;
+  if (!wadg::build_ref_ops(mesh->N, mesh->nq1, &ops, &err)) return fail(WADG_E_UNSUPPORTED, err);
+  std::vector<double> vol0, face0;
+  std::vector<int32_t> nbr0;
+  int g = wadg::build_geometry(mesh_in(mesh), ops, &vol0, &face0, &nbr0, &err);
+  if (g) return fail(g == -1 ? WADG_E_INVALID : WADG_E_GEOMETRY, err);
+  const int nq = mesh->nq1;
+  std::vector<double> vol = wadg::tile_planes(vol0, 6 * nq * nq, mesh->K);
+  std::vector<double> face = wadg::tile_planes(face0, 12 * nq, mesh->K);
+  std::vector<int32_t> nbr = wadg::tile_planes(nbr0, 8, mesh->K);
+
+  int dev = device;
+  if (dev < 0) WADG_HIP(hipGetDevice(&dev));
+  DeviceGuard guard(dev);
+  if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select HIP device " + std::to_string(dev));
+
+  wadg_ctx c = new wadg_ctx_s();
+  c->device = dev;
+  c->N = mesh->N;
+  c->nq1 = mesh->nq1;
+  c->K = mesh->K;
+  c->tau_p = mesh->tau_p;
+  c->tau_u = mesh->tau_u;
+  hipError_t e;
+  if ((e = hipMalloc(&c->d_vol, vol.size() * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc(&c->d_face, face.size() * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc(&c->d_nbr, nbr.size() * sizeof(int32_t))) != hipSuccess ||
+      (e = hipMemcpy(c->d_vol, vol.data(), vol.size() * sizeof(double),
+                     hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(c->d_face, face.data(), face.size() * sizeof(double),
+                     hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(c->d_nbr, nbr.data(), nbr.size() * sizeof(int32_t),
+                     hipMemcpyHostToDevice)) != hipSuccess) {
+    free_ctx(c);
+    return hip_fail(e, "wadg_create device setup");
+  }
+  *out = c;
+  return WADG_OK;
+}
+
+void wadg_destroy(wadg_ctx ctx) {
+  if (!ctx) return;
+  DeviceGuard guard(ctx->device);
+  free_ctx(ctx);
+}
+
+int wadg_state_doubles(wadg_ctx ctx, size_t* count) {
+  if (!ctx) return fail(WADG_E_INVALID, "context is NULL");
+  if (!count) return fail(WADG_E_INVALID, "count is NULL");
+  *count = ctx->slice_doubles();
+  return WADG_OK;
+}
+
+int wadg_workspace_bytes(wadg_ctx ctx, int32_t S, size_t* bytes) {
+  int st = check_slices(ctx, S);
+  if (st) return st;
+  if (!bytes) return fail(WADG_E_INVALID, "bytes is NULL");
+  *bytes = 2 * ctx->state_doubles(S) * sizeof(double);
+  return WADG_OK;
+}
+
+int wadg_set_slice_group(wadg_ctx ctx, int32_t g) {
+  if (!ctx) return fail(WADG_E_INVALID, "context is NULL");
+  if (g < 1) return fail(WADG_E_INVALID, "slice group must be >= 1");
+  ctx->group = g;
+  return WADG_OK;
+}
+
+int wadg_rhs(wadg_ctx ctx, const double* Q, double* dQdt, int32_t S, void* stream) {
+  int st = check_slices(ctx, S);
+  if (st) return st;
+  if (!Q || !dQdt) return fail(WADG_E_INVALID, "Q and dQdt must not be NULL");
+  const size_t nbytes = ctx->state_doubles(S) * sizeof(double);
+  if (overlaps(Q, nbytes, dQdt, nbytes)) return fail(WADG_E_INVALID, "dQdt must not alias Q");
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select the context's device");
+  wadg::StageParams p = base_params(ctx, S);
+  p.Qin = Q;
+  p.Qout = dQdt;
+  p.res = nullptr;
+  int e = wadg::launch_stage(ctx->N, ctx->nq1, true, p, stream);
+  if (e) return hip_fail((hipError_t)e, "stage kernel launch");
+  return WADG_OK;
+}
+
+int wadg_integrate(wadg_ctx ctx, double* Q, double* work, int32_t S, double dt, int32_t nsteps,
+                   void* stream) {
+  int st = check_slices(ctx, S);
+  if (st) return st;
+  if (!Q || !work) return fail(WADG_E_INVALID, "Q and work must not be NULL");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(WADG_E_INVALID, "dt must be finite and > 0");
+  if (nsteps < 0) return fail(WADG_E_INVALID, "nsteps must be >= 0");
+  const size_t n = ctx->state_doubles(S);
+  if (overlaps(Q, n * sizeof(double), work, 2 * n * sizeof(double)))
+    return fail(WADG_E_INVALID, "work must not alias Q");
+  if (nsteps == 0) return WADG_OK;
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select the context's device");
+  double* res = work;
+  double* other = work + n;
+  double* cur = Q;
+  wadg::StageParams p = base_params(ctx, S);
+  p.res = res;
+  p.dt = dt;
+  for (int stp = 0; stp < nsteps; ++stp)
+    for (int i = 0; i < 5; ++i) {
+      p.Qin = cur;
+      p.Qout = (cur == Q) ? other : Q;
+      p.rkA = kRkA[i];
+      p.rkB = kRkB[i];
+      int e = wadg::launch_stage(ctx->N, ctx->nq1, false, p, stream);
+      if (e) return hip_fail((hipError_t)e, "stage kernel launch");
+      cur = p.Qout;
+    }
+  if (cur != Q)
+    WADG_HIP(hipMemcpyAsync(Q, cur, n * sizeof(double), hipMemcpyDeviceToDevice,
+                            static_cast<hipStream_t>(stream)));
+  return WADG_OK;
+}
+
+int wadg_norms(wadg_ctx ctx, const double* A, const double* B, int32_t S, double* out,
+               void* stream) {
+  int st = check_slices(ctx, S);
+  if (st) return st;
+  if (!A || !out) return fail(WADG_E_INVALID, "A and out must not be NULL");
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select the context's device");
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  if (S > ctx->norms_cap) {
+    // scratch grows with the largest S seen; the stream is drained first so
+    // that no queued reduction still reads the old buffers
+    WADG_HIP(hipStreamSynchronize(hs));
+    if (ctx->d_partials) (void)hipFree(ctx->d_partials);
+    if (ctx->d_out) (void)hipFree(ctx->d_out);
+    ctx->d_partials = nullptr;
+    ctx->d_out = nullptr;
+    ctx->norms_cap = 0;
+    WADG_HIP(hipMalloc(&ctx->d_partials, (size_t)S * kNormBlocks * 4 * sizeof(double)));
+    WADG_HIP(hipMalloc(&ctx->d_out, (size_t)S * 4 * sizeof(double)));
+    ctx->norms_cap = S;
+  }
+  const int64_t per = (int64_t)ctx->slice_doubles();
+  int e = wadg::launch_norms(A, B, S, per, (int32_t)ctx->tile(), ctx->K, ctx->d_partials,
+                             kNormBlocks, ctx->d_out, stream);
+  if (e) return hip_fail((hipError_t)e, "norms kernel launch");
+  WADG_HIP(hipMemcpyAsync(out, ctx->d_out, (size_t)S * 4 * sizeof(double),
+                          hipMemcpyDeviceToHost, hs));
+  WADG_HIP(hipStreamSynchronize(hs));
+  bool all_finite = true;
+  for (int s = 0; s < S; ++s) {
+    out[4 * s + 0] = std::sqrt(out[4 * s + 0]);
+    out[4 * s + 1] = std::sqrt(out[4 * s + 1]);
+    if (out[4 * s + 3] != 0.0) all_finite = false;
+    out[4 * s + 3] = out[4 * s + 3] != 0.0 ? 0.0 : 1.0;
+  }
+  if (!all_finite) return fail(WADG_E_NONFINITE, "non-finite entries in A");
+  return WADG_OK;
+}
+
+const char* wadg_status_string(int status) {
+  switch (status) {
+    case WADG_OK: return "ok";
+    case WADG_E_INVALID: return "invalid argument";
+    case WADG_E_GEOMETRY: return "invalid geometry";
+    case WADG_E_UNSUPPORTED: return "unsupported degree or quadrature";
+    case WADG_E_DEVICE: return "HIP device error";
+    case WADG_E_NONFINITE: return "non-finite values";
+    default: return "unknown status";
+  }
+}
+
+const char* wadg_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,540 @@
+// Fused WADG stage kernel for gfx950.
+//
+// One LSRK stage of the WADG acoustic sweep for S slices at once, or one
+// right-hand-side evaluation.  A workgroup owns one 64-element group of one
+// slice and has two waves: lane l of wave 0 computes the pressure equation
+// of element l, lane l of wave 1 the two velocity equations of the same
+// element.  State and geometry are tiled by element group with the lane
+// index fastest, so every per-node access of a wave is one contiguous
+// 512-byte access at a compile-time offset inside the group's tile, and
+// every reference-operator entry is wave-uniform: the 1D tables are
+// compile-time constants folded into the instruction stream.
+//
+// The group's input tile (3 (N+1)^2 x 64 doubles) is first copied into LDS
+// by both waves with 16-byte coalesced loads, so every first-touch HBM read
+// of the stage is in flight at once; the waves then re-read their own nodal
+// values from LDS (lane-contiguous, conflict-free) instead of keeping them
+// in registers.  Per lane:
+//
+//   a1  own face nodes (LDS) and the neighbours' face nodes (gathered from
+//       the input slice through precomputed byte offsets, flip-aware),
+//       interpolated to the face Gauss points;
+//   a2  volume term of the strong-weak form (Section 4.1; Section 5.4,
+//       volume kernel): u, v (pressure wave) or grad p (velocity wave) at the
+//       volume Gauss points through the tensor factors of V_q, V_q^r, V_q^s,
+//       times the weighted metric terms, and back to the nodes through the
+//       transposed factors -- one quadrature column at a time, with the next
+//       column's metric terms loaded while the current one is computed;
+//   a3  penalised numerical flux and its lift (Section 5.4, surface kernel;
+//       with GLL nodes the lift of face f touches only that face's nodes);
+//   a4  weight-adjusted mass inverse P_q diag(w_q) V_q (Section 5.2, the
+//       matrix-free product; w = c2/J for p and 1/J for u, v, Section 6),
+//       with Mhat^{-1} folded into the first factor (V_q Mhat^{-1});
+//   a5  the 2N-storage stage update res <- A res + dt dQ, Q <- Q + B res,
+//       reading Q from one buffer and writing the other, so that neighbour
+//       gathers never see a partly updated state.
+//
+// Workgroup -> (slice, element group): workgroups are dealt to the 8 XCDs
+// round-robin; each XCD receives a contiguous range of the logical order
+// (slice group, element group, slice in group), so the slices of one group
+// share the element group's geometry in that XCD's L2.
+
+#include <hip/hip_runtime.h>
+
+#include "reference_tables.h"
+#include "wadg_internal.h"
+
+namespace wadg {
+namespace {
+
+// Memory access through buffer resources: the base address and size of an
+// array live in four scalar registers, the per-plane offset (node, field,
+// quadrature point -- wave-uniform) in the instruction's offset fields, and
+// the per-lane offset in one vector register shared by every access to the
+// same tile.  Accesses outside the resource return zero instead of faulting.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+typedef unsigned int u32x2 __attribute__((vector_size(8)));
+typedef unsigned int u32x4 __attribute__((vector_size(16)));
+constexpr int kRsrcWord3 = 0x00020000;   // raw dword buffer, gfx9 family
+constexpr unsigned kPlane = kWave * 8;   // bytes of one 64-lane plane
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                           kRsrcWord3);
+}
+__device__ __forceinline__ double ld(rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ void st(rsrc_t r, unsigned voff, unsigned soff, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ int ldi(rsrc_t r, unsigned voff, unsigned soff) {
+  return (int)__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+}
+
+// Compiler-only barriers (no instructions are emitted).  order() keeps memory
+// operations on their side of it, so a column's prefetches are issued before
+// the previous column's arithmetic and LDS re-reads are not hoisted;
+// pin(a) forces the values of `a` to be computed at that point, so the
+// arithmetic of a quadrature column or face is not sunk towards the final
+// stores (which would keep every loaded operand live to the end).
+__device__ __forceinline__ void order() { asm volatile("" ::: "memory"); }
+template <int M>
+__device__ __forceinline__ void pin(double (&a)[M]) {
+#pragma unroll
+  for (int i = 0; i < M; ++i) asm volatile("" : "+v"(a[i]));
+}
+
+// local node index of face node m (face parameter order) on face f
+template <int N>
+__device__ constexpr int fnode(int f, int m) {
+  return f == 0 ? m : f == 1 ? (N + (N + 1) * m) : f == 2 ? (m + (N + 1) * N) : ((N + 1) * m);
+}
+
+// Buffer resources of one workgroup: the group's tiles of the state arrays
+// and of the geometry, and the whole input slice for neighbour gathers.
+struct Bufs {
+  rsrc_t qin, qout, res, qslice, vol, face, nbr;
+};
+
+// dq = P_q diag(w) (V_q Mhat^{-1}) b in tensor form; w at the volume points
+// (planes wplane .. wplane + NQ^2 of the geometry tile).
+template <int N, int NQ>
+__device__ __forceinline__ void wadg_inverse(const double (&b)[(N + 1) * (N + 1)], const Bufs& B,
+                                             unsigned wplane, unsigned kb,
+                                             double (&dq)[(N + 1) * (N + 1)]) {
+  constexpr ct::Tables<N, NQ> T = ct::make_tables<N, NQ>();
+  constexpr int NP1 = N + 1;
+#pragma unroll
+  for (int n = 0; n < NP1 * NP1; ++n) dq[n] = 0.0;
+  double wc[NQ], wn[NQ];
+#pragma unroll
+  for (int j = 0; j < NQ; ++j) wc[j] = ld(B.vol, kb, (wplane + NQ * j) * kPlane);
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    if (i + 1 < NQ) {
+#pragma unroll
+      for (int j = 0; j < NQ; ++j) wn[j] = ld(B.vol, kb, (wplane + i + 1 + NQ * j) * kPlane);
+    }
+    order();
+    double t[NP1];
+#pragma unroll
+    for (int bb = 0; bb < NP1; ++bb) {
+      double acc = 0.0;
+#pragma unroll
+      for (int a = 0; a < NP1; ++a) acc += T.Vt[i][a] * b[a + NP1 * bb];
+      t[bb] = acc;
+    }
+    double c[NP1];
+#pragma unroll
+    for (int bb = 0; bb < NP1; ++bb) c[bb] = 0.0;
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) {
+      double rq = 0.0;
+#pragma unroll
+      for (int bb = 0; bb < NP1; ++bb) rq += T.Vt[j][bb] * t[bb];
+      rq *= wc[j];
+#pragma unroll
+      for (int bb = 0; bb < NP1; ++bb) c[bb] += T.P[bb][j] * rq;
+    }
+#pragma unroll
+    for (int bb = 0; bb < NP1; ++bb)
+#pragma unroll
+      for (int a = 0; a < NP1; ++a) dq[a + NP1 * bb] += T.P[a][i] * c[bb];
+    pin(dq);
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) wc[j] = wn[j];
+  }
+}
+
+// a5 for field c: res <- A res + dt dq; Qout <- Qin + B res  (or dQ/dt).
+// `resv` holds the residual prefetched before the WADG product.
+template <int NP, bool RHS>
+__device__ __forceinline__ void finish_field(const StageParams& p, const Bufs& B,
+                                             const double* tq, int c, unsigned kb, int lane,
+                                             bool active, const double (&resv)[NP],
+                                             const double (&dq)[NP]) {
+  if (!active) return;
+  if constexpr (RHS) {
+#pragma unroll
+    for (int n = 0; n < NP; ++n) st(B.qout, kb, (c * NP + n) * kPlane, dq[n]);
+  } else {
+    const double A = p.rkA, Bc = p.rkB, dt = p.dt;
+#pragma unroll
+    for (int n = 0; n < NP; ++n) {
+      const unsigned so = (c * NP + n) * kPlane;
+      const double r = A * resv[n] + dt * dq[n];
+      st(B.res, kb, so, r);
+      st(B.qout, kb, so, tq[(c * NP + n) * kWave + lane] + Bc * r);
+    }
+  }
+}
+
+// Residual of field c, read before the WADG product so that its latency
+// overlaps the arithmetic; not read at all when A = 0 (first stage).
+template <int NP, bool RHS>
+__device__ __forceinline__ void load_res(const StageParams& p, const Bufs& B, int c, unsigned kb,
+                                         double (&resv)[NP]) {
+  if constexpr (!RHS) {
+    if (p.rkA != 0.0) {
+#pragma unroll
+      for (int n = 0; n < NP; ++n) resv[n] = ld(B.res, kb, (c * NP + n) * kPlane);
+      return;
+    }
+  }
+#pragma unroll
+  for (int n = 0; n < NP; ++n) resv[n] = 0.0;
+}
+
+// Pressure equation: b_p = int u.grad(v) J - int 1/2(2{u}.n - tau_p [p]) v sJ.
+template <int N, int NQ, bool RHS>
+__device__ __forceinline__ void pressure_wave(const StageParams& p, const Bufs& B,
+                                              const double* tq, unsigned kb, int lane,
+                                              bool active) {
+  constexpr ct::Tables<N, NQ> T = ct::make_tables<N, NQ>();
+  constexpr int NP1 = N + 1, NP = NP1 * NP1, NQ2 = NQ * NQ;
+  auto U = [&](int n) { return tq[(NP + n) * kWave + lane]; };
+  auto V = [&](int n) { return tq[(2 * NP + n) * kWave + lane]; };
+  auto P = [&](int n) { return tq[n * kWave + lane]; };
+
+  double bp[NP];
+#pragma unroll
+  for (int n = 0; n < NP; ++n) bp[n] = 0.0;
+
+  // a2: sum_q w_q J (l_r (Jr_x u + Jr_y v) + l_s (Js_x u + Js_y v))
+  double gc[4][NQ], gn[4][NQ];
+#pragma unroll
+  for (int g = 0; g < 4; ++g)
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) gc[g][j] = ld(B.vol, kb, (g * NQ2 + NQ * j) * kPlane);
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    if (i + 1 < NQ) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) gn[g][j] = ld(B.vol, kb, (g * NQ2 + i + 1 + NQ * j) * kPlane);
+    }
+    order();
+    double tu[NP1], tv[NP1];
+#pragma unroll
+    for (int bb = 0; bb < NP1; ++bb) {
+      double su = 0.0, sv = 0.0;
+#pragma unroll
+      for (int a = 0; a < NP1; ++a) {
+        su += T.V[i][a] * U(a + NP1 * bb);
+        sv += T.V[i][a] * V(a + NP1 * bb);
+      }
+      tu[bb] = su;
+      tv[bb] = sv;
+    }
+    double cr[NP1], cs[NP1];
+#pragma unroll
+    for (int bb = 0; bb < NP1; ++bb) cr[bb] = cs[bb] = 0.0;
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) {
+      double uq = 0.0, vq = 0.0;
+#pragma unroll
+      for (int bb = 0; bb < NP1; ++bb) {
+        uq += T.V[j][bb] * tu[bb];
+        vq += T.V[j][bb] * tv[bb];
+      }
+      const double Ur = gc[0][j] * uq + gc[1][j] * vq;
+      const double Us = gc[2][j] * uq + gc[3][j] * vq;
+#pragma unroll
+      for (int bb = 0; bb < NP1; ++bb) {
+        cr[bb] += T.V[j][bb] * Ur;
+        cs[bb] += T.D[j][bb] * Us;
+      }
+    }
+#pragma unroll
+    for (int bb = 0; bb < NP1; ++bb)
+#pragma unroll
+      for (int a = 0; a < NP1; ++a) bp[a + NP1 * bb] += T.D[i][a] * cr[bb] + T.V[i][a] * cs[bb];
+    pin(bp);
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int j = 0; j < NQ; ++j) gc[g][j] = gn[g][j];
+  }
+
+  // a1 + a3
+  const double tau_p = p.tau_p;
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    order();
+    // byte offset (in the slice) of the neighbour's value at my face node 0,
+    // and the byte step along my face parameter
+    const unsigned nb0 = (unsigned)ldi(B.nbr, kb >> 1, (0 * 4 + f) * (kPlane >> 1));
+    const int nstep = ldi(B.nbr, kb >> 1, (1 * 4 + f) * (kPlane >> 1));
+    double pn[NP1], un[NP1], vn[NP1], fg[3][NQ];
+#pragma unroll
+    for (int m = 0; m < NP1; ++m) {
+      const unsigned off = nb0 + (unsigned)(nstep * m);
+      pn[m] = ld(B.qslice, off, 0);
+      un[m] = ld(B.qslice, off, NP * kPlane);
+      vn[m] = ld(B.qslice, off, 2 * NP * kPlane);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int j = 0; j < NQ; ++j) fg[c][j] = ld(B.face, kb, (c * 4 * NQ + f * NQ + j) * kPlane);
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) {
+      double pm = 0.0, um = 0.0, vm = 0.0, pp = 0.0, up = 0.0, vp = 0.0;
+#pragma unroll
+      for (int m = 0; m < NP1; ++m) {
+        pm += T.V[j][m] * P(fnode<N>(f, m));
+        um += T.V[j][m] * U(fnode<N>(f, m));
+        vm += T.V[j][m] * V(fnode<N>(f, m));
+        pp += T.V[j][m] * pn[m];
+        up += T.V[j][m] * un[m];
+        vp += T.V[j][m] * vn[m];
+      }
+      const double nx = fg[0][j], ny = fg[1][j], wsJ = fg[2][j];
+      const double fp = 0.5 * wsJ * ((up + um) * nx + (vp + vm) * ny - tau_p * (pp - pm));
+#pragma unroll
+      for (int m = 0; m < NP1; ++m) bp[fnode<N>(f, m)] -= T.V[j][m] * fp;
+    }
+    pin(bp);
+  }
+
+  // a4 + a5
+  order();
+  double resv[NP], dq[NP];
+  load_res<NP, RHS>(p, B, 0, kb, resv);
+  wadg_inverse<N, NQ>(bp, B, 4 * NQ2, kb, dq);
+  finish_field<NP, RHS>(p, B, tq, 0, kb, lane, active, resv, dq);
+}
+
+// Velocity equations: b_u = -int grad(p) . tau J - int 1/2([p] - tau_u [u].n) tau.n sJ.
+template <int N, int NQ, bool RHS>
+__device__ __forceinline__ void velocity_wave(const StageParams& p, const Bufs& B,
+                                              const double* tq, unsigned kb, int lane,
+                                              bool active) {
+  constexpr ct::Tables<N, NQ> T = ct::make_tables<N, NQ>();
+  constexpr int NP1 = N + 1, NP = NP1 * NP1, NQ2 = NQ * NQ;
+  auto U = [&](int n) { return tq[(NP + n) * kWave + lane]; };
+  auto V = [&](int n) { return tq[(2 * NP + n) * kWave + lane]; };
+  auto P = [&](int n) { return tq[n * kWave + lane]; };
+
+  double bu[NP], bv[NP];
+#pragma unroll
+  for (int n = 0; n < NP; ++n) bu[n] = bv[n] = 0.0;
+
+  // a2: -sum_q w_q J l (p_x, p_y)
+  double gc[4][NQ], gn[4][NQ];
+#pragma unroll
+  for (int g = 0; g < 4; ++g)
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) gc[g][j] = ld(B.vol, kb, (g * NQ2 + NQ * j) * kPlane);
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    if (i + 1 < NQ) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) gn[g][j] = ld(B.vol, kb, (g * NQ2 + i + 1 + NQ * j) * kPlane);
+    }
+    order();
+    double td[NP1], tp[NP1];
+#pragma unroll
+    for (int bb = 0; bb < NP1; ++bb) {
+      double sd = 0.0, sp = 0.0;
+#pragma unroll
+      for (int a = 0; a < NP1; ++a) {
+        const double pa = P(a + NP1 * bb);
+        sd += T.D[i][a] * pa;
+        sp += T.V[i][a] * pa;
+      }
+      td[bb] = sd;
+      tp[bb] = sp;
+    }
+    double cx[NP1], cy[NP1];
+#pragma unroll
+    for (int bb = 0; bb < NP1; ++bb) cx[bb] = cy[bb] = 0.0;
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) {
+      double pr = 0.0, ps = 0.0;
+#pragma unroll
+      for (int bb = 0; bb < NP1; ++bb) {
+        pr += T.V[j][bb] * td[bb];
+        ps += T.D[j][bb] * tp[bb];
+      }
+      const double Gx = gc[0][j] * pr + gc[2][j] * ps;
+      const double Gy = gc[1][j] * pr + gc[3][j] * ps;
+#pragma unroll
+      for (int bb = 0; bb < NP1; ++bb) {
+        cx[bb] += T.V[j][bb] * Gx;
+        cy[bb] += T.V[j][bb] * Gy;
+      }
+    }
+#pragma unroll
+    for (int bb = 0; bb < NP1; ++bb)
+#pragma unroll
+      for (int a = 0; a < NP1; ++a) {
+        bu[a + NP1 * bb] -= T.V[i][a] * cx[bb];
+        bv[a + NP1 * bb] -= T.V[i][a] * cy[bb];
+      }
+    pin(bu);
+    pin(bv);
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int j = 0; j < NQ; ++j) gc[g][j] = gn[g][j];
+  }
+
+  // a1 + a3
+  const double tau_u = p.tau_u;
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    order();
+    const unsigned nb0 = (unsigned)ldi(B.nbr, kb >> 1, (0 * 4 + f) * (kPlane >> 1));
+    const int nstep = ldi(B.nbr, kb >> 1, (1 * 4 + f) * (kPlane >> 1));
+    double pn[NP1], un[NP1], vn[NP1], fg[3][NQ];
+#pragma unroll
+    for (int m = 0; m < NP1; ++m) {
+      const unsigned off = nb0 + (unsigned)(nstep * m);
+      pn[m] = ld(B.qslice, off, 0);
+      un[m] = ld(B.qslice, off, NP * kPlane);
+      vn[m] = ld(B.qslice, off, 2 * NP * kPlane);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int j = 0; j < NQ; ++j) fg[c][j] = ld(B.face, kb, (c * 4 * NQ + f * NQ + j) * kPlane);
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) {
+      double pm = 0.0, um = 0.0, vm = 0.0, pp = 0.0, up = 0.0, vp = 0.0;
+#pragma unroll
+      for (int m = 0; m < NP1; ++m) {
+        pm += T.V[j][m] * P(fnode<N>(f, m));
+        um += T.V[j][m] * U(fnode<N>(f, m));
+        vm += T.V[j][m] * V(fnode<N>(f, m));
+        pp += T.V[j][m] * pn[m];
+        up += T.V[j][m] * un[m];
+        vp += T.V[j][m] * vn[m];
+      }
+      const double nx = fg[0][j], ny = fg[1][j], wsJ = fg[2][j];
+      const double fu = 0.5 * wsJ * ((pp - pm) - tau_u * ((up - um) * nx + (vp - vm) * ny));
+      const double fx = fu * nx, fy = fu * ny;
+#pragma unroll
+      for (int m = 0; m < NP1; ++m) {
+        bu[fnode<N>(f, m)] -= T.V[j][m] * fx;
+        bv[fnode<N>(f, m)] -= T.V[j][m] * fy;
+      }
+    }
+    pin(bu);
+    pin(bv);
+  }
+
+  // a4 + a5, one field at a time
+  order();
+  double resv[NP], dq[NP];
+  load_res<NP, RHS>(p, B, 1, kb, resv);
+  wadg_inverse<N, NQ>(bu, B, 5 * NQ2, kb, dq);
+  finish_field<NP, RHS>(p, B, tq, 1, kb, lane, active, resv, dq);
+  order();
+  load_res<NP, RHS>(p, B, 2, kb, resv);
+  wadg_inverse<N, NQ>(bv, B, 5 * NQ2, kb, dq);
+  finish_field<NP, RHS>(p, B, tq, 2, kb, lane, active, resv, dq);
+}
+
+}  // namespace
+
+template <int N, int NQ, bool RHS>
+__global__ __launch_bounds__(2 * kWave) void stage_kernel(const StageParams p) {
+  constexpr int NP = (N + 1) * (N + 1);
+  constexpr int NQ2 = NQ * NQ;
+  constexpr unsigned tile = 3u * NP * kWave;   // doubles per group tile
+  __shared__ double tq[tile];
+
+  // workgroup -> work item (XCD-aware), work item -> (slice, element group)
+  const int nb = gridDim.x, bid = blockIdx.x;
+  const int q8 = nb >> 3, r8 = nb & 7;
+  const int xcd = bid & 7, jx = bid >> 3;
+  const int w = xcd * q8 + (xcd < r8 ? xcd : r8) + jx;
+  const int G = p.group;
+  const int per_group = p.nEG * G;
+  const int nfull = p.S / G;
+  int eg, s;
+  if (w < nfull * per_group) {
+    const int sg = w / per_group;
+    const int r = w - sg * per_group;
+    eg = r / G;
+    s = sg * G + (r - eg * G);
+  } else {
+    const int rem = p.S - nfull * G;
+    const int r = w - nfull * per_group;
+    eg = r / rem;
+    s = nfull * G + (r - eg * rem);
+  }
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & (kWave - 1);
+
+  const size_t slice = (size_t)s * p.nEG * tile;
+  const size_t grp = slice + (size_t)eg * tile;
+  Bufs B;
+  B.qin = make_rsrc(p.Qin + grp, tile * 8u);
+  B.qout = make_rsrc(p.Qout + grp, tile * 8u);
+  B.res = make_rsrc(RHS ? p.Qout + grp : p.res + grp, tile * 8u);
+  B.qslice = make_rsrc(p.Qin + slice, (unsigned)p.nEG * tile * 8u);
+  B.vol = make_rsrc(p.vol + (size_t)eg * 6 * NQ2 * kWave, 6u * NQ2 * kPlane);
+  B.face = make_rsrc(p.face + (size_t)eg * 12 * NQ * kWave, 12u * NQ * kPlane);
+  B.nbr = make_rsrc(p.nbr + (size_t)eg * 8 * kWave, 8u * kWave * 4u);
+
+  // stage the input tile in LDS: 16-byte chunks, consecutive threads on
+  // consecutive chunks
+  for (unsigned c = tid; c < tile / 2; c += 2 * kWave) {
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(B.qin, c * 16u, 0, 0);
+    *reinterpret_cast<u32x4*>(&tq[2 * c]) = v;
+  }
+  __syncthreads();
+
+  const bool active = eg * kWave + lane < p.K;
+  const unsigned kb = (unsigned)lane * 8u;
+  if (wave == 0)
+    pressure_wave<N, NQ, RHS>(p, B, tq, kb, lane, active);
+  else
+    velocity_wave<N, NQ, RHS>(p, B, tq, kb, lane, active);
+}
+
+namespace {
+
+template <int N, int NQ>
+int launch_nq(bool rhs, const StageParams& p, void* stream) {
+  const int nwg = p.nEG * p.S;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (rhs)
+    hipLaunchKernelGGL((stage_kernel<N, NQ, true>), dim3(nwg), dim3(2 * kWave), 0, st, p);
+  else
+    hipLaunchKernelGGL((stage_kernel<N, NQ, false>), dim3(nwg), dim3(2 * kWave), 0, st, p);
+  return (int)hipGetLastError();
+}
+
+template <int N>
+int launch_n(int nq, bool rhs, const StageParams& p, void* stream) {
+  switch (nq - N) {
+    case 1: return launch_nq<N, N + 1>(rhs, p, stream);
+    case 2: return launch_nq<N, N + 2>(rhs, p, stream);
+    case 3: return launch_nq<N, N + 3>(rhs, p, stream);
+    default: return (int)hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+bool stage_supported(int N, int nq) { return N >= 1 && N <= 4 && nq >= N + 1 && nq <= N + 3; }
+
+int launch_stage(int N, int nq, bool rhs, const StageParams& p, void* stream) {
+  switch (N) {
+    case 1: return launch_n<1>(nq, rhs, p, stream);
+    case 2: return launch_n<2>(nq, rhs, p, stream);
+    case 3: return launch_n<3>(nq, rhs, p, stream);
+    case 4: return launch_n<4>(nq, rhs, p, stream);
+    default: return (int)hipErrorInvalidValue;
+  }
+}
+
+}  // namespace wadg

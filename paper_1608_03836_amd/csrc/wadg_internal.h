@@ -1,0 +1,90 @@
+// Internal declarations shared by the host setup, the kernels and the C ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace wadg {
+
+constexpr int kMaxNp1 = 5;   // N <= 4
+constexpr int kMaxNq = 7;    // nq1 <= N + 3
+constexpr int kWave = 64;    // elements per workgroup: one element per lane
+
+// 1D reference operators of the tensor-product nodal basis.  All 2D
+// operators are tensor products of these (the reference square is a tensor
+// product and the GLL nodal basis is l_a(r) l_b(s)).
+//   V[i][a]  = l_a(x_i)                 Lagrange basis at Gauss points
+//   D[i][a]  = l_a'(x_i)
+//   Vt[i][a] = (V M1^{-1})[i][a]        interpolation of Mhat^{-1} b
+//   P[a][i]  = (M1^{-1} V^T W)[a][i]    quadrature-based L2 projection
+// with M1 the 1D nodal mass matrix.  Section 5.2 defines V_q and
+// P_q = Mhat^{-1} V_q^T diag(w_q); Mhat = M1 (x) M1 and V_q = V (x) V.
+struct RefOps {
+  int N = 0, nq = 0;
+  double xg[kMaxNp1] = {};
+  double xq[kMaxNq] = {}, wq[kMaxNq] = {};
+  double V[kMaxNq][kMaxNp1] = {};
+  double D[kMaxNq][kMaxNp1] = {};
+  double Vt[kMaxNq][kMaxNp1] = {};
+  double P[kMaxNp1][kMaxNq] = {};
+};
+
+// Build the 1D operators for degree N and an nq-point Gauss rule.
+bool build_ref_ops(int N, int nq, RefOps* ops, std::string* err);
+
+struct MeshIn {
+  int N, nq1, K;
+  const double *x, *y;
+  const int32_t *etoe, *etof;
+  const double* c2q;
+};
+
+// Host geometry arrays, untiled (element index fastest):
+//   vol  [6][nq*nq][K]   W ys, -W xs, -W yr, W xr, c2/J, 1/J
+//   face [3][4][nq][K]   nx, ny, w sJ
+//   nbr  [2][4][K]       byte offset, within one slice of the tiled state
+//                        layout, of the neighbour's value at my face node 0
+//                        (field 0), and the byte step along my face parameter
+int build_geometry(const MeshIn& m, const RefOps& ops, std::vector<double>* vol,
+                   std::vector<double>* face, std::vector<int32_t>* nbr, std::string* err);
+
+// Re-layout an untiled [P][K] array into the tiled [G][P][64] device layout
+// (padding zero-filled).
+template <typename T>
+std::vector<T> tile_planes(const std::vector<T>& a, int planes, int K) {
+  const int G = (K + kWave - 1) / kWave;
+  std::vector<T> t((size_t)G * planes * kWave, T(0));
+  for (int p = 0; p < planes; ++p)
+    for (int k = 0; k < K; ++k)
+      t[((size_t)(k / kWave) * planes + p) * kWave + (k % kWave)] = a[(size_t)p * K + k];
+  return t;
+}
+
+// Physical coordinates of the volume quadrature points, [K][nq*nq].
+void quadrature_points(const MeshIn& m, const RefOps& ops, double* xq, double* yq);
+
+struct StageParams {
+  const double* Qin;     // [S][G][3][Np][64]
+  double* Qout;          // [S][G][3][Np][64]  (rhs mode: dQ/dt)
+  double* res;           // [S][G][3][Np][64]  LSRK residual (stage mode)
+  const double* vol;     // [G][6][Nq][64]
+  const double* face;    // [G][3][4][nq][64]
+  const int32_t* nbr;    // [G][2][4][64]
+  int32_t K, S, group, nEG;
+  double tau_p, tau_u;
+  double rkA, rkB, dt;
+};
+
+// Launch one stage (rhs == false: LSRK stage update; rhs == true: write
+// dQ/dt to Qout).  Returns a hipError_t as int.
+int launch_stage(int N, int nq, bool rhs, const StageParams& p, void* stream);
+bool stage_supported(int N, int nq);
+
+// Per-slice norms over the tiled layout (padding skipped): partial sums into
+// `partials` [S][nblk][4] then a fixed-order reduction into `out` [S][4].
+int launch_norms(const double* A, const double* B, int32_t S, int64_t n_per_slice, int32_t tile,
+                 int32_t K, double* partials, int nblk, double* out, void* stream);
+
+}  // namespace wadg

@@ -1,0 +1,87 @@
+"""Convenience layer over the C ABI: device memory and streams from torch,
+layout conversion on the host.  All arithmetic of the sweep runs in the HIP
+library."""
+
+import numpy as np
+
+from . import binding as B
+
+
+class Solver:
+    """One WADG context on one HIP device.
+
+    ``mesh`` is any object with ``N, x, y, etoe, etof`` (GLL node coordinates
+    [K][(N+1)^2], connectivity [K][4]); ``c2`` an optional callable
+    ``c2(x, y)`` evaluated at the volume quadrature points.
+    """
+
+    def __init__(self, mesh, nq1=None, c2=None, tau_p=1.0, tau_u=1.0, device=0):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        N = int(mesh.N)
+        nq1 = N + 2 if nq1 is None else int(nq1)
+        desc = B.MeshDesc(N, nq1, mesh.x, mesh.y, mesh.etoe, mesh.etof, None, tau_p, tau_u)
+        if c2 is not None:
+            xq, yq = B.wadg_quadrature_points(desc)
+            desc = B.MeshDesc(N, nq1, mesh.x, mesh.y, mesh.etoe, mesh.etof,
+                              np.asarray(c2(xq, yq), dtype=np.float64), tau_p, tau_u)
+        self.desc = desc
+        self.N, self.nq1, self.K = N, nq1, desc.K
+        self.Np = (N + 1) ** 2
+        with torch.cuda.device(self.device):
+            self.ctx = B.wadg_create(desc, device)
+        self.slice_doubles = B.wadg_state_doubles(self.ctx)
+
+    @classmethod
+    def from_problem(cls, prob, device=0):
+        return cls(prob.mesh, nq1=prob.nq1, c2=prob.c2, tau_p=prob.tau_p, tau_u=prob.tau_u,
+                   device=device)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            B.wadg_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- memory ----------------------------------------------------------
+    def empty_state(self, S):
+        return self.torch.zeros(S * self.slice_doubles, dtype=self.torch.float64,
+                                device=self.device)
+
+    def workspace(self, S):
+        n = B.wadg_workspace_bytes(self.ctx, S) // 8
+        return self.torch.empty(n, dtype=self.torch.float64, device=self.device)
+
+    def upload(self, Qn):
+        """Natural [S][3][Np][K] host array -> tiled device tensor."""
+        t = B.tile_state(np.asarray(Qn).reshape(-1, 3, self.Np, self.K))
+        return self.torch.from_numpy(t.reshape(-1)).to(self.device)
+
+    def download(self, Q, S):
+        """Tiled device tensor -> natural [S][3][Np][K] host array."""
+        G = self.slice_doubles // (3 * self.Np * B.TILE_LANES)
+        h = Q.detach().cpu().numpy().reshape(S, G, 3, self.Np, B.TILE_LANES)
+        return B.untile_state(h, self.K)
+
+    # -- the sweep -------------------------------------------------------
+    def rhs(self, Q, S, out=None, stream=None):
+        out = self.empty_state(S) if out is None else out
+        B.wadg_rhs(self.ctx, Q, out, S, stream)
+        return out
+
+    def integrate(self, Q, S, dt, nsteps, work=None, stream=None):
+        work = self.workspace(S) if work is None else work
+        B.wadg_integrate(self.ctx, Q, work, S, dt, nsteps, stream)
+        return Q
+
+    def norms(self, A, Bt=None, S=1, stream=None, check_finite=True):
+        return B.wadg_norms(self.ctx, A, Bt, S, stream, check_finite=check_finite)
+
+    def set_slice_group(self, g):
+        B.wadg_set_slice_group(self.ctx, g)
