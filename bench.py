@@ -29,7 +29,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="wadg64")
-    ap.add_argument("--slice-group", type=int, default=None)
+    ap.add_argument("--tile-groups", type=int, default=None,
+                    help="schedule: element groups per tile (default: library default)")
+    ap.add_argument("--tile-slices", type=int, default=0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one device-to-device copy of this size before the timed "
+                         "region, as the known-size reference for HBM byte counters")
     ap.add_argument("--cpu-baseline-seconds", type=float, default=15.0,
                     help="approximate CPU seconds for the oracle baseline (0: skip)")
     return ap.parse_args()
@@ -87,8 +92,8 @@ def main():
 
     prob = make_problem(args.workload)
     sol = W.Solver.from_problem(prob)
-    if args.slice_group:
-        sol.set_slice_group(args.slice_group)
+    if args.tile_groups:
+        sol.set_schedule(args.tile_groups, args.tile_slices)
     S, K, N = prob.S, prob.K, prob.N
     Q = sol.upload(prob.Q0)
     work = sol.workspace(S)
@@ -98,6 +103,14 @@ def main():
         sol.integrate(Q, S, prob.dt, prob.nsteps, work=work, stream=stream)
         out = sol.norms(Q, None, S, stream=stream)
         return out
+
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=sol.device)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         step()

@@ -162,9 +162,13 @@ int wadg_integrate(wadg_ctx ctx, double* Q, double* work, int32_t S, double dt,
 int wadg_norms(wadg_ctx ctx, const double* A, const double* B, int32_t S, double* out,
                void* stream);
 
-/* Tuning: slices processed back to back on one element group (geometry
- * reuse in L2).  g >= 1; default 8. */
-int wadg_set_slice_group(wadg_ctx ctx, int32_t g);
+/* Tuning: the order in which (slice, 64-element group) work items are
+ * launched.  Items are grouped in tiles of groups_per_tile element groups x
+ * slices_per_tile slices (0: all slices), slice-major inside a tile; each
+ * XCD takes a contiguous range of tiles.  Results do not depend on it
+ * (bitwise).  Defaults: 8, 0.  Returns WADG_E_INVALID for
+ * groups_per_tile < 1 or slices_per_tile < 0. */
+int wadg_set_schedule(wadg_ctx ctx, int32_t groups_per_tile, int32_t slices_per_tile);
 
 /* Static description of a status code; never NULL. */
 const char* wadg_status_string(int status);

@@ -60,7 +60,7 @@ def _load():
         "wadg_integrate": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, ctypes.c_double,
                                           ctypes.c_int32, vp]),
         "wadg_norms": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, _c_double_p, vp]),
-        "wadg_set_slice_group": (ctypes.c_int, [vp, ctypes.c_int32]),
+        "wadg_set_schedule": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32]),
         "wadg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "wadg_last_error": (ctypes.c_char_p, []),
     }
@@ -74,7 +74,7 @@ def _load():
 LIB = _load()
 EXPORTED = ("wadg_quadrature_points", "wadg_geometry", "wadg_create", "wadg_destroy",
             "wadg_state_doubles", "wadg_workspace_bytes", "wadg_rhs", "wadg_integrate",
-            "wadg_norms", "wadg_set_slice_group", "wadg_status_string", "wadg_last_error")
+            "wadg_norms", "wadg_set_schedule", "wadg_status_string", "wadg_last_error")
 
 
 def _check(status):
@@ -196,8 +196,8 @@ def wadg_norms(ctx, A, B, S, stream=None, check_finite=True):
     return out
 
 
-def wadg_set_slice_group(ctx, g):
-    _check(LIB.wadg_set_slice_group(ctx, int(g)))
+def wadg_set_schedule(ctx, groups_per_tile, slices_per_tile=0):
+    _check(LIB.wadg_set_schedule(ctx, int(groups_per_tile), int(slices_per_tile)))
 
 
 def wadg_status_string(status):

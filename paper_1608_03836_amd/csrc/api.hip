@@ -83,7 +83,8 @@ struct wadg_ctx_s {
   int device = 0;
   int N = 0, nq1 = 0, K = 0;
   double tau_p = 1.0, tau_u = 1.0;
-  int group = 8;
+  int tile_groups = 8;   // schedule: element groups per tile
+  int tile_slices = 0;   // slices per tile (0: all)
   double* d_vol = nullptr;
   double* d_face = nullptr;
   int32_t* d_nbr = nullptr;
@@ -133,8 +134,9 @@ wadg::StageParams base_params(wadg_ctx c, int32_t S) {
   p.nbr = c->d_nbr;
   p.K = c->K;
   p.S = S;
-  p.group = c->group < S ? c->group : S;
   p.nEG = (c->K + wadg::kWave - 1) / wadg::kWave;
+  p.tile_groups = c->tile_groups < p.nEG ? c->tile_groups : p.nEG;
+  p.tile_slices = (c->tile_slices == 0 || c->tile_slices > S) ? S : c->tile_slices;
   p.tau_p = c->tau_p;
   p.tau_u = c->tau_u;
   return p;
@@ -238,10 +240,12 @@ int wadg_workspace_bytes(wadg_ctx ctx, int32_t S, size_t* bytes) {
   return WADG_OK;
 }
 
-int wadg_set_slice_group(wadg_ctx ctx, int32_t g) {
+int wadg_set_schedule(wadg_ctx ctx, int32_t groups_per_tile, int32_t slices_per_tile) {
   if (!ctx) return fail(WADG_E_INVALID, "context is NULL");
-  if (g < 1) return fail(WADG_E_INVALID, "slice group must be >= 1");
-  ctx->group = g;
+  if (groups_per_tile < 1 || slices_per_tile < 0)
+    return fail(WADG_E_INVALID, "groups_per_tile must be >= 1 and slices_per_tile >= 0");
+  ctx->tile_groups = groups_per_tile;
+  ctx->tile_slices = slices_per_tile;
   return WADG_OK;
 }
 

@@ -35,9 +35,11 @@
 //       gathers never see a partly updated state.
 //
 // Workgroup -> (slice, element group): workgroups are dealt to the 8 XCDs
-// round-robin; each XCD receives a contiguous range of the logical order
-// (slice group, element group, slice in group), so the slices of one group
-// share the element group's geometry in that XCD's L2.
+// round-robin; each XCD receives a contiguous range of a logical order made
+// of tiles of Be element groups x Bs slices, slice-major inside a tile.  With
+// all slices in one tile, an XCD keeps its element groups' geometry in its
+// L2 for every slice, and the neighbouring groups of one slice (whose face
+// values it gathers) are processed back to back.
 
 #include <hip/hip_runtime.h>
 
@@ -449,26 +451,23 @@ __global__ __launch_bounds__(2 * kWave) void stage_kernel(const StageParams p) {
   constexpr unsigned tile = 3u * NP * kWave;   // doubles per group tile
   __shared__ double tq[tile];
 
-  // workgroup -> work item (XCD-aware), work item -> (slice, element group)
+  // workgroup -> work item (XCD-aware): XCD x = bid % 8 receives the
+  // contiguous logical range [x q8 + min(x, r8), ...) in launch order
   const int nb = gridDim.x, bid = blockIdx.x;
   const int q8 = nb >> 3, r8 = nb & 7;
   const int xcd = bid & 7, jx = bid >> 3;
   const int w = xcd * q8 + (xcd < r8 ? xcd : r8) + jx;
-  const int G = p.group;
-  const int per_group = p.nEG * G;
-  const int nfull = p.S / G;
-  int eg, s;
-  if (w < nfull * per_group) {
-    const int sg = w / per_group;
-    const int r = w - sg * per_group;
-    eg = r / G;
-    s = sg * G + (r - eg * G);
-  } else {
-    const int rem = p.S - nfull * G;
-    const int r = w - nfull * per_group;
-    eg = r / rem;
-    s = nfull * G + (r - eg * rem);
-  }
+  // work item -> (slice, element group): tiles of Be element groups x Bs
+  // slices, ordered (slice block, element block), slice-major inside a tile
+  const int Be = p.tile_groups, Bs = p.tile_slices, nEG = p.nEG;
+  const int sb = w / (Bs * nEG);
+  const int r = w - sb * Bs * nEG;
+  const int bs = min(Bs, p.S - sb * Bs);
+  const int eb = r / (Be * bs);
+  const int r2 = r - eb * Be * bs;
+  const int be = min(Be, nEG - eb * Be);
+  const int s = sb * Bs + r2 / be;
+  const int eg = eb * Be + r2 % be;
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & (kWave - 1);

@@ -72,7 +72,8 @@ struct StageParams {
   const double* vol;     // [G][6][Nq][64]
   const double* face;    // [G][3][4][nq][64]
   const int32_t* nbr;    // [G][2][4][64]
-  int32_t K, S, group, nEG;
+  int32_t K, S, nEG;
+  int32_t tile_groups, tile_slices;   // schedule tile (clamped to nEG, S)
   double tau_p, tau_u;
   double rkA, rkB, dt;
 };

@@ -83,5 +83,5 @@ class Solver:
     def norms(self, A, Bt=None, S=1, stream=None, check_finite=True):
         return B.wadg_norms(self.ctx, A, Bt, S, stream, check_finite=check_finite)
 
-    def set_slice_group(self, g):
-        B.wadg_set_slice_group(self.ctx, g)
+    def set_schedule(self, groups_per_tile, slices_per_tile=0):
+        B.wadg_set_schedule(self.ctx, groups_per_tile, slices_per_tile)

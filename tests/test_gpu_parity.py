@@ -144,13 +144,13 @@ def test_edge_shapes(W):
     _assert_close(sol.download(Q, 1), o.integrate(Q0, 0.01, 2))
 
 
-def test_deterministic_and_slice_group_invariant(W):
+def test_deterministic_and_schedule_invariant(W):
     _print_case(test="determinism")
     prob = make_problem("wadg4")
     sol = W.Solver.from_problem(prob)
     outs = []
-    for g in (8, 8, 1, 3, 16):
-        sol.set_slice_group(g)
+    for g, sl in ((8, 0), (8, 0), (1, 1), (3, 5), (16, 2), (1, 0)):
+        sol.set_schedule(g, sl)
         Q = sol.upload(prob.Q0)
         sol.integrate(Q, prob.S, prob.dt, 4)
         outs.append(sol.download(Q, prob.S))
