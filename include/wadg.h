@@ -150,6 +150,19 @@ int wadg_rhs(wadg_ctx ctx, const double* Q, double* dQdt, int32_t S, void* strea
 int wadg_integrate(wadg_ctx ctx, double* Q, double* work, int32_t S, double dt,
                    int32_t nsteps, void* stream);
 
+/* FP32-bulk propagation: the same sweep as wadg_integrate with the slice
+ * interior in single precision.  Q (FP64, tiled layout) is rounded to an
+ * FP32 copy, advanced by nsteps LSRK(5,4) steps with FP32 state, residual,
+ * geometry and operators, and widened back into Q; start and end states and
+ * everything done on them (norms, corrections) stay FP64.  Its error against
+ * the FP64 sweep is that of FP32 rounding in the interior (about 1e-7
+ * relative per step, measured by the tests).
+ *   work  device workspace of wadg_workspace_bytes_fp32(S) bytes
+ *         (3 * S * wadg_state_doubles * 4), not aliasing Q. */
+int wadg_workspace_bytes_fp32(wadg_ctx ctx, int32_t S, size_t* bytes);
+int wadg_integrate_fp32(wadg_ctx ctx, double* Q, void* work, int32_t S, double dt,
+                        int32_t nsteps, void* stream);
+
 /* Per-slice reductions (the norms the convergence checks use):
  *   out[s][0] = ||A_s - B_s||_2,  out[s][1] = ||B_s||_2,
  *   out[s][2] = max |A_s - B_s|,  out[s][3] = 1 if every A_s entry is finite

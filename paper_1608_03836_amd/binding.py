@@ -6,7 +6,7 @@ as torch tensors (contiguous, float64, on a HIP device) or as raw integer
 device addresses; streams as ``torch.cuda.Stream`` objects, raw handles or
 ``None`` (the current torch stream).
 
-The library must have been built (``python -m paper_1608_03836_amd.build``);
+The library must have been built (``python paper_1608_03836_amd/build.py``);
 importing this module without it raises immediately -- there is no
 fallback implementation.
 """
@@ -46,7 +46,7 @@ class wadg_mesh(ctypes.Structure):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1608_03836_amd.build`")
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python paper_1608_03836_amd/build.py`")
     lib = ctypes.CDLL(LIB_PATH)
     vp, sz = ctypes.c_void_p, ctypes.c_size_t
     sig = {
@@ -59,6 +59,9 @@ def _load():
         "wadg_rhs": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, vp]),
         "wadg_integrate": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, ctypes.c_double,
                                           ctypes.c_int32, vp]),
+        "wadg_workspace_bytes_fp32": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.POINTER(sz)]),
+        "wadg_integrate_fp32": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, ctypes.c_double,
+                                               ctypes.c_int32, vp]),
         "wadg_norms": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, _c_double_p, vp]),
         "wadg_set_schedule": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32]),
         "wadg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -74,6 +77,7 @@ def _load():
 LIB = _load()
 EXPORTED = ("wadg_quadrature_points", "wadg_geometry", "wadg_create", "wadg_destroy",
             "wadg_state_doubles", "wadg_workspace_bytes", "wadg_rhs", "wadg_integrate",
+            "wadg_workspace_bytes_fp32", "wadg_integrate_fp32",
             "wadg_norms", "wadg_set_schedule", "wadg_status_string", "wadg_last_error")
 
 
@@ -184,6 +188,17 @@ def wadg_rhs(ctx, Q, dQdt, S, stream=None):
 def wadg_integrate(ctx, Q, work, S, dt, nsteps, stream=None):
     _check(LIB.wadg_integrate(ctx, _ptr(Q), _ptr(work), int(S), float(dt), int(nsteps),
                               _stream(stream)))
+
+
+def wadg_workspace_bytes_fp32(ctx, S):
+    n = ctypes.c_size_t()
+    _check(LIB.wadg_workspace_bytes_fp32(ctx, int(S), ctypes.byref(n)))
+    return n.value
+
+
+def wadg_integrate_fp32(ctx, Q, work, S, dt, nsteps, stream=None):
+    _check(LIB.wadg_integrate_fp32(ctx, _ptr(Q), _ptr(work), int(S), float(dt), int(nsteps),
+                                   _stream(stream)))
 
 
 def wadg_norms(ctx, A, B, S, stream=None, check_finite=True):

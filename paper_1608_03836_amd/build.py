@@ -1,6 +1,7 @@
 """Build the HIP library ``libwadg.so`` in-tree for gfx950.
 
-Usage: ``python -m paper_1608_03836_amd.build`` (or ``__graft_entry__.build()``).
+Usage: ``python paper_1608_03836_amd/build.py`` (or ``__graft_entry__.build()``); run as a
+script, since importing the package loads the library this builds.
 """
 
 import os
@@ -13,7 +14,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libwadg.so")
 
-SOURCES = ["reference.cpp", "stage_kernel.hip", "norms_kernel.hip", "api.hip"]
+SOURCES = ["reference.cpp", "stage_kernel.hip", "norms_kernel.hip", "convert_kernel.hip",
+           "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -87,6 +87,8 @@ struct wadg_ctx_s {
   int tile_slices = 0;   // slices per tile (0: all)
   double* d_vol = nullptr;
   double* d_face = nullptr;
+  float* d_vol32 = nullptr;      // geometry rounded to FP32 (FP32-bulk path)
+  float* d_face32 = nullptr;
   int32_t* d_nbr = nullptr;
   double* d_partials = nullptr;  // norms scratch, grown on demand
   double* d_out = nullptr;
@@ -103,6 +105,8 @@ void free_ctx(wadg_ctx c) {
   if (!c) return;
   if (c->d_vol) (void)hipFree(c->d_vol);
   if (c->d_face) (void)hipFree(c->d_face);
+  if (c->d_vol32) (void)hipFree(c->d_vol32);
+  if (c->d_face32) (void)hipFree(c->d_face32);
   if (c->d_nbr) (void)hipFree(c->d_nbr);
   if (c->d_partials) (void)hipFree(c->d_partials);
   if (c->d_out) (void)hipFree(c->d_out);
@@ -189,6 +193,7 @@ int wadg_create(const wadg_mesh* mesh, int32_t device, wadg_ctx* out) {
   std::vector<double> vol = wadg::tile_planes(vol0, 6 * nq * nq, mesh->K);
   std::vector<double> face = wadg::tile_planes(face0, 12 * nq, mesh->K);
   std::vector<int32_t> nbr = wadg::tile_planes(nbr0, 8, mesh->K);
+  std::vector<float> vol32(vol.begin(), vol.end()), face32(face.begin(), face.end());
 
   int dev = device;
   if (dev < 0) WADG_HIP(hipGetDevice(&dev));
@@ -211,6 +216,12 @@ int wadg_create(const wadg_mesh* mesh, int32_t device, wadg_ctx* out) {
       (e = hipMemcpy(c->d_face, face.data(), face.size() * sizeof(double),
                      hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(c->d_nbr, nbr.data(), nbr.size() * sizeof(int32_t),
+                     hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMalloc(&c->d_vol32, vol32.size() * sizeof(float))) != hipSuccess ||
+      (e = hipMalloc(&c->d_face32, face32.size() * sizeof(float))) != hipSuccess ||
+      (e = hipMemcpy(c->d_vol32, vol32.data(), vol32.size() * sizeof(float),
+                     hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(c->d_face32, face32.data(), face32.size() * sizeof(float),
                      hipMemcpyHostToDevice)) != hipSuccess) {
     free_ctx(c);
     return hip_fail(e, "wadg_create device setup");
@@ -293,11 +304,58 @@ int wadg_integrate(wadg_ctx ctx, double* Q, double* work, int32_t S, double dt, 
       p.rkB = kRkB[i];
       int e = wadg::launch_stage(ctx->N, ctx->nq1, false, p, stream);
       if (e) return hip_fail((hipError_t)e, "stage kernel launch");
-      cur = p.Qout;
+      cur = static_cast<double*>(p.Qout);
     }
   if (cur != Q)
     WADG_HIP(hipMemcpyAsync(Q, cur, n * sizeof(double), hipMemcpyDeviceToDevice,
                             static_cast<hipStream_t>(stream)));
+  return WADG_OK;
+}
+
+int wadg_workspace_bytes_fp32(wadg_ctx ctx, int32_t S, size_t* bytes) {
+  int st = check_slices(ctx, S);
+  if (st) return st;
+  if (!bytes) return fail(WADG_E_INVALID, "bytes is NULL");
+  *bytes = 3 * ctx->state_doubles(S) * sizeof(float);
+  return WADG_OK;
+}
+
+int wadg_integrate_fp32(wadg_ctx ctx, double* Q, void* work, int32_t S, double dt,
+                        int32_t nsteps, void* stream) {
+  int st = check_slices(ctx, S);
+  if (st) return st;
+  if (!Q || !work) return fail(WADG_E_INVALID, "Q and work must not be NULL");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(WADG_E_INVALID, "dt must be finite and > 0");
+  if (nsteps < 0) return fail(WADG_E_INVALID, "nsteps must be >= 0");
+  const size_t n = ctx->state_doubles(S);
+  if (overlaps(Q, n * sizeof(double), work, 3 * n * sizeof(float)))
+    return fail(WADG_E_INVALID, "work must not alias Q");
+  if (nsteps == 0) return WADG_OK;
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select the context's device");
+  float* q0 = static_cast<float*>(work);
+  float* q1 = q0 + n;
+  float* res = q1 + n;
+  int e = wadg::launch_to_fp32(Q, q0, n, stream);
+  if (e) return hip_fail((hipError_t)e, "conversion kernel launch");
+  wadg::StageParams p = base_params(ctx, S);
+  p.vol = ctx->d_vol32;
+  p.face = ctx->d_face32;
+  p.res = res;
+  p.dt = dt;
+  float* cur = q0;
+  for (int stp = 0; stp < nsteps; ++stp)
+    for (int i = 0; i < 5; ++i) {
+      p.Qin = cur;
+      p.Qout = (cur == q0) ? q1 : q0;
+      p.rkA = kRkA[i];
+      p.rkB = kRkB[i];
+      e = wadg::launch_stage_fp32(ctx->N, ctx->nq1, p, stream);
+      if (e) return hip_fail((hipError_t)e, "stage kernel launch");
+      cur = static_cast<float*>(p.Qout);
+    }
+  e = wadg::launch_to_fp64(cur, Q, n, stream);
+  if (e) return hip_fail((hipError_t)e, "conversion kernel launch");
   return WADG_OK;
 }
 

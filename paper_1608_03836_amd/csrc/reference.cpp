@@ -209,15 +209,15 @@ int build_geometry(const MeshIn& m, const RefOps& o, std::vector<double>* vol,
       }
       if (nbr) {
         // tiled state: element kn is lane kn % 64 of group kn / 64; a group
-        // holds 3 * Np node planes of 64 doubles
+        // holds 3 * Np node planes of 64 values
         const long long Np = (long long)Np1 * Np1;
         const int n0 = base[fn] + (flip ? stride[fn] * N : 0);
         const int dn = flip ? -stride[fn] : stride[fn];
         const long long off =
-            ((long long)(kn / kWave) * 3 * Np * kWave + (long long)n0 * kWave + kn % kWave) * 8;
+            (long long)(kn / kWave) * 3 * Np * kWave + (long long)n0 * kWave + kn % kWave;
         int32_t* B = nbr->data();
         B[(0 * 4 + f) * KK + k] = (int32_t)off;
-        B[(1 * 4 + f) * KK + k] = dn * kWave * 8;
+        B[(1 * 4 + f) * KK + k] = dn * kWave;
       }
     }
   return 0;

@@ -173,5 +173,25 @@ struct Ref {
   static constexpr Tables<N, NQ> t = make_tables<N, NQ>();
 };
 
+// The operators the kernels use, rounded once to the arithmetic type R.
+template <typename R, int N, int NQ>
+struct Ops {
+  R V[NQ][N + 1], D[NQ][N + 1], Vt[NQ][N + 1], P[N + 1][NQ];
+};
+
+template <typename R, int N, int NQ>
+constexpr Ops<R, N, NQ> make_ops() {
+  const Tables<N, NQ> t = make_tables<N, NQ>();
+  Ops<R, N, NQ> o{};
+  for (int i = 0; i < NQ; ++i)
+    for (int a = 0; a <= N; ++a) {
+      o.V[i][a] = static_cast<R>(t.V[i][a]);
+      o.D[i][a] = static_cast<R>(t.D[i][a]);
+      o.Vt[i][a] = static_cast<R>(t.Vt[i][a]);
+      o.P[a][i] = static_cast<R>(t.P[a][i]);
+    }
+  return o;
+}
+
 }  // namespace ct
 }  // namespace wadg

@@ -1,23 +1,24 @@
 // Fused WADG stage kernel for gfx950.
 //
 // One LSRK stage of the WADG acoustic sweep for S slices at once, or one
-// right-hand-side evaluation.  A workgroup owns one 64-element group of one
+// right-hand-side evaluation, in arithmetic type R (double; float for the
+// FP32-bulk propagator).  A workgroup owns one 64-element group of one
 // slice and has two waves: lane l of wave 0 computes the pressure equation
 // of element l, lane l of wave 1 the two velocity equations of the same
 // element.  State and geometry are tiled by element group with the lane
 // index fastest, so every per-node access of a wave is one contiguous
-// 512-byte access at a compile-time offset inside the group's tile, and
+// 64-lane access at a compile-time offset inside the group's tile, and
 // every reference-operator entry is wave-uniform: the 1D tables are
 // compile-time constants folded into the instruction stream.
 //
-// The group's input tile (3 (N+1)^2 x 64 doubles) is first copied into LDS
+// The group's input tile (3 (N+1)^2 x 64 values) is first copied into LDS
 // by both waves with 16-byte coalesced loads, so every first-touch HBM read
 // of the stage is in flight at once; the waves then re-read their own nodal
 // values from LDS (lane-contiguous, conflict-free) instead of keeping them
 // in registers.  Per lane:
 //
 //   a1  own face nodes (LDS) and the neighbours' face nodes (gathered from
-//       the input slice through precomputed byte offsets, flip-aware),
+//       the input slice through precomputed offsets, flip-aware),
 //       interpolated to the face Gauss points;
 //   a2  volume term of the strong-weak form (Section 4.1; Section 5.4,
 //       volume kernel): u, v (pressure wave) or grad p (velocity wave) at the
@@ -58,17 +59,28 @@ using rsrc_t = __amdgpu_buffer_rsrc_t;
 typedef unsigned int u32x2 __attribute__((vector_size(8)));
 typedef unsigned int u32x4 __attribute__((vector_size(16)));
 constexpr int kRsrcWord3 = 0x00020000;   // raw dword buffer, gfx9 family
-constexpr unsigned kPlane = kWave * 8;   // bytes of one 64-lane plane
 
 __device__ __forceinline__ rsrc_t make_rsrc(const void* base, unsigned bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
                                            kRsrcWord3);
 }
-__device__ __forceinline__ double ld(rsrc_t r, unsigned voff, unsigned soff) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+__device__ __forceinline__ void ld(rsrc_t r, unsigned voff, unsigned soff, double& v) {
+  v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ void ld(rsrc_t r, unsigned voff, unsigned soff, float& v) {
+  v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <typename R>
+__device__ __forceinline__ R ldr(rsrc_t r, unsigned voff, unsigned soff) {
+  R v;
+  ld(r, voff, soff, v);
+  return v;
 }
 __device__ __forceinline__ void st(rsrc_t r, unsigned voff, unsigned soff, double v) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void st(rsrc_t r, unsigned voff, unsigned soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
 }
 __device__ __forceinline__ int ldi(rsrc_t r, unsigned voff, unsigned soff) {
   return (int)__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
@@ -81,8 +93,8 @@ __device__ __forceinline__ int ldi(rsrc_t r, unsigned voff, unsigned soff) {
 // arithmetic of a quadrature column or face is not sunk towards the final
 // stores (which would keep every loaded operand live to the end).
 __device__ __forceinline__ void order() { asm volatile("" ::: "memory"); }
-template <int M>
-__device__ __forceinline__ void pin(double (&a)[M]) {
+template <typename R, int M>
+__device__ __forceinline__ void pin(R (&a)[M]) {
 #pragma unroll
   for (int i = 0; i < M; ++i) asm volatile("" : "+v"(a[i]));
 }
@@ -99,40 +111,47 @@ struct Bufs {
   rsrc_t qin, qout, res, qslice, vol, face, nbr;
 };
 
+// Stage-wide constants of one launch.
+template <typename R>
+struct StageScalars {
+  R tau_p, tau_u, A, B, dt;
+};
+
 // dq = P_q diag(w) (V_q Mhat^{-1}) b in tensor form; w at the volume points
 // (planes wplane .. wplane + NQ^2 of the geometry tile).
-template <int N, int NQ>
-__device__ __forceinline__ void wadg_inverse(const double (&b)[(N + 1) * (N + 1)], const Bufs& B,
+template <typename R, int N, int NQ>
+__device__ __forceinline__ void wadg_inverse(const R (&b)[(N + 1) * (N + 1)], const Bufs& B,
                                              unsigned wplane, unsigned kb,
-                                             double (&dq)[(N + 1) * (N + 1)]) {
-  constexpr ct::Tables<N, NQ> T = ct::make_tables<N, NQ>();
+                                             R (&dq)[(N + 1) * (N + 1)]) {
+  constexpr ct::Ops<R, N, NQ> T = ct::make_ops<R, N, NQ>();
   constexpr int NP1 = N + 1;
+  constexpr unsigned KP = kWave * sizeof(R);
 #pragma unroll
-  for (int n = 0; n < NP1 * NP1; ++n) dq[n] = 0.0;
-  double wc[NQ], wn[NQ];
+  for (int n = 0; n < NP1 * NP1; ++n) dq[n] = R(0);
+  R wc[NQ], wn[NQ];
 #pragma unroll
-  for (int j = 0; j < NQ; ++j) wc[j] = ld(B.vol, kb, (wplane + NQ * j) * kPlane);
+  for (int j = 0; j < NQ; ++j) wc[j] = ldr<R>(B.vol, kb, (wplane + NQ * j) * KP);
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
     if (i + 1 < NQ) {
 #pragma unroll
-      for (int j = 0; j < NQ; ++j) wn[j] = ld(B.vol, kb, (wplane + i + 1 + NQ * j) * kPlane);
+      for (int j = 0; j < NQ; ++j) wn[j] = ldr<R>(B.vol, kb, (wplane + i + 1 + NQ * j) * KP);
     }
     order();
-    double t[NP1];
+    R t[NP1];
 #pragma unroll
     for (int bb = 0; bb < NP1; ++bb) {
-      double acc = 0.0;
+      R acc = R(0);
 #pragma unroll
       for (int a = 0; a < NP1; ++a) acc += T.Vt[i][a] * b[a + NP1 * bb];
       t[bb] = acc;
     }
-    double c[NP1];
+    R c[NP1];
 #pragma unroll
-    for (int bb = 0; bb < NP1; ++bb) c[bb] = 0.0;
+    for (int bb = 0; bb < NP1; ++bb) c[bb] = R(0);
 #pragma unroll
     for (int j = 0; j < NQ; ++j) {
-      double rq = 0.0;
+      R rq = R(0);
 #pragma unroll
       for (int bb = 0; bb < NP1; ++bb) rq += T.Vt[j][bb] * t[bb];
       rq *= wc[j];
@@ -151,77 +170,102 @@ __device__ __forceinline__ void wadg_inverse(const double (&b)[(N + 1) * (N + 1)
 
 // a5 for field c: res <- A res + dt dq; Qout <- Qin + B res  (or dQ/dt).
 // `resv` holds the residual prefetched before the WADG product.
-template <int NP, bool RHS>
-__device__ __forceinline__ void finish_field(const StageParams& p, const Bufs& B,
-                                             const double* tq, int c, unsigned kb, int lane,
-                                             bool active, const double (&resv)[NP],
-                                             const double (&dq)[NP]) {
+template <typename R, int NP, bool RHS>
+__device__ __forceinline__ void finish_field(const StageScalars<R>& k, const Bufs& B,
+                                             const R* tq, int c, unsigned kb, int lane,
+                                             bool active, const R (&resv)[NP],
+                                             const R (&dq)[NP]) {
+  constexpr unsigned KP = kWave * sizeof(R);
   if (!active) return;
   if constexpr (RHS) {
 #pragma unroll
-    for (int n = 0; n < NP; ++n) st(B.qout, kb, (c * NP + n) * kPlane, dq[n]);
+    for (int n = 0; n < NP; ++n) st(B.qout, kb, (c * NP + n) * KP, dq[n]);
   } else {
-    const double A = p.rkA, Bc = p.rkB, dt = p.dt;
 #pragma unroll
     for (int n = 0; n < NP; ++n) {
-      const unsigned so = (c * NP + n) * kPlane;
-      const double r = A * resv[n] + dt * dq[n];
+      const unsigned so = (c * NP + n) * KP;
+      const R r = k.A * resv[n] + k.dt * dq[n];
       st(B.res, kb, so, r);
-      st(B.qout, kb, so, tq[(c * NP + n) * kWave + lane] + Bc * r);
+      st(B.qout, kb, so, tq[(c * NP + n) * kWave + lane] + k.B * r);
     }
   }
 }
 
 // Residual of field c, read before the WADG product so that its latency
 // overlaps the arithmetic; not read at all when A = 0 (first stage).
-template <int NP, bool RHS>
-__device__ __forceinline__ void load_res(const StageParams& p, const Bufs& B, int c, unsigned kb,
-                                         double (&resv)[NP]) {
+template <typename R, int NP, bool RHS>
+__device__ __forceinline__ void load_res(const StageScalars<R>& k, const Bufs& B, int c,
+                                         unsigned kb, R (&resv)[NP]) {
+  constexpr unsigned KP = kWave * sizeof(R);
   if constexpr (!RHS) {
-    if (p.rkA != 0.0) {
+    if (k.A != R(0)) {
 #pragma unroll
-      for (int n = 0; n < NP; ++n) resv[n] = ld(B.res, kb, (c * NP + n) * kPlane);
+      for (int n = 0; n < NP; ++n) resv[n] = ldr<R>(B.res, kb, (c * NP + n) * KP);
       return;
     }
   }
 #pragma unroll
-  for (int n = 0; n < NP; ++n) resv[n] = 0.0;
+  for (int n = 0; n < NP; ++n) resv[n] = R(0);
+}
+
+// Neighbour face nodes of face f (in my face's parameter order) and the
+// face geometry at the face's Gauss points.
+template <typename R, int N, int NQ>
+__device__ __forceinline__ void face_data(const Bufs& B, int f, unsigned kb, R (&pn)[N + 1],
+                                          R (&un)[N + 1], R (&vn)[N + 1], R (&fg)[3][NQ]) {
+  constexpr int NP = (N + 1) * (N + 1);
+  constexpr unsigned KP = kWave * sizeof(R);
+  // offset (in values, within the slice) of the neighbour's value at my
+  // face node 0, and the step along my face parameter
+  const unsigned nb0 = (unsigned)ldi(B.nbr, kb / sizeof(R) * 4, (0 * 4 + f) * kWave * 4);
+  const int nstep = ldi(B.nbr, kb / sizeof(R) * 4, (1 * 4 + f) * kWave * 4);
+#pragma unroll
+  for (int m = 0; m <= N; ++m) {
+    const unsigned off = (nb0 + (unsigned)(nstep * m)) * sizeof(R);
+    pn[m] = ldr<R>(B.qslice, off, 0);
+    un[m] = ldr<R>(B.qslice, off, NP * KP);
+    vn[m] = ldr<R>(B.qslice, off, 2 * NP * KP);
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) fg[c][j] = ldr<R>(B.face, kb, (c * 4 * NQ + f * NQ + j) * KP);
 }
 
 // Pressure equation: b_p = int u.grad(v) J - int 1/2(2{u}.n - tau_p [p]) v sJ.
-template <int N, int NQ, bool RHS>
-__device__ __forceinline__ void pressure_wave(const StageParams& p, const Bufs& B,
-                                              const double* tq, unsigned kb, int lane,
-                                              bool active) {
-  constexpr ct::Tables<N, NQ> T = ct::make_tables<N, NQ>();
+template <typename R, int N, int NQ, bool RHS>
+__device__ __forceinline__ void pressure_wave(const StageScalars<R>& k, const Bufs& B,
+                                              const R* tq, unsigned kb, int lane, bool active) {
+  constexpr ct::Ops<R, N, NQ> T = ct::make_ops<R, N, NQ>();
   constexpr int NP1 = N + 1, NP = NP1 * NP1, NQ2 = NQ * NQ;
+  constexpr unsigned KP = kWave * sizeof(R);
   auto U = [&](int n) { return tq[(NP + n) * kWave + lane]; };
   auto V = [&](int n) { return tq[(2 * NP + n) * kWave + lane]; };
   auto P = [&](int n) { return tq[n * kWave + lane]; };
 
-  double bp[NP];
+  R bp[NP];
 #pragma unroll
-  for (int n = 0; n < NP; ++n) bp[n] = 0.0;
+  for (int n = 0; n < NP; ++n) bp[n] = R(0);
 
   // a2: sum_q w_q J (l_r (Jr_x u + Jr_y v) + l_s (Js_x u + Js_y v))
-  double gc[4][NQ], gn[4][NQ];
+  R gc[4][NQ], gn[4][NQ];
 #pragma unroll
   for (int g = 0; g < 4; ++g)
 #pragma unroll
-    for (int j = 0; j < NQ; ++j) gc[g][j] = ld(B.vol, kb, (g * NQ2 + NQ * j) * kPlane);
+    for (int j = 0; j < NQ; ++j) gc[g][j] = ldr<R>(B.vol, kb, (g * NQ2 + NQ * j) * KP);
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
     if (i + 1 < NQ) {
 #pragma unroll
       for (int g = 0; g < 4; ++g)
 #pragma unroll
-        for (int j = 0; j < NQ; ++j) gn[g][j] = ld(B.vol, kb, (g * NQ2 + i + 1 + NQ * j) * kPlane);
+        for (int j = 0; j < NQ; ++j) gn[g][j] = ldr<R>(B.vol, kb, (g * NQ2 + i + 1 + NQ * j) * KP);
     }
     order();
-    double tu[NP1], tv[NP1];
+    R tu[NP1], tv[NP1];
 #pragma unroll
     for (int bb = 0; bb < NP1; ++bb) {
-      double su = 0.0, sv = 0.0;
+      R su = R(0), sv = R(0);
 #pragma unroll
       for (int a = 0; a < NP1; ++a) {
         su += T.V[i][a] * U(a + NP1 * bb);
@@ -230,19 +274,19 @@ __device__ __forceinline__ void pressure_wave(const StageParams& p, const Bufs& 
       tu[bb] = su;
       tv[bb] = sv;
     }
-    double cr[NP1], cs[NP1];
+    R cr[NP1], cs[NP1];
 #pragma unroll
-    for (int bb = 0; bb < NP1; ++bb) cr[bb] = cs[bb] = 0.0;
+    for (int bb = 0; bb < NP1; ++bb) cr[bb] = cs[bb] = R(0);
 #pragma unroll
     for (int j = 0; j < NQ; ++j) {
-      double uq = 0.0, vq = 0.0;
+      R uq = R(0), vq = R(0);
 #pragma unroll
       for (int bb = 0; bb < NP1; ++bb) {
         uq += T.V[j][bb] * tu[bb];
         vq += T.V[j][bb] * tv[bb];
       }
-      const double Ur = gc[0][j] * uq + gc[1][j] * vq;
-      const double Us = gc[2][j] * uq + gc[3][j] * vq;
+      const R Ur = gc[0][j] * uq + gc[1][j] * vq;
+      const R Us = gc[2][j] * uq + gc[3][j] * vq;
 #pragma unroll
       for (int bb = 0; bb < NP1; ++bb) {
         cr[bb] += T.V[j][bb] * Ur;
@@ -261,29 +305,14 @@ __device__ __forceinline__ void pressure_wave(const StageParams& p, const Bufs& 
   }
 
   // a1 + a3
-  const double tau_p = p.tau_p;
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
     order();
-    // byte offset (in the slice) of the neighbour's value at my face node 0,
-    // and the byte step along my face parameter
-    const unsigned nb0 = (unsigned)ldi(B.nbr, kb >> 1, (0 * 4 + f) * (kPlane >> 1));
-    const int nstep = ldi(B.nbr, kb >> 1, (1 * 4 + f) * (kPlane >> 1));
-    double pn[NP1], un[NP1], vn[NP1], fg[3][NQ];
-#pragma unroll
-    for (int m = 0; m < NP1; ++m) {
-      const unsigned off = nb0 + (unsigned)(nstep * m);
-      pn[m] = ld(B.qslice, off, 0);
-      un[m] = ld(B.qslice, off, NP * kPlane);
-      vn[m] = ld(B.qslice, off, 2 * NP * kPlane);
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int j = 0; j < NQ; ++j) fg[c][j] = ld(B.face, kb, (c * 4 * NQ + f * NQ + j) * kPlane);
+    R pn[NP1], un[NP1], vn[NP1], fg[3][NQ];
+    face_data<R, N, NQ>(B, f, kb, pn, un, vn, fg);
 #pragma unroll
     for (int j = 0; j < NQ; ++j) {
-      double pm = 0.0, um = 0.0, vm = 0.0, pp = 0.0, up = 0.0, vp = 0.0;
+      R pm = R(0), um = R(0), vm = R(0), pp = R(0), up = R(0), vp = R(0);
 #pragma unroll
       for (int m = 0; m < NP1; ++m) {
         pm += T.V[j][m] * P(fnode<N>(f, m));
@@ -293,8 +322,8 @@ __device__ __forceinline__ void pressure_wave(const StageParams& p, const Bufs& 
         up += T.V[j][m] * un[m];
         vp += T.V[j][m] * vn[m];
       }
-      const double nx = fg[0][j], ny = fg[1][j], wsJ = fg[2][j];
-      const double fp = 0.5 * wsJ * ((up + um) * nx + (vp + vm) * ny - tau_p * (pp - pm));
+      const R nx = fg[0][j], ny = fg[1][j], wsJ = fg[2][j];
+      const R fp = R(0.5) * wsJ * ((up + um) * nx + (vp + vm) * ny - k.tau_p * (pp - pm));
 #pragma unroll
       for (int m = 0; m < NP1; ++m) bp[fnode<N>(f, m)] -= T.V[j][m] * fp;
     }
@@ -303,68 +332,68 @@ __device__ __forceinline__ void pressure_wave(const StageParams& p, const Bufs& 
 
   // a4 + a5
   order();
-  double resv[NP], dq[NP];
-  load_res<NP, RHS>(p, B, 0, kb, resv);
-  wadg_inverse<N, NQ>(bp, B, 4 * NQ2, kb, dq);
-  finish_field<NP, RHS>(p, B, tq, 0, kb, lane, active, resv, dq);
+  R resv[NP], dq[NP];
+  load_res<R, NP, RHS>(k, B, 0, kb, resv);
+  wadg_inverse<R, N, NQ>(bp, B, 4 * NQ2, kb, dq);
+  finish_field<R, NP, RHS>(k, B, tq, 0, kb, lane, active, resv, dq);
 }
 
 // Velocity equations: b_u = -int grad(p) . tau J - int 1/2([p] - tau_u [u].n) tau.n sJ.
-template <int N, int NQ, bool RHS>
-__device__ __forceinline__ void velocity_wave(const StageParams& p, const Bufs& B,
-                                              const double* tq, unsigned kb, int lane,
-                                              bool active) {
-  constexpr ct::Tables<N, NQ> T = ct::make_tables<N, NQ>();
+template <typename R, int N, int NQ, bool RHS>
+__device__ __forceinline__ void velocity_wave(const StageScalars<R>& k, const Bufs& B,
+                                              const R* tq, unsigned kb, int lane, bool active) {
+  constexpr ct::Ops<R, N, NQ> T = ct::make_ops<R, N, NQ>();
   constexpr int NP1 = N + 1, NP = NP1 * NP1, NQ2 = NQ * NQ;
+  constexpr unsigned KP = kWave * sizeof(R);
   auto U = [&](int n) { return tq[(NP + n) * kWave + lane]; };
   auto V = [&](int n) { return tq[(2 * NP + n) * kWave + lane]; };
   auto P = [&](int n) { return tq[n * kWave + lane]; };
 
-  double bu[NP], bv[NP];
+  R bu[NP], bv[NP];
 #pragma unroll
-  for (int n = 0; n < NP; ++n) bu[n] = bv[n] = 0.0;
+  for (int n = 0; n < NP; ++n) bu[n] = bv[n] = R(0);
 
   // a2: -sum_q w_q J l (p_x, p_y)
-  double gc[4][NQ], gn[4][NQ];
+  R gc[4][NQ], gn[4][NQ];
 #pragma unroll
   for (int g = 0; g < 4; ++g)
 #pragma unroll
-    for (int j = 0; j < NQ; ++j) gc[g][j] = ld(B.vol, kb, (g * NQ2 + NQ * j) * kPlane);
+    for (int j = 0; j < NQ; ++j) gc[g][j] = ldr<R>(B.vol, kb, (g * NQ2 + NQ * j) * KP);
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
     if (i + 1 < NQ) {
 #pragma unroll
       for (int g = 0; g < 4; ++g)
 #pragma unroll
-        for (int j = 0; j < NQ; ++j) gn[g][j] = ld(B.vol, kb, (g * NQ2 + i + 1 + NQ * j) * kPlane);
+        for (int j = 0; j < NQ; ++j) gn[g][j] = ldr<R>(B.vol, kb, (g * NQ2 + i + 1 + NQ * j) * KP);
     }
     order();
-    double td[NP1], tp[NP1];
+    R td[NP1], tp[NP1];
 #pragma unroll
     for (int bb = 0; bb < NP1; ++bb) {
-      double sd = 0.0, sp = 0.0;
+      R sd = R(0), sp = R(0);
 #pragma unroll
       for (int a = 0; a < NP1; ++a) {
-        const double pa = P(a + NP1 * bb);
+        const R pa = P(a + NP1 * bb);
         sd += T.D[i][a] * pa;
         sp += T.V[i][a] * pa;
       }
       td[bb] = sd;
       tp[bb] = sp;
     }
-    double cx[NP1], cy[NP1];
+    R cx[NP1], cy[NP1];
 #pragma unroll
-    for (int bb = 0; bb < NP1; ++bb) cx[bb] = cy[bb] = 0.0;
+    for (int bb = 0; bb < NP1; ++bb) cx[bb] = cy[bb] = R(0);
 #pragma unroll
     for (int j = 0; j < NQ; ++j) {
-      double pr = 0.0, ps = 0.0;
+      R pr = R(0), ps = R(0);
 #pragma unroll
       for (int bb = 0; bb < NP1; ++bb) {
         pr += T.V[j][bb] * td[bb];
         ps += T.D[j][bb] * tp[bb];
       }
-      const double Gx = gc[0][j] * pr + gc[2][j] * ps;
-      const double Gy = gc[1][j] * pr + gc[3][j] * ps;
+      const R Gx = gc[0][j] * pr + gc[2][j] * ps;
+      const R Gy = gc[1][j] * pr + gc[3][j] * ps;
 #pragma unroll
       for (int bb = 0; bb < NP1; ++bb) {
         cx[bb] += T.V[j][bb] * Gx;
@@ -387,27 +416,14 @@ __device__ __forceinline__ void velocity_wave(const StageParams& p, const Bufs& 
   }
 
   // a1 + a3
-  const double tau_u = p.tau_u;
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
     order();
-    const unsigned nb0 = (unsigned)ldi(B.nbr, kb >> 1, (0 * 4 + f) * (kPlane >> 1));
-    const int nstep = ldi(B.nbr, kb >> 1, (1 * 4 + f) * (kPlane >> 1));
-    double pn[NP1], un[NP1], vn[NP1], fg[3][NQ];
-#pragma unroll
-    for (int m = 0; m < NP1; ++m) {
-      const unsigned off = nb0 + (unsigned)(nstep * m);
-      pn[m] = ld(B.qslice, off, 0);
-      un[m] = ld(B.qslice, off, NP * kPlane);
-      vn[m] = ld(B.qslice, off, 2 * NP * kPlane);
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int j = 0; j < NQ; ++j) fg[c][j] = ld(B.face, kb, (c * 4 * NQ + f * NQ + j) * kPlane);
+    R pn[NP1], un[NP1], vn[NP1], fg[3][NQ];
+    face_data<R, N, NQ>(B, f, kb, pn, un, vn, fg);
 #pragma unroll
     for (int j = 0; j < NQ; ++j) {
-      double pm = 0.0, um = 0.0, vm = 0.0, pp = 0.0, up = 0.0, vp = 0.0;
+      R pm = R(0), um = R(0), vm = R(0), pp = R(0), up = R(0), vp = R(0);
 #pragma unroll
       for (int m = 0; m < NP1; ++m) {
         pm += T.V[j][m] * P(fnode<N>(f, m));
@@ -417,9 +433,9 @@ __device__ __forceinline__ void velocity_wave(const StageParams& p, const Bufs& 
         up += T.V[j][m] * un[m];
         vp += T.V[j][m] * vn[m];
       }
-      const double nx = fg[0][j], ny = fg[1][j], wsJ = fg[2][j];
-      const double fu = 0.5 * wsJ * ((pp - pm) - tau_u * ((up - um) * nx + (vp - vm) * ny));
-      const double fx = fu * nx, fy = fu * ny;
+      const R nx = fg[0][j], ny = fg[1][j], wsJ = fg[2][j];
+      const R fu = R(0.5) * wsJ * ((pp - pm) - k.tau_u * ((up - um) * nx + (vp - vm) * ny));
+      const R fx = fu * nx, fy = fu * ny;
 #pragma unroll
       for (int m = 0; m < NP1; ++m) {
         bu[fnode<N>(f, m)] -= T.V[j][m] * fx;
@@ -432,24 +448,25 @@ __device__ __forceinline__ void velocity_wave(const StageParams& p, const Bufs& 
 
   // a4 + a5, one field at a time
   order();
-  double resv[NP], dq[NP];
-  load_res<NP, RHS>(p, B, 1, kb, resv);
-  wadg_inverse<N, NQ>(bu, B, 5 * NQ2, kb, dq);
-  finish_field<NP, RHS>(p, B, tq, 1, kb, lane, active, resv, dq);
+  R resv[NP], dq[NP];
+  load_res<R, NP, RHS>(k, B, 1, kb, resv);
+  wadg_inverse<R, N, NQ>(bu, B, 5 * NQ2, kb, dq);
+  finish_field<R, NP, RHS>(k, B, tq, 1, kb, lane, active, resv, dq);
   order();
-  load_res<NP, RHS>(p, B, 2, kb, resv);
-  wadg_inverse<N, NQ>(bv, B, 5 * NQ2, kb, dq);
-  finish_field<NP, RHS>(p, B, tq, 2, kb, lane, active, resv, dq);
+  load_res<R, NP, RHS>(k, B, 2, kb, resv);
+  wadg_inverse<R, N, NQ>(bv, B, 5 * NQ2, kb, dq);
+  finish_field<R, NP, RHS>(k, B, tq, 2, kb, lane, active, resv, dq);
 }
 
 }  // namespace
 
-template <int N, int NQ, bool RHS>
+template <typename R, int N, int NQ, bool RHS>
 __global__ __launch_bounds__(2 * kWave) void stage_kernel(const StageParams p) {
   constexpr int NP = (N + 1) * (N + 1);
   constexpr int NQ2 = NQ * NQ;
-  constexpr unsigned tile = 3u * NP * kWave;   // doubles per group tile
-  __shared__ double tq[tile];
+  constexpr unsigned tile = 3u * NP * kWave;   // values per group tile
+  constexpr unsigned KP = kWave * sizeof(R);
+  __shared__ __attribute__((aligned(16))) R tq[tile];
 
   // workgroup -> work item (XCD-aware): XCD x = bid % 8 receives the
   // contiguous logical range [x q8 + min(x, r8), ...) in launch order
@@ -472,52 +489,72 @@ __global__ __launch_bounds__(2 * kWave) void stage_kernel(const StageParams p) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & (kWave - 1);
 
+  const R* Qin = static_cast<const R*>(p.Qin);
   const size_t slice = (size_t)s * p.nEG * tile;
   const size_t grp = slice + (size_t)eg * tile;
   Bufs B;
-  B.qin = make_rsrc(p.Qin + grp, tile * 8u);
-  B.qout = make_rsrc(p.Qout + grp, tile * 8u);
-  B.res = make_rsrc(RHS ? p.Qout + grp : p.res + grp, tile * 8u);
-  B.qslice = make_rsrc(p.Qin + slice, (unsigned)p.nEG * tile * 8u);
-  B.vol = make_rsrc(p.vol + (size_t)eg * 6 * NQ2 * kWave, 6u * NQ2 * kPlane);
-  B.face = make_rsrc(p.face + (size_t)eg * 12 * NQ * kWave, 12u * NQ * kPlane);
+  B.qin = make_rsrc(Qin + grp, tile * sizeof(R));
+  B.qout = make_rsrc(static_cast<R*>(p.Qout) + grp, tile * sizeof(R));
+  B.res = make_rsrc(static_cast<R*>(RHS ? p.Qout : p.res) + grp, tile * sizeof(R));
+  B.qslice = make_rsrc(Qin + slice, (unsigned)p.nEG * tile * sizeof(R));
+  B.vol = make_rsrc(static_cast<const R*>(p.vol) + (size_t)eg * 6 * NQ2 * kWave, 6u * NQ2 * KP);
+  B.face = make_rsrc(static_cast<const R*>(p.face) + (size_t)eg * 12 * NQ * kWave,
+                     12u * NQ * KP);
   B.nbr = make_rsrc(p.nbr + (size_t)eg * 8 * kWave, 8u * kWave * 4u);
 
   // stage the input tile in LDS: 16-byte chunks, consecutive threads on
   // consecutive chunks
-  for (unsigned c = tid; c < tile / 2; c += 2 * kWave) {
+  constexpr unsigned chunks = tile * sizeof(R) / 16;
+  for (unsigned c = tid; c < chunks; c += 2 * kWave) {
     const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(B.qin, c * 16u, 0, 0);
-    *reinterpret_cast<u32x4*>(&tq[2 * c]) = v;
+    *reinterpret_cast<u32x4*>(reinterpret_cast<char*>(tq) + c * 16u) = v;
   }
   __syncthreads();
 
+  StageScalars<R> k;
+  k.tau_p = (R)p.tau_p;
+  k.tau_u = (R)p.tau_u;
+  k.A = (R)p.rkA;
+  k.B = (R)p.rkB;
+  k.dt = (R)p.dt;
   const bool active = eg * kWave + lane < p.K;
-  const unsigned kb = (unsigned)lane * 8u;
+  const unsigned kb = (unsigned)lane * sizeof(R);
   if (wave == 0)
-    pressure_wave<N, NQ, RHS>(p, B, tq, kb, lane, active);
+    pressure_wave<R, N, NQ, RHS>(k, B, tq, kb, lane, active);
   else
-    velocity_wave<N, NQ, RHS>(p, B, tq, kb, lane, active);
+    velocity_wave<R, N, NQ, RHS>(k, B, tq, kb, lane, active);
 }
 
 namespace {
 
-template <int N, int NQ>
+template <typename R, int N, int NQ>
 int launch_nq(bool rhs, const StageParams& p, void* stream) {
   const int nwg = p.nEG * p.S;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (rhs)
-    hipLaunchKernelGGL((stage_kernel<N, NQ, true>), dim3(nwg), dim3(2 * kWave), 0, st, p);
+    hipLaunchKernelGGL((stage_kernel<R, N, NQ, true>), dim3(nwg), dim3(2 * kWave), 0, st, p);
   else
-    hipLaunchKernelGGL((stage_kernel<N, NQ, false>), dim3(nwg), dim3(2 * kWave), 0, st, p);
+    hipLaunchKernelGGL((stage_kernel<R, N, NQ, false>), dim3(nwg), dim3(2 * kWave), 0, st, p);
   return (int)hipGetLastError();
 }
 
-template <int N>
+template <typename R, int N>
 int launch_n(int nq, bool rhs, const StageParams& p, void* stream) {
   switch (nq - N) {
-    case 1: return launch_nq<N, N + 1>(rhs, p, stream);
-    case 2: return launch_nq<N, N + 2>(rhs, p, stream);
-    case 3: return launch_nq<N, N + 3>(rhs, p, stream);
+    case 1: return launch_nq<R, N, N + 1>(rhs, p, stream);
+    case 2: return launch_nq<R, N, N + 2>(rhs, p, stream);
+    case 3: return launch_nq<R, N, N + 3>(rhs, p, stream);
+    default: return (int)hipErrorInvalidValue;
+  }
+}
+
+template <typename R>
+int launch_r(int N, int nq, bool rhs, const StageParams& p, void* stream) {
+  switch (N) {
+    case 1: return launch_n<R, 1>(nq, rhs, p, stream);
+    case 2: return launch_n<R, 2>(nq, rhs, p, stream);
+    case 3: return launch_n<R, 3>(nq, rhs, p, stream);
+    case 4: return launch_n<R, 4>(nq, rhs, p, stream);
     default: return (int)hipErrorInvalidValue;
   }
 }
@@ -527,13 +564,11 @@ int launch_n(int nq, bool rhs, const StageParams& p, void* stream) {
 bool stage_supported(int N, int nq) { return N >= 1 && N <= 4 && nq >= N + 1 && nq <= N + 3; }
 
 int launch_stage(int N, int nq, bool rhs, const StageParams& p, void* stream) {
-  switch (N) {
-    case 1: return launch_n<1>(nq, rhs, p, stream);
-    case 2: return launch_n<2>(nq, rhs, p, stream);
-    case 3: return launch_n<3>(nq, rhs, p, stream);
-    case 4: return launch_n<4>(nq, rhs, p, stream);
-    default: return (int)hipErrorInvalidValue;
-  }
+  return launch_r<double>(N, nq, rhs, p, stream);
+}
+
+int launch_stage_fp32(int N, int nq, const StageParams& p, void* stream) {
+  return launch_r<float>(N, nq, false, p, stream);
 }
 
 }  // namespace wadg

@@ -44,9 +44,9 @@ struct MeshIn {
 // Host geometry arrays, untiled (element index fastest):
 //   vol  [6][nq*nq][K]   W ys, -W xs, -W yr, W xr, c2/J, 1/J
 //   face [3][4][nq][K]   nx, ny, w sJ
-//   nbr  [2][4][K]       byte offset, within one slice of the tiled state
-//                        layout, of the neighbour's value at my face node 0
-//                        (field 0), and the byte step along my face parameter
+//   nbr  [2][4][K]       offset (in values), within one slice of the tiled
+//                        state layout, of the neighbour's value at my face
+//                        node 0 (field 0), and the step along my face parameter
 int build_geometry(const MeshIn& m, const RefOps& ops, std::vector<double>* vol,
                    std::vector<double>* face, std::vector<int32_t>* nbr, std::string* err);
 
@@ -65,12 +65,14 @@ std::vector<T> tile_planes(const std::vector<T>& a, int planes, int K) {
 // Physical coordinates of the volume quadrature points, [K][nq*nq].
 void quadrature_points(const MeshIn& m, const RefOps& ops, double* xq, double* yq);
 
+// Arrays are of the kernel's arithmetic type (double, or float for the
+// FP32-bulk propagator) except the int32 neighbour offsets.
 struct StageParams {
-  const double* Qin;     // [S][G][3][Np][64]
-  double* Qout;          // [S][G][3][Np][64]  (rhs mode: dQ/dt)
-  double* res;           // [S][G][3][Np][64]  LSRK residual (stage mode)
-  const double* vol;     // [G][6][Nq][64]
-  const double* face;    // [G][3][4][nq][64]
+  const void* Qin;       // [S][G][3][Np][64]
+  void* Qout;            // [S][G][3][Np][64]  (rhs mode: dQ/dt)
+  void* res;             // [S][G][3][Np][64]  LSRK residual (stage mode)
+  const void* vol;       // [G][6][Nq][64]
+  const void* face;      // [G][3][4][nq][64]
   const int32_t* nbr;    // [G][2][4][64]
   int32_t K, S, nEG;
   int32_t tile_groups, tile_slices;   // schedule tile (clamped to nEG, S)
@@ -81,6 +83,11 @@ struct StageParams {
 // Launch one stage (rhs == false: LSRK stage update; rhs == true: write
 // dQ/dt to Qout).  Returns a hipError_t as int.
 int launch_stage(int N, int nq, bool rhs, const StageParams& p, void* stream);
+// The same LSRK stage in FP32 (arrays of float).
+int launch_stage_fp32(int N, int nq, const StageParams& p, void* stream);
+// Elementwise precision conversion of n values (FP64 <-> FP32).
+int launch_to_fp32(const double* in, float* out, size_t n, void* stream);
+int launch_to_fp64(const float* in, double* out, size_t n, void* stream);
 bool stage_supported(int N, int nq);
 
 // Per-slice norms over the tiled layout (padding skipped): partial sums into

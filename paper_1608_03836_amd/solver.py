@@ -80,6 +80,16 @@ class Solver:
         B.wadg_integrate(self.ctx, Q, work, S, dt, nsteps, stream)
         return Q
 
+    def workspace_fp32(self, S):
+        n = B.wadg_workspace_bytes_fp32(self.ctx, S) // 4
+        return self.torch.empty(n, dtype=self.torch.float32, device=self.device)
+
+    def integrate_fp32(self, Q, S, dt, nsteps, work=None, stream=None):
+        """FP32-bulk sweep: FP64 Q in and out, FP32 interior."""
+        work = self.workspace_fp32(S) if work is None else work
+        B.wadg_integrate_fp32(self.ctx, Q, work, S, dt, nsteps, stream)
+        return Q
+
     def norms(self, A, Bt=None, S=1, stream=None, check_finite=True):
         return B.wadg_norms(self.ctx, A, Bt, S, stream, check_finite=check_finite)
 

@@ -22,7 +22,7 @@ W = pytest.importorskip("paper_1608_03836_amd.binding",
 def _declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(wadg_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(wadg_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_exports_every_declared_symbol():

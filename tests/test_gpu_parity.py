@@ -222,3 +222,44 @@ def test_full_size_wadg128_sampled_slices(W):
     slices 0, 17, 255 checked."""
     _print_case(test="full-size", workload="wadg128")
     _sampled_full_size(W, "wadg128", [0, 17, 255])
+
+
+# -- FP32-bulk propagation: FP64 boundary states, FP32 slice interior ---------
+TOL_FP32 = 1e-6
+
+
+def _fp32_error(got, want):
+    return max(_rel(got[s], want[s]) for s in range(want.shape[0]))
+
+
+def test_fp32_bulk_small(W):
+    """wadg4 with 4 steps per slice through the FP32-bulk propagator, against
+    the FP64 oracle: relative error per slice <= 1e-6."""
+    _print_case(test="fp32-bulk", workload="wadg4")
+    prob = make_problem("wadg4")
+    o = WADGOracle(prob.mesh, nq1=prob.nq1, c2=prob.c2, tau_p=prob.tau_p, tau_u=prob.tau_u)
+    want = o.integrate(prob.Q0, prob.dt, 4)
+    sol = W.Solver.from_problem(prob)
+    Q = sol.upload(prob.Q0)
+    sol.integrate_fp32(Q, prob.S, prob.dt, 4)
+    err = _fp32_error(sol.download(Q, prob.S), want)
+    print(f"FP32-bulk wadg4 relative error vs FP64 oracle: {err:.3e}")
+    assert err <= TOL_FP32
+    assert err > 1e-12          # it really ran in single precision
+
+
+def test_fp32_bulk_full_size_wadg128(W):
+    """wadg128 (heterogeneous c^2, 256 slices x 10 steps) in FP32 bulk;
+    slices 0, 17, 255 against the FP64 oracle."""
+    _print_case(test="fp32-bulk", workload="wadg128")
+    prob = make_problem("wadg128")
+    sol = W.Solver.from_problem(prob)
+    Q = sol.upload(prob.Q0)
+    sol.integrate_fp32(Q, prob.S, prob.dt, prob.nsteps)
+    got = sol.download(Q, prob.S)
+    sample = [0, 17, 255]
+    o = WADGOracle(prob.mesh, nq1=prob.nq1, c2=prob.c2, tau_p=prob.tau_p, tau_u=prob.tau_u)
+    want = o.integrate(prob.Q0[sample], prob.dt, prob.nsteps)
+    err = _fp32_error(got[sample], want)
+    print(f"FP32-bulk wadg128 relative error vs FP64 oracle: {err:.3e}")
+    assert err <= TOL_FP32
