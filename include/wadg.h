@@ -163,6 +163,28 @@ int wadg_workspace_bytes_fp32(wadg_ctx ctx, int32_t S, size_t* bytes);
 int wadg_integrate_fp32(wadg_ctx ctx, double* Q, void* work, int32_t S, double dt,
                         int32_t nsteps, void* stream);
 
+/* Parareal iteration over S time slices of length dT = dt * nsteps_fine
+ * (concurrent propagation and correction of the slices; the paper defines
+ * only the propagators, the iteration is the standard parareal one):
+ *   U_0 = y0,  U_{s+1}^0 = G(U_s^0),
+ *   U_{s+1}^{k+1} = G(U_s^{k+1}) + F(U_s^k) - G(U_s^k),
+ * F = nsteps_fine LSRK steps of dt (all S slices in one wadg_integrate, or
+ * wadg_integrate_fp32 when fine_fp32 != 0), G = nsteps_coarse steps of
+ * dT / nsteps_coarse, always FP64, one slice after another; the correction
+ * update and the convergence norm run in FP64 on the GPU.  Stops when
+ * max_s ||U_s^{k+1} - U_s^k||_2 / ||U_s^{k+1}||_2 <= tol or after max_iter
+ * iterations; after k iterations U_0..U_k equal the serial fine sweep (to
+ * rounding), after S iterations all of them do.
+ *   y0  device, one slice (tiled layout); may be U itself.
+ *   U   device, S+1 slices: out, U_s ~ y(t0 + s dT).
+ *   work  device workspace of wadg_parareal_workspace_bytes bytes.
+ *   iterations, last_change: host out.  Synchronises `stream` once per
+ *   iteration.  Returns WADG_E_NONFINITE if an iterate is not finite. */
+int wadg_parareal_workspace_bytes(wadg_ctx ctx, int32_t S, int32_t fine_fp32, size_t* bytes);
+int wadg_parareal(wadg_ctx ctx, const double* y0, double* U, void* work, int32_t S, double dt,
+                  int32_t nsteps_fine, int32_t nsteps_coarse, int32_t max_iter, double tol,
+                  int32_t fine_fp32, int32_t* iterations, double* last_change, void* stream);
+
 /* Per-slice reductions (the norms the convergence checks use):
  *   out[s][0] = ||A_s - B_s||_2,  out[s][1] = ||B_s||_2,
  *   out[s][2] = max |A_s - B_s|,  out[s][3] = 1 if every A_s entry is finite

@@ -34,3 +34,4 @@ from .basis import (gauss_legendre, gll_nodes, legendre_orthonormal,  # noqa: F4
 from .lsrk import LSRK54, lsrk_integrate, stability_polynomial_coeffs  # noqa: F401
 from .wadg import WADGOracle  # noqa: F401
 from .heat import heat_rhs, heat_integrate, heat_eigenvalues  # noqa: F401
+from .parareal import parareal, wadg_propagators  # noqa: F401

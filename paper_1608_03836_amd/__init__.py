@@ -10,7 +10,7 @@ from . import binding  # noqa: F401  (raises if libwadg.so is missing)
 from .binding import (  # noqa: F401
     wadg_quadrature_points, wadg_geometry, wadg_create, wadg_destroy, wadg_state_doubles,
     wadg_workspace_bytes, wadg_rhs, wadg_integrate, wadg_workspace_bytes_fp32,
-    wadg_integrate_fp32, wadg_norms, wadg_set_schedule,
+    wadg_integrate_fp32, wadg_parareal_workspace_bytes, wadg_parareal, wadg_norms, wadg_set_schedule,
     wadg_status_string, wadg_last_error, MeshDesc, WadgError, tile_state, untile_state,
 )
 from .solver import Solver  # noqa: F401

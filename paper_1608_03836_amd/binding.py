@@ -62,6 +62,13 @@ def _load():
         "wadg_workspace_bytes_fp32": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.POINTER(sz)]),
         "wadg_integrate_fp32": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, ctypes.c_double,
                                                ctypes.c_int32, vp]),
+        "wadg_parareal_workspace_bytes": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32,
+                                                         ctypes.POINTER(sz)]),
+        "wadg_parareal": (ctypes.c_int, [vp, vp, vp, vp, ctypes.c_int32, ctypes.c_double,
+                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_double, ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_double), vp]),
         "wadg_norms": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, _c_double_p, vp]),
         "wadg_set_schedule": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32]),
         "wadg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -78,6 +85,7 @@ LIB = _load()
 EXPORTED = ("wadg_quadrature_points", "wadg_geometry", "wadg_create", "wadg_destroy",
             "wadg_state_doubles", "wadg_workspace_bytes", "wadg_rhs", "wadg_integrate",
             "wadg_workspace_bytes_fp32", "wadg_integrate_fp32",
+            "wadg_parareal_workspace_bytes", "wadg_parareal",
             "wadg_norms", "wadg_set_schedule", "wadg_status_string", "wadg_last_error")
 
 
@@ -199,6 +207,24 @@ def wadg_workspace_bytes_fp32(ctx, S):
 def wadg_integrate_fp32(ctx, Q, work, S, dt, nsteps, stream=None):
     _check(LIB.wadg_integrate_fp32(ctx, _ptr(Q), _ptr(work), int(S), float(dt), int(nsteps),
                                    _stream(stream)))
+
+
+def wadg_parareal_workspace_bytes(ctx, S, fine_fp32=False):
+    n = ctypes.c_size_t()
+    _check(LIB.wadg_parareal_workspace_bytes(ctx, int(S), int(bool(fine_fp32)), ctypes.byref(n)))
+    return n.value
+
+
+def wadg_parareal(ctx, y0, U, work, S, dt, nsteps_fine, nsteps_coarse, max_iter, tol,
+                  fine_fp32=False, stream=None):
+    """Returns (iterations, last relative change)."""
+    it = ctypes.c_int32()
+    ch = ctypes.c_double()
+    _check(LIB.wadg_parareal(ctx, _ptr(y0), _ptr(U), _ptr(work), int(S), float(dt),
+                             int(nsteps_fine), int(nsteps_coarse), int(max_iter), float(tol),
+                             int(bool(fine_fp32)), ctypes.byref(it), ctypes.byref(ch),
+                             _stream(stream)))
+    return it.value, ch.value
 
 
 def wadg_norms(ctx, A, B, S, stream=None, check_finite=True):

@@ -15,7 +15,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libwadg.so")
 
 SOURCES = ["reference.cpp", "stage_kernel.hip", "norms_kernel.hip", "convert_kernel.hip",
-           "api.hip"]
+           "parareal_kernel.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

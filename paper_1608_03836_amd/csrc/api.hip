@@ -359,6 +359,110 @@ int wadg_integrate_fp32(wadg_ctx ctx, double* Q, void* work, int32_t S, double d
   return WADG_OK;
 }
 
+namespace {
+size_t fine_work_bytes(wadg_ctx ctx, int32_t S, int32_t fine_fp32) {
+  const size_t n = ctx->state_doubles(S);
+  return fine_fp32 ? 3 * n * sizeof(float) : 2 * n * sizeof(double);
+}
+size_t parareal_bytes(wadg_ctx ctx, int32_t S, int32_t fine_fp32) {
+  const size_t n1 = ctx->slice_doubles();
+  return (2 * (size_t)S + 3) * n1 * sizeof(double) + fine_work_bytes(ctx, S, fine_fp32) +
+         ((size_t)S * kNormBlocks * 4 + (size_t)S * 4) * sizeof(double);
+}
+}  // namespace
+
+int wadg_parareal_workspace_bytes(wadg_ctx ctx, int32_t S, int32_t fine_fp32, size_t* bytes) {
+  int st = check_slices(ctx, S);
+  if (st) return st;
+  if (!bytes) return fail(WADG_E_INVALID, "bytes is NULL");
+  *bytes = parareal_bytes(ctx, S, fine_fp32);
+  return WADG_OK;
+}
+
+int wadg_parareal(wadg_ctx ctx, const double* y0, double* U, void* work, int32_t S, double dt,
+                  int32_t nsteps_fine, int32_t nsteps_coarse, int32_t max_iter, double tol,
+                  int32_t fine_fp32, int32_t* iterations, double* last_change, void* stream) {
+  int st = check_slices(ctx, S);
+  if (st) return st;
+  if (!y0 || !U || !work || !iterations || !last_change)
+    return fail(WADG_E_INVALID, "y0, U, work, iterations and last_change must not be NULL");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(WADG_E_INVALID, "dt must be finite and > 0");
+  if (nsteps_fine < 1 || nsteps_coarse < 1 || max_iter < 0)
+    return fail(WADG_E_INVALID, "nsteps_fine, nsteps_coarse >= 1 and max_iter >= 0 required");
+  if (!(tol >= 0.0)) return fail(WADG_E_INVALID, "tol must be >= 0");
+  const size_t n1 = ctx->slice_doubles();
+  const size_t ubytes = (S + 1) * n1 * sizeof(double);
+  const size_t wbytes = parareal_bytes(ctx, S, fine_fp32);
+  if (overlaps(U, ubytes, work, wbytes)) return fail(WADG_E_INVALID, "work must not alias U");
+  if (y0 != U && overlaps(y0, n1 * sizeof(double), U, ubytes))
+    return fail(WADG_E_INVALID, "y0 must be U itself or not overlap U");
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select the context's device");
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+
+  double* F = static_cast<double*>(work);
+  double* Gold = F + (size_t)S * n1;
+  double* tmp = Gold + (size_t)S * n1;
+  double* cwork = tmp + n1;
+  char* fwork = reinterpret_cast<char*>(cwork + 2 * n1);
+  double* partials = reinterpret_cast<double*>(fwork + fine_work_bytes(ctx, S, fine_fp32));
+  double* dout = partials + (size_t)S * kNormBlocks * 4;
+  const double dtc = dt * nsteps_fine / nsteps_coarse;
+  const int32_t tile = (int32_t)ctx->tile();
+  const size_t sb = n1 * sizeof(double);
+
+  auto coarse = [&](double* q) { return wadg_integrate(ctx, q, cwork, 1, dtc, nsteps_coarse, stream); };
+  if (y0 != U) WADG_HIP(hipMemcpyAsync(U, y0, sb, hipMemcpyDeviceToDevice, hs));
+  // coarse prediction U_{s+1}^0 = G(U_s^0), remembered as G(U_s^0)
+  for (int s = 0; s < S; ++s) {
+    WADG_HIP(hipMemcpyAsync(Gold + s * n1, U + s * n1, sb, hipMemcpyDeviceToDevice, hs));
+    if ((st = coarse(Gold + s * n1))) return st;
+    WADG_HIP(hipMemcpyAsync(U + (s + 1) * n1, Gold + s * n1, sb, hipMemcpyDeviceToDevice, hs));
+  }
+  std::vector<double> out((size_t)S * 4);
+  double change = INFINITY;
+  int32_t it = 0;
+  for (int k = 0; k < max_iter; ++k) {
+    // fine propagation of all slices at once: F_s = F(U_s^k)
+    WADG_HIP(hipMemcpyAsync(F, U, (size_t)S * sb, hipMemcpyDeviceToDevice, hs));
+    st = fine_fp32 ? wadg_integrate_fp32(ctx, F, fwork, S, dt, nsteps_fine, stream)
+                   : wadg_integrate(ctx, F, reinterpret_cast<double*>(fwork), S, dt, nsteps_fine,
+                                    stream);
+    if (st) return st;
+    // serial coarse sweep with the correction update
+    for (int s = 0; s < S; ++s) {
+      WADG_HIP(hipMemcpyAsync(tmp, U + s * n1, sb, hipMemcpyDeviceToDevice, hs));
+      if ((st = coarse(tmp))) return st;
+      int e = wadg::launch_parareal_correct(tmp, F + s * n1, Gold + s * n1, U + (s + 1) * n1,
+                                            (int64_t)n1, tile, ctx->K,
+                                            partials + (size_t)s * kNormBlocks * 4, kNormBlocks,
+                                            stream);
+      if (e) return hip_fail((hipError_t)e, "parareal correction launch");
+    }
+    int e = wadg::launch_norms_final(partials, kNormBlocks, S, dout, stream);
+    if (e) return hip_fail((hipError_t)e, "reduction launch");
+    WADG_HIP(hipMemcpyAsync(out.data(), dout, out.size() * sizeof(double), hipMemcpyDeviceToHost,
+                            hs));
+    WADG_HIP(hipStreamSynchronize(hs));
+    it = k + 1;
+    change = 0.0;
+    for (int s = 0; s < S; ++s) {
+      if (out[4 * s + 3] != 0.0) {
+        *iterations = it;
+        *last_change = NAN;
+        return fail(WADG_E_NONFINITE, "non-finite parareal iterate");
+      }
+      const double c = out[4 * s + 1] > 0.0 ? std::sqrt(out[4 * s] / out[4 * s + 1])
+                                             : std::sqrt(out[4 * s]);
+      change = c > change ? c : change;
+    }
+    if (change <= tol) break;
+  }
+  *iterations = it;
+  *last_change = change;
+  return WADG_OK;
+}
+
 int wadg_norms(wadg_ctx ctx, const double* A, const double* B, int32_t S, double* out,
                void* stream) {
   int st = check_slices(ctx, S);

@@ -70,6 +70,12 @@ __global__ void norms_final_kernel(const double* __restrict__ partials, int nblk
   out[4 * s + 0] = r0; out[4 * s + 1] = r1; out[4 * s + 2] = r2; out[4 * s + 3] = r3;
 }
 
+int launch_norms_final(const double* partials, int nblk, int32_t S, double* out, void* stream) {
+  hipLaunchKernelGGL(norms_final_kernel, dim3((S + 63) / 64), dim3(64), 0,
+                     static_cast<hipStream_t>(stream), partials, nblk, S, out);
+  return (int)hipGetLastError();
+}
+
 int launch_norms(const double* A, const double* B, int32_t S, int64_t n_per_slice, int32_t tile,
                  int32_t K, double* partials, int nblk, double* out, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);

@@ -95,4 +95,13 @@ bool stage_supported(int N, int nq);
 int launch_norms(const double* A, const double* B, int32_t S, int64_t n_per_slice, int32_t tile,
                  int32_t K, double* partials, int nblk, double* out, void* stream);
 
+// Second pass of a per-slice reduction: partials [S][nblk][4] -> out [S][4].
+int launch_norms_final(const double* partials, int nblk, int32_t S, double* out, void* stream);
+
+// Parareal correction of one slice (see parareal_kernel.hip); writes block
+// partials [nblk][4] of ||change||^2, ||new||^2, max |change|, non-finite.
+int launch_parareal_correct(const double* g, const double* f, double* gold, double* u,
+                            int64_t n, int32_t tile, int32_t K, double* partials, int nblk,
+                            void* stream);
+
 }  // namespace wadg

@@ -90,6 +90,18 @@ class Solver:
         B.wadg_integrate_fp32(self.ctx, Q, work, S, dt, nsteps, stream)
         return Q
 
+    def parareal(self, y0, S, dt, nsteps_fine, nsteps_coarse, max_iter, tol, fine_fp32=False,
+                 U=None, work=None, stream=None):
+        """Parareal over S slices from the device state y0 (one slice).
+        Returns (U device tensor of S+1 slices, iterations, last change)."""
+        U = self.empty_state(S + 1) if U is None else U
+        if work is None:
+            n = B.wadg_parareal_workspace_bytes(self.ctx, S, fine_fp32) // 8 + 1
+            work = self.torch.empty(n, dtype=self.torch.float64, device=self.device)
+        it, ch = B.wadg_parareal(self.ctx, y0, U, work, S, dt, nsteps_fine, nsteps_coarse,
+                                 max_iter, tol, fine_fp32, stream)
+        return U, it, ch
+
     def norms(self, A, Bt=None, S=1, stream=None, check_finite=True):
         return B.wadg_norms(self.ctx, A, Bt, S, stream, check_finite=check_finite)
 

@@ -263,3 +263,61 @@ def test_fp32_bulk_full_size_wadg128(W):
     err = _fp32_error(got[sample], want)
     print(f"FP32-bulk wadg128 relative error vs FP64 oracle: {err:.3e}")
     assert err <= TOL_FP32
+
+
+# -- parareal slice correction ------------------------------------------------
+
+def _parareal_setup():
+    from oracle.parareal import parareal, wadg_propagators
+    prob = make_problem("wadg4", slices=[0])
+    o = WADGOracle(prob.mesh, nq1=prob.nq1, c2=prob.c2, tau_p=prob.tau_p, tau_u=prob.tau_u)
+    F, G = wadg_propagators(o, prob.dt, 4, 1)
+    return prob, parareal, F, G
+
+
+@pytest.mark.parametrize("k", [0, 2, 6])
+def test_parareal_matches_oracle_iterate(W, k):
+    """FP64 fine: the GPU iterate after k iterations equals the oracle's."""
+    _print_case(test="parareal", k=k)
+    prob, parareal, F, G = _parareal_setup()
+    S = 6
+    want, it_o, _ = parareal(F, G, prob.Q0[0], S, max_iter=k, tol=0.0)
+    sol = W.Solver.from_problem(prob)
+    y0 = sol.upload(prob.Q0)
+    U, it, ch = sol.parareal(y0, S, prob.dt, 4, 1, max_iter=k, tol=0.0)
+    assert it == it_o == k
+    _assert_close(sol.download(U, S + 1), want)
+
+
+def test_parareal_reproduces_serial_fine_solution(W):
+    """After S iterations every slice equals the serial fine sweep."""
+    _print_case(test="parareal-serial")
+    prob, parareal, F, G = _parareal_setup()
+    S = 6
+    serial = [prob.Q0[0]]
+    for _ in range(S):
+        serial.append(F(serial[-1]))
+    sol = W.Solver.from_problem(prob)
+    U, it, ch = sol.parareal(sol.upload(prob.Q0), S, prob.dt, 4, 1, max_iter=S, tol=0.0)
+    _assert_close(sol.download(U, S + 1), np.stack(serial))
+
+
+def test_parareal_fp32_fine_converges(W):
+    """FP32-bulk fine propagator, FP64 coarse/correction/norm: converges by
+    the tolerance rule, and its fixed point is within 1e-6 of the FP64
+    serial fine sweep (the error is stated)."""
+    _print_case(test="parareal-fp32")
+    prob, parareal, F, G = _parareal_setup()
+    S = 6
+    serial = [prob.Q0[0]]
+    for _ in range(S):
+        serial.append(F(serial[-1]))
+    sol = W.Solver.from_problem(prob)
+    U, it, ch = sol.parareal(sol.upload(prob.Q0), S, prob.dt, 4, 1, max_iter=S, tol=1e-6,
+                             fine_fp32=True)
+    got = sol.download(U, S + 1)
+    err = max(_rel(got[s], serial[s]) for s in range(1, S + 1))
+    print(f"parareal FP32-fine: {it} iterations, last change {ch:.2e}, "
+          f"error vs FP64 serial sweep {err:.2e}")
+    assert ch <= 1e-6 and it <= S
+    assert err <= 1e-6
