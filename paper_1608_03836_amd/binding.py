@@ -47,6 +47,15 @@ class wadg_mesh(ctypes.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built; run `python paper_1608_03836_amd/build.py`")
+    # One HIP runtime per process: torch ships its own libamdhip64 (same
+    # soname, requested under its unversioned name), so torch is loaded first
+    # and the library's dependency then resolves to that copy.  Loading the
+    # library first would bring in a second runtime, and device selection in
+    # one of them fails.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     vp, sz = ctypes.c_void_p, ctypes.c_size_t
     sig = {

@@ -147,3 +147,12 @@ def test_tiled_layout_round_trip():
         # element k = 64 g + l, field f, node n sits at t[s, g, f, n, l]
         k = K - 1
         assert t[2, k // 64, 1, 4, k % 64] == Q[2, 1, 4, k]
+
+
+def test_single_hip_runtime_in_process():
+    """The binding and torch share one libamdhip64 (two runtimes in one
+    process break device selection)."""
+    import torch  # noqa: F401
+    maps = open("/proc/self/maps").read()
+    libs = {line.split()[-1] for line in maps.splitlines() if "libamdhip64" in line}
+    assert len(libs) == 1, libs
