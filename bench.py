@@ -32,6 +32,8 @@ def parse():
     ap.add_argument("--tile-groups", type=int, default=None,
                     help="schedule: element groups per tile (default: library default)")
     ap.add_argument("--tile-slices", type=int, default=0)
+    ap.add_argument("--kernel", choices=("auto", "streamed", "resident"), default="auto",
+                    help="stage-kernel variant (default: the library's choice)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size before the timed "
                          "region, as the known-size reference for HBM byte counters")
@@ -94,6 +96,10 @@ def main():
     sol = W.Solver.from_problem(prob)
     if args.tile_groups:
         sol.set_schedule(args.tile_groups, args.tile_slices)
+    sol.set_kernel({"auto": W.WADG_KERNEL_AUTO, "streamed": W.WADG_KERNEL_STREAMED,
+                    "resident": W.WADG_KERNEL_RESIDENT}[args.kernel])
+    resident = sol.kernel_in_use() == W.WADG_KERNEL_RESIDENT
+    kname = ("resident_kernel" if resident else "stage_kernel") + f"<double,{prob.N},{prob.nq1},false>"
     S, K, N = prob.S, prob.K, prob.N
     Q = sol.upload(prob.Q0)
     work = sol.workspace(S)
@@ -156,7 +162,7 @@ def main():
                    "unknowns_per_slice": 3 * nodes, "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "kernel": f"stage_kernel<{N},{prob.nq1},false>",
+                     "kernel": kname,
                      "avg_launch_us": stage_ms * 1e3,
                      "algorithmic_bytes_per_launch": bytes_launch},
     }

@@ -63,6 +63,11 @@ extern "C" {
 
 #define WADG_MAX_N 4            /* degrees 1..4 are compiled in            */
 
+/* Stage-kernel variants (wadg_set_kernel). */
+#define WADG_KERNEL_AUTO 0      /* resident where it fits, else streamed      */
+#define WADG_KERNEL_STREAMED 1  /* geometry read from global memory per item */
+#define WADG_KERNEL_RESIDENT 2  /* geometry held in LDS per element group    */
+
 typedef struct wadg_ctx_s* wadg_ctx;
 
 /* Mesh and problem description.  All pointers are host memory, read during
@@ -204,6 +209,25 @@ int wadg_norms(wadg_ctx ctx, const double* A, const double* B, int32_t S, double
  * (bitwise).  Defaults: 8, 0.  Returns WADG_E_INVALID for
  * groups_per_tile < 1 or slices_per_tile < 0. */
 int wadg_set_schedule(wadg_ctx ctx, int32_t groups_per_tile, int32_t slices_per_tile);
+
+/* Tuning: which stage kernel runs (Section 5.4's volume, surface and update
+ * kernels, fused).  WADG_KERNEL_STREAMED launches one 128-thread workgroup
+ * per (slice, 64-element group) and reads the group's geometry from global
+ * memory for each; it follows wadg_set_schedule.  WADG_KERNEL_RESIDENT
+ * launches 256-thread workgroups that each hold one element group's
+ * geometry in LDS (up to 160 KiB) and sweep a range of its slices; it
+ * ignores wadg_set_schedule.  WADG_KERNEL_AUTO (default) takes the resident
+ * kernel wherever the geometry fits (FP64: N <= 2, or N = 3 with
+ * nq1 <= 5; the FP32-bulk propagator decides separately, with its smaller
+ * footprint).  All variants give bitwise-identical results.  Returns
+ * WADG_E_INVALID for an unknown value and WADG_E_UNSUPPORTED when the
+ * resident kernel is requested for an (N, nq1) whose FP64 geometry does
+ * not fit. */
+int wadg_set_kernel(wadg_ctx ctx, int32_t kernel);
+
+/* The kernel variant the stage launches of `ctx` use: for the FP64 path
+ * (fp32 == 0) or the FP32-bulk path (fp32 != 0).  kernel: host out. */
+int wadg_kernel_in_use(wadg_ctx ctx, int32_t fp32, int32_t* kernel);
 
 /* Static description of a status code; never NULL. */
 const char* wadg_status_string(int status);

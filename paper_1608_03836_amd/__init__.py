@@ -11,6 +11,7 @@ from .binding import (  # noqa: F401
     wadg_quadrature_points, wadg_geometry, wadg_create, wadg_destroy, wadg_state_doubles,
     wadg_workspace_bytes, wadg_rhs, wadg_integrate, wadg_workspace_bytes_fp32,
     wadg_integrate_fp32, wadg_parareal_workspace_bytes, wadg_parareal, wadg_norms, wadg_set_schedule,
-    wadg_status_string, wadg_last_error, MeshDesc, WadgError, tile_state, untile_state,
+    wadg_set_kernel, wadg_kernel_in_use, WADG_KERNEL_AUTO, WADG_KERNEL_STREAMED,
+    WADG_KERNEL_RESIDENT, wadg_status_string, wadg_last_error, MeshDesc, WadgError, tile_state, untile_state,
 )
 from .solver import Solver  # noqa: F401

@@ -25,6 +25,9 @@ WADG_E_UNSUPPORTED = -3
 WADG_E_DEVICE = -4
 WADG_E_NONFINITE = -5
 WADG_MAX_N = 4
+WADG_KERNEL_AUTO = 0
+WADG_KERNEL_STREAMED = 1
+WADG_KERNEL_RESIDENT = 2
 TILE_LANES = 64
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
@@ -80,6 +83,8 @@ def _load():
                                          ctypes.POINTER(ctypes.c_double), vp]),
         "wadg_norms": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, _c_double_p, vp]),
         "wadg_set_schedule": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32]),
+        "wadg_set_kernel": (ctypes.c_int, [vp, ctypes.c_int32]),
+        "wadg_kernel_in_use": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
         "wadg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "wadg_last_error": (ctypes.c_char_p, []),
     }
@@ -95,7 +100,8 @@ EXPORTED = ("wadg_quadrature_points", "wadg_geometry", "wadg_create", "wadg_dest
             "wadg_state_doubles", "wadg_workspace_bytes", "wadg_rhs", "wadg_integrate",
             "wadg_workspace_bytes_fp32", "wadg_integrate_fp32",
             "wadg_parareal_workspace_bytes", "wadg_parareal",
-            "wadg_norms", "wadg_set_schedule", "wadg_status_string", "wadg_last_error")
+            "wadg_norms", "wadg_set_schedule", "wadg_set_kernel", "wadg_kernel_in_use",
+            "wadg_status_string", "wadg_last_error")
 
 
 def _check(status):
@@ -248,6 +254,16 @@ def wadg_norms(ctx, A, B, S, stream=None, check_finite=True):
 
 def wadg_set_schedule(ctx, groups_per_tile, slices_per_tile=0):
     _check(LIB.wadg_set_schedule(ctx, int(groups_per_tile), int(slices_per_tile)))
+
+
+def wadg_set_kernel(ctx, kernel):
+    _check(LIB.wadg_set_kernel(ctx, int(kernel)))
+
+
+def wadg_kernel_in_use(ctx, fp32=False):
+    out = ctypes.c_int32()
+    _check(LIB.wadg_kernel_in_use(ctx, 1 if fp32 else 0, ctypes.byref(out)))
+    return out.value
 
 
 def wadg_status_string(status):

@@ -85,6 +85,8 @@ struct wadg_ctx_s {
   double tau_p = 1.0, tau_u = 1.0;
   int tile_groups = 8;   // schedule: element groups per tile
   int tile_slices = 0;   // slices per tile (0: all)
+  int kernel = WADG_KERNEL_AUTO;
+  int cus = 256;         // compute units of the device
   double* d_vol = nullptr;
   double* d_face = nullptr;
   float* d_vol32 = nullptr;      // geometry rounded to FP32 (FP32-bulk path)
@@ -129,6 +131,23 @@ int check_slices(wadg_ctx c, int32_t S) {
   const long long nEG = (c->K + wadg::kWave - 1) / wadg::kWave;
   if (nEG * (long long)S >= (1LL << 31)) return fail(WADG_E_INVALID, "too many slices");
   return WADG_OK;
+}
+
+// Kernel variant that runs for this context and precision.
+int kernel_path(wadg_ctx c, bool fp32) {
+  const bool fits = wadg::resident_supported(c->N, c->nq1, fp32);
+  if (c->kernel == WADG_KERNEL_STREAMED || !fits) return WADG_KERNEL_STREAMED;
+  return WADG_KERNEL_RESIDENT;
+}
+
+int launch_stage(wadg_ctx c, bool rhs, bool fp32, const wadg::StageParams& p, void* stream) {
+  if (kernel_path(c, fp32) == WADG_KERNEL_RESIDENT) {
+    const int ranges = wadg::resident_ranges(p.nEG, p.S, c->cus);
+    return fp32 ? wadg::launch_stage_resident_fp32(c->N, c->nq1, p, ranges, stream)
+                : wadg::launch_stage_resident(c->N, c->nq1, rhs, p, ranges, stream);
+  }
+  return fp32 ? wadg::launch_stage_streamed_fp32(c->N, c->nq1, p, stream)
+              : wadg::launch_stage_streamed(c->N, c->nq1, rhs, p, stream);
 }
 
 wadg::StageParams base_params(wadg_ctx c, int32_t S) {
@@ -202,6 +221,10 @@ int wadg_create(const wadg_mesh* mesh, int32_t device, wadg_ctx* out) {
 
   wadg_ctx c = new wadg_ctx_s();
   c->device = dev;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      cus > 0)
+    c->cus = cus;
   c->N = mesh->N;
   c->nq1 = mesh->nq1;
   c->K = mesh->K;
@@ -260,6 +283,24 @@ int wadg_set_schedule(wadg_ctx ctx, int32_t groups_per_tile, int32_t slices_per_
   return WADG_OK;
 }
 
+int wadg_set_kernel(wadg_ctx ctx, int32_t kernel) {
+  if (!ctx) return fail(WADG_E_INVALID, "context is NULL");
+  if (kernel != WADG_KERNEL_AUTO && kernel != WADG_KERNEL_STREAMED &&
+      kernel != WADG_KERNEL_RESIDENT)
+    return fail(WADG_E_INVALID, "unknown kernel variant");
+  if (kernel == WADG_KERNEL_RESIDENT && !wadg::resident_supported(ctx->N, ctx->nq1, false))
+    return fail(WADG_E_UNSUPPORTED, "the element group's geometry does not fit in LDS");
+  ctx->kernel = kernel;
+  return WADG_OK;
+}
+
+int wadg_kernel_in_use(wadg_ctx ctx, int32_t fp32, int32_t* kernel) {
+  if (!ctx) return fail(WADG_E_INVALID, "context is NULL");
+  if (!kernel) return fail(WADG_E_INVALID, "kernel is NULL");
+  *kernel = kernel_path(ctx, fp32 != 0);
+  return WADG_OK;
+}
+
 int wadg_rhs(wadg_ctx ctx, const double* Q, double* dQdt, int32_t S, void* stream) {
   int st = check_slices(ctx, S);
   if (st) return st;
@@ -272,7 +313,7 @@ int wadg_rhs(wadg_ctx ctx, const double* Q, double* dQdt, int32_t S, void* strea
   p.Qin = Q;
   p.Qout = dQdt;
   p.res = nullptr;
-  int e = wadg::launch_stage(ctx->N, ctx->nq1, true, p, stream);
+  int e = launch_stage(ctx, true, false, p, stream);
   if (e) return hip_fail((hipError_t)e, "stage kernel launch");
   return WADG_OK;
 }
@@ -302,7 +343,7 @@ int wadg_integrate(wadg_ctx ctx, double* Q, double* work, int32_t S, double dt, 
       p.Qout = (cur == Q) ? other : Q;
       p.rkA = kRkA[i];
       p.rkB = kRkB[i];
-      int e = wadg::launch_stage(ctx->N, ctx->nq1, false, p, stream);
+      int e = launch_stage(ctx, false, false, p, stream);
       if (e) return hip_fail((hipError_t)e, "stage kernel launch");
       cur = static_cast<double*>(p.Qout);
     }
@@ -350,7 +391,7 @@ int wadg_integrate_fp32(wadg_ctx ctx, double* Q, void* work, int32_t S, double d
       p.Qout = (cur == q0) ? q1 : q0;
       p.rkA = kRkA[i];
       p.rkB = kRkB[i];
-      e = wadg::launch_stage_fp32(ctx->N, ctx->nq1, p, stream);
+      e = launch_stage(ctx, false, true, p, stream);
       if (e) return hip_fail((hipError_t)e, "stage kernel launch");
       cur = static_cast<float*>(p.Qout);
     }

@@ -1,4 +1,4 @@
-// Fused WADG stage kernel for gfx950.
+// Fused WADG stage kernel for gfx950, streamed-geometry variant.
 //
 // One LSRK stage of the WADG acoustic sweep for S slices at once, or one
 // right-hand-side evaluation, in arithmetic type R (double; float for the
@@ -11,26 +11,26 @@
 // every reference-operator entry is wave-uniform: the 1D tables are
 // compile-time constants folded into the instruction stream.
 //
+// This variant reads the geometry of its element group from global memory
+// (L2-resident, shared by all slices) for every work item.  It serves every
+// (N, nq) the library supports; where the group's geometry fits in LDS, the
+// resident-geometry kernel is used instead (resident_kernel.hip).
+//
 // The group's input tile (3 (N+1)^2 x 64 values) is first copied into LDS
-// by both waves with 16-byte coalesced loads, so every first-touch HBM read
-// of the stage is in flight at once; the waves then re-read their own nodal
-// values from LDS (lane-contiguous, conflict-free) instead of keeping them
-// in registers.  Per lane:
+// with 16-byte coalesced loads; the waves then re-read their own nodal
+// values from LDS (lane-contiguous, conflict-free).  Every global operand
+// is requested one phase ahead of its use: the metric terms of volume
+// column i+1 during column i, the first face's operands during the last
+// volume column, face f+1's during face f, and the mass-inverse weights
+// and the first residual during the last face; the neighbour offsets and
+// volume column 0 are requested with the tile.  Per lane:
 //
 //   a1  own face nodes (LDS) and the neighbours' face nodes (gathered from
 //       the input slice through precomputed offsets, flip-aware),
 //       interpolated to the face Gauss points;
-//   a2  volume term of the strong-weak form (Section 4.1; Section 5.4,
-//       volume kernel): u, v (pressure wave) or grad p (velocity wave) at the
-//       volume Gauss points through the tensor factors of V_q, V_q^r, V_q^s,
-//       times the weighted metric terms, and back to the nodes through the
-//       transposed factors -- one quadrature column at a time, with the next
-//       column's metric terms loaded while the current one is computed;
-//   a3  penalised numerical flux and its lift (Section 5.4, surface kernel;
-//       with GLL nodes the lift of face f touches only that face's nodes);
-//   a4  weight-adjusted mass inverse P_q diag(w_q) V_q (Section 5.2, the
-//       matrix-free product; w = c2/J for p and 1/J for u, v, Section 6),
-//       with Mhat^{-1} folded into the first factor (V_q Mhat^{-1});
+//   a2  volume term of the strong-weak form;
+//   a3  penalised numerical flux and its lift;
+//   a4  weight-adjusted mass inverse;
 //   a5  the 2N-storage stage update res <- A res + dt dQ, Q <- Q + B res,
 //       reading Q from one buffer and writing the other, so that neighbour
 //       gathers never see a partly updated state.
@@ -44,66 +44,12 @@
 
 #include <hip/hip_runtime.h>
 
-#include "reference_tables.h"
-#include "wadg_internal.h"
+#include "stage_common.h"
 
 namespace wadg {
 namespace {
 
-// Memory access through buffer resources: the base address and size of an
-// array live in four scalar registers, the per-plane offset (node, field,
-// quadrature point -- wave-uniform) in the instruction's offset fields, and
-// the per-lane offset in one vector register shared by every access to the
-// same tile.  Accesses outside the resource return zero instead of faulting.
-using rsrc_t = __amdgpu_buffer_rsrc_t;
-typedef unsigned int u32x2 __attribute__((vector_size(8)));
-typedef unsigned int u32x4 __attribute__((vector_size(16)));
-constexpr int kRsrcWord3 = 0x00020000;   // raw dword buffer, gfx9 family
-
-__device__ __forceinline__ rsrc_t make_rsrc(const void* base, unsigned bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
-                                           kRsrcWord3);
-}
-__device__ __forceinline__ void ld(rsrc_t r, unsigned voff, unsigned soff, double& v) {
-  v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
-}
-__device__ __forceinline__ void ld(rsrc_t r, unsigned voff, unsigned soff, float& v) {
-  v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
-}
-template <typename R>
-__device__ __forceinline__ R ldr(rsrc_t r, unsigned voff, unsigned soff) {
-  R v;
-  ld(r, voff, soff, v);
-  return v;
-}
-__device__ __forceinline__ void st(rsrc_t r, unsigned voff, unsigned soff, double v) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
-}
-__device__ __forceinline__ void st(rsrc_t r, unsigned voff, unsigned soff, float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
-}
-__device__ __forceinline__ int ldi(rsrc_t r, unsigned voff, unsigned soff) {
-  return (int)__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
-}
-
-// Compiler-only barriers (no instructions are emitted).  order() keeps memory
-// operations on their side of it, so a column's prefetches are issued before
-// the previous column's arithmetic and LDS re-reads are not hoisted;
-// pin(a) forces the values of `a` to be computed at that point, so the
-// arithmetic of a quadrature column or face is not sunk towards the final
-// stores (which would keep every loaded operand live to the end).
-__device__ __forceinline__ void order() { asm volatile("" ::: "memory"); }
-template <typename R, int M>
-__device__ __forceinline__ void pin(R (&a)[M]) {
-#pragma unroll
-  for (int i = 0; i < M; ++i) asm volatile("" : "+v"(a[i]));
-}
-
-// local node index of face node m (face parameter order) on face f
-template <int N>
-__device__ constexpr int fnode(int f, int m) {
-  return f == 0 ? m : f == 1 ? (N + (N + 1) * m) : f == 2 ? (m + (N + 1) * N) : ((N + 1) * m);
-}
+using namespace dev;
 
 // Buffer resources of one workgroup: the group's tiles of the state arrays
 // and of the geometry, and the whole input slice for neighbour gathers.
@@ -111,351 +57,128 @@ struct Bufs {
   rsrc_t qin, qout, res, qslice, vol, face, nbr;
 };
 
-// Stage-wide constants of one launch.
-template <typename R>
-struct StageScalars {
-  R tau_p, tau_u, A, B, dt;
+// The NQ^2 weights of the weight-adjusted inverse (geometry plane `wplane`).
+template <typename R, int NQ>
+__device__ __forceinline__ void load_weights(const Bufs& B, unsigned wplane, unsigned kb,
+                                             R (&w)[NQ * NQ]) {
+  constexpr unsigned KP = kWave * sizeof(R);
+#pragma unroll
+  for (int q = 0; q < NQ * NQ; ++q) w[q] = ldr<R>(B.vol, kb, (wplane + q) * KP);
+}
+
+// Operands of one face: the neighbour's trace and the face geometry at the
+// face Gauss points.
+template <typename R, int N, int NQ>
+struct FaceData {
+  Trace<R, N> t;
+  R g[3][NQ];   // nx, ny, w sJ
 };
 
-// dq = P_q diag(w) (V_q Mhat^{-1}) b in tensor form; w at the volume points
-// (planes wplane .. wplane + NQ^2 of the geometry tile).
 template <typename R, int N, int NQ>
-__device__ __forceinline__ void wadg_inverse(const R (&b)[(N + 1) * (N + 1)], const Bufs& B,
-                                             unsigned wplane, unsigned kb,
-                                             R (&dq)[(N + 1) * (N + 1)]) {
-  constexpr ct::Ops<R, N, NQ> T = ct::make_ops<R, N, NQ>();
-  constexpr int NP1 = N + 1;
+__device__ __forceinline__ void load_face(const Bufs& B, const NbrOffsets& o, int f,
+                                          unsigned kb, FaceData<R, N, NQ>& d) {
   constexpr unsigned KP = kWave * sizeof(R);
-#pragma unroll
-  for (int n = 0; n < NP1 * NP1; ++n) dq[n] = R(0);
-  R wc[NQ], wn[NQ];
-#pragma unroll
-  for (int j = 0; j < NQ; ++j) wc[j] = ldr<R>(B.vol, kb, (wplane + NQ * j) * KP);
-#pragma unroll
-  for (int i = 0; i < NQ; ++i) {
-    if (i + 1 < NQ) {
-#pragma unroll
-      for (int j = 0; j < NQ; ++j) wn[j] = ldr<R>(B.vol, kb, (wplane + i + 1 + NQ * j) * KP);
-    }
-    order();
-    R t[NP1];
-#pragma unroll
-    for (int bb = 0; bb < NP1; ++bb) {
-      R acc = R(0);
-#pragma unroll
-      for (int a = 0; a < NP1; ++a) acc += T.Vt[i][a] * b[a + NP1 * bb];
-      t[bb] = acc;
-    }
-    R c[NP1];
-#pragma unroll
-    for (int bb = 0; bb < NP1; ++bb) c[bb] = R(0);
-#pragma unroll
-    for (int j = 0; j < NQ; ++j) {
-      R rq = R(0);
-#pragma unroll
-      for (int bb = 0; bb < NP1; ++bb) rq += T.Vt[j][bb] * t[bb];
-      rq *= wc[j];
-#pragma unroll
-      for (int bb = 0; bb < NP1; ++bb) c[bb] += T.P[bb][j] * rq;
-    }
-#pragma unroll
-    for (int bb = 0; bb < NP1; ++bb)
-#pragma unroll
-      for (int a = 0; a < NP1; ++a) dq[a + NP1 * bb] += T.P[a][i] * c[bb];
-    pin(dq);
-#pragma unroll
-    for (int j = 0; j < NQ; ++j) wc[j] = wn[j];
-  }
-}
-
-// a5 for field c: res <- A res + dt dq; Qout <- Qin + B res  (or dQ/dt).
-// `resv` holds the residual prefetched before the WADG product.
-template <typename R, int NP, bool RHS>
-__device__ __forceinline__ void finish_field(const StageScalars<R>& k, const Bufs& B,
-                                             const R* tq, int c, unsigned kb, int lane,
-                                             bool active, const R (&resv)[NP],
-                                             const R (&dq)[NP]) {
-  constexpr unsigned KP = kWave * sizeof(R);
-  if (!active) return;
-  if constexpr (RHS) {
-#pragma unroll
-    for (int n = 0; n < NP; ++n) st(B.qout, kb, (c * NP + n) * KP, dq[n]);
-  } else {
-#pragma unroll
-    for (int n = 0; n < NP; ++n) {
-      const unsigned so = (c * NP + n) * KP;
-      const R r = k.A * resv[n] + k.dt * dq[n];
-      st(B.res, kb, so, r);
-      st(B.qout, kb, so, tq[(c * NP + n) * kWave + lane] + k.B * r);
-    }
-  }
-}
-
-// Residual of field c, read before the WADG product so that its latency
-// overlaps the arithmetic; not read at all when A = 0 (first stage).
-template <typename R, int NP, bool RHS>
-__device__ __forceinline__ void load_res(const StageScalars<R>& k, const Bufs& B, int c,
-                                         unsigned kb, R (&resv)[NP]) {
-  constexpr unsigned KP = kWave * sizeof(R);
-  if constexpr (!RHS) {
-    if (k.A != R(0)) {
-#pragma unroll
-      for (int n = 0; n < NP; ++n) resv[n] = ldr<R>(B.res, kb, (c * NP + n) * KP);
-      return;
-    }
-  }
-#pragma unroll
-  for (int n = 0; n < NP; ++n) resv[n] = R(0);
-}
-
-// Neighbour face nodes of face f (in my face's parameter order) and the
-// face geometry at the face's Gauss points.
-template <typename R, int N, int NQ>
-__device__ __forceinline__ void face_data(const Bufs& B, int f, unsigned kb, R (&pn)[N + 1],
-                                          R (&un)[N + 1], R (&vn)[N + 1], R (&fg)[3][NQ]) {
-  constexpr int NP = (N + 1) * (N + 1);
-  constexpr unsigned KP = kWave * sizeof(R);
-  // offset (in values, within the slice) of the neighbour's value at my
-  // face node 0, and the step along my face parameter
-  const unsigned nb0 = (unsigned)ldi(B.nbr, kb / sizeof(R) * 4, (0 * 4 + f) * kWave * 4);
-  const int nstep = ldi(B.nbr, kb / sizeof(R) * 4, (1 * 4 + f) * kWave * 4);
-#pragma unroll
-  for (int m = 0; m <= N; ++m) {
-    const unsigned off = (nb0 + (unsigned)(nstep * m)) * sizeof(R);
-    pn[m] = ldr<R>(B.qslice, off, 0);
-    un[m] = ldr<R>(B.qslice, off, NP * KP);
-    vn[m] = ldr<R>(B.qslice, off, 2 * NP * KP);
-  }
+  gather_trace<R, N>(B.qslice, o, f, d.t);
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int j = 0; j < NQ; ++j) fg[c][j] = ldr<R>(B.face, kb, (c * 4 * NQ + f * NQ + j) * KP);
+    for (int j = 0; j < NQ; ++j) d.g[c][j] = ldr<R>(B.face, kb, (c * 4 * NQ + f * NQ + j) * KP);
 }
 
-// Pressure equation: b_p = int u.grad(v) J - int 1/2(2{u}.n - tau_p [p]) v sJ.
-template <typename R, int N, int NQ, bool RHS>
-__device__ __forceinline__ void pressure_wave(const StageScalars<R>& k, const Bufs& B,
-                                              const R* tq, unsigned kb, int lane, bool active) {
-  constexpr ct::Ops<R, N, NQ> T = ct::make_ops<R, N, NQ>();
-  constexpr int NP1 = N + 1, NP = NP1 * NP1, NQ2 = NQ * NQ;
+// Metric planes 0..3 (W ys, -W xs, -W yr, W xr) of volume column i.
+template <typename R, int NQ>
+__device__ __forceinline__ void load_metric_column(const Bufs& B, int i, unsigned kb,
+                                                   R (&g)[4][NQ]) {
   constexpr unsigned KP = kWave * sizeof(R);
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) g[p][j] = ldr<R>(B.vol, kb, (p * NQ * NQ + i + NQ * j) * KP);
+}
+
+// One wave's share of a work item: the pressure equation (wave 0) or the two
+// velocity equations (wave 1).
+template <typename R, int N, int NQ, bool RHS, bool PRESSURE>
+__device__ __forceinline__ void stage_wave(const StageScalars<R>& k, const Bufs& B, const R* tq,
+                                           unsigned kb, int lane, bool active,
+                                           const NbrOffsets& nbo, const R (&g0)[4][NQ]) {
+  constexpr int NP1 = N + 1, NP = NP1 * NP1, NQ2 = NQ * NQ;
+  auto P = [&](int n) { return tq[n * kWave + lane]; };
   auto U = [&](int n) { return tq[(NP + n) * kWave + lane]; };
   auto V = [&](int n) { return tq[(2 * NP + n) * kWave + lane]; };
-  auto P = [&](int n) { return tq[n * kWave + lane]; };
 
-  R bp[NP];
+  R b0[NP], b1[NP];   // pressure: b0; velocity: b0 = b_u, b1 = b_v
 #pragma unroll
-  for (int n = 0; n < NP; ++n) bp[n] = R(0);
+  for (int n = 0; n < NP; ++n) b0[n] = b1[n] = R(0);
+  FaceData<R, N, NQ> fd[2];
 
-  // a2: sum_q w_q J (l_r (Jr_x u + Jr_y v) + l_s (Js_x u + Js_y v))
+  // a2, metric terms one column ahead
   R gc[4][NQ], gn[4][NQ];
 #pragma unroll
   for (int g = 0; g < 4; ++g)
 #pragma unroll
-    for (int j = 0; j < NQ; ++j) gc[g][j] = ldr<R>(B.vol, kb, (g * NQ2 + NQ * j) * KP);
+    for (int j = 0; j < NQ; ++j) gc[g][j] = g0[g][j];
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
+    if (i + 1 < NQ)
+      load_metric_column<R, NQ>(B, i + 1, kb, gn);
+    else
+      load_face<R, N, NQ>(B, nbo, 0, kb, fd[0]);
+    order();
+    if constexpr (PRESSURE) {
+      pressure_volume_column<R, N, NQ>(i, U, V, gc, b0);
+      pin(b0);
+    } else {
+      velocity_volume_column<R, N, NQ>(i, P, gc, b0, b1);
+      pin(b0);
+      pin(b1);
+    }
     if (i + 1 < NQ) {
 #pragma unroll
       for (int g = 0; g < 4; ++g)
 #pragma unroll
-        for (int j = 0; j < NQ; ++j) gn[g][j] = ldr<R>(B.vol, kb, (g * NQ2 + i + 1 + NQ * j) * KP);
+        for (int j = 0; j < NQ; ++j) gc[g][j] = gn[g][j];
     }
-    order();
-    R tu[NP1], tv[NP1];
-#pragma unroll
-    for (int bb = 0; bb < NP1; ++bb) {
-      R su = R(0), sv = R(0);
-#pragma unroll
-      for (int a = 0; a < NP1; ++a) {
-        su += T.V[i][a] * U(a + NP1 * bb);
-        sv += T.V[i][a] * V(a + NP1 * bb);
-      }
-      tu[bb] = su;
-      tv[bb] = sv;
-    }
-    R cr[NP1], cs[NP1];
-#pragma unroll
-    for (int bb = 0; bb < NP1; ++bb) cr[bb] = cs[bb] = R(0);
-#pragma unroll
-    for (int j = 0; j < NQ; ++j) {
-      R uq = R(0), vq = R(0);
-#pragma unroll
-      for (int bb = 0; bb < NP1; ++bb) {
-        uq += T.V[j][bb] * tu[bb];
-        vq += T.V[j][bb] * tv[bb];
-      }
-      const R Ur = gc[0][j] * uq + gc[1][j] * vq;
-      const R Us = gc[2][j] * uq + gc[3][j] * vq;
-#pragma unroll
-      for (int bb = 0; bb < NP1; ++bb) {
-        cr[bb] += T.V[j][bb] * Ur;
-        cs[bb] += T.D[j][bb] * Us;
-      }
-    }
-#pragma unroll
-    for (int bb = 0; bb < NP1; ++bb)
-#pragma unroll
-      for (int a = 0; a < NP1; ++a) bp[a + NP1 * bb] += T.D[i][a] * cr[bb] + T.V[i][a] * cs[bb];
-    pin(bp);
-#pragma unroll
-    for (int g = 0; g < 4; ++g)
-#pragma unroll
-      for (int j = 0; j < NQ; ++j) gc[g][j] = gn[g][j];
   }
 
-  // a1 + a3
+  // a1 + a3, face operands one face ahead
+  R w[NQ2], resv[NP];
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
-    order();
-    R pn[NP1], un[NP1], vn[NP1], fg[3][NQ];
-    face_data<R, N, NQ>(B, f, kb, pn, un, vn, fg);
-#pragma unroll
-    for (int j = 0; j < NQ; ++j) {
-      R pm = R(0), um = R(0), vm = R(0), pp = R(0), up = R(0), vp = R(0);
-#pragma unroll
-      for (int m = 0; m < NP1; ++m) {
-        pm += T.V[j][m] * P(fnode<N>(f, m));
-        um += T.V[j][m] * U(fnode<N>(f, m));
-        vm += T.V[j][m] * V(fnode<N>(f, m));
-        pp += T.V[j][m] * pn[m];
-        up += T.V[j][m] * un[m];
-        vp += T.V[j][m] * vn[m];
-      }
-      const R nx = fg[0][j], ny = fg[1][j], wsJ = fg[2][j];
-      const R fp = R(0.5) * wsJ * ((up + um) * nx + (vp + vm) * ny - k.tau_p * (pp - pm));
-#pragma unroll
-      for (int m = 0; m < NP1; ++m) bp[fnode<N>(f, m)] -= T.V[j][m] * fp;
-    }
-    pin(bp);
-  }
-
-  // a4 + a5
-  order();
-  R resv[NP], dq[NP];
-  load_res<R, NP, RHS>(k, B, 0, kb, resv);
-  wadg_inverse<R, N, NQ>(bp, B, 4 * NQ2, kb, dq);
-  finish_field<R, NP, RHS>(k, B, tq, 0, kb, lane, active, resv, dq);
-}
-
-// Velocity equations: b_u = -int grad(p) . tau J - int 1/2([p] - tau_u [u].n) tau.n sJ.
-template <typename R, int N, int NQ, bool RHS>
-__device__ __forceinline__ void velocity_wave(const StageScalars<R>& k, const Bufs& B,
-                                              const R* tq, unsigned kb, int lane, bool active) {
-  constexpr ct::Ops<R, N, NQ> T = ct::make_ops<R, N, NQ>();
-  constexpr int NP1 = N + 1, NP = NP1 * NP1, NQ2 = NQ * NQ;
-  constexpr unsigned KP = kWave * sizeof(R);
-  auto U = [&](int n) { return tq[(NP + n) * kWave + lane]; };
-  auto V = [&](int n) { return tq[(2 * NP + n) * kWave + lane]; };
-  auto P = [&](int n) { return tq[n * kWave + lane]; };
-
-  R bu[NP], bv[NP];
-#pragma unroll
-  for (int n = 0; n < NP; ++n) bu[n] = bv[n] = R(0);
-
-  // a2: -sum_q w_q J l (p_x, p_y)
-  R gc[4][NQ], gn[4][NQ];
-#pragma unroll
-  for (int g = 0; g < 4; ++g)
-#pragma unroll
-    for (int j = 0; j < NQ; ++j) gc[g][j] = ldr<R>(B.vol, kb, (g * NQ2 + NQ * j) * KP);
-#pragma unroll
-  for (int i = 0; i < NQ; ++i) {
-    if (i + 1 < NQ) {
-#pragma unroll
-      for (int g = 0; g < 4; ++g)
-#pragma unroll
-        for (int j = 0; j < NQ; ++j) gn[g][j] = ldr<R>(B.vol, kb, (g * NQ2 + i + 1 + NQ * j) * KP);
+    if (f + 1 < 4) {
+      load_face<R, N, NQ>(B, nbo, f + 1, kb, fd[(f + 1) & 1]);
+    } else {
+      load_weights<R, NQ>(B, (PRESSURE ? 4 : 5) * NQ2, kb, w);
+      load_res<R, NP, RHS>(k, B.res, PRESSURE ? 0 : 1, kb, resv);
     }
     order();
-    R td[NP1], tp[NP1];
-#pragma unroll
-    for (int bb = 0; bb < NP1; ++bb) {
-      R sd = R(0), sp = R(0);
-#pragma unroll
-      for (int a = 0; a < NP1; ++a) {
-        const R pa = P(a + NP1 * bb);
-        sd += T.D[i][a] * pa;
-        sp += T.V[i][a] * pa;
-      }
-      td[bb] = sd;
-      tp[bb] = sp;
+    const FaceData<R, N, NQ>& d = fd[f & 1];
+    if constexpr (PRESSURE) {
+      pressure_face<R, N, NQ>(f, P, U, V, d.t, d.g, k.tau_p, b0);
+      pin(b0);
+    } else {
+      velocity_face<R, N, NQ>(f, P, U, V, d.t, d.g, k.tau_u, b0, b1);
+      pin(b0);
+      pin(b1);
     }
-    R cx[NP1], cy[NP1];
-#pragma unroll
-    for (int bb = 0; bb < NP1; ++bb) cx[bb] = cy[bb] = R(0);
-#pragma unroll
-    for (int j = 0; j < NQ; ++j) {
-      R pr = R(0), ps = R(0);
-#pragma unroll
-      for (int bb = 0; bb < NP1; ++bb) {
-        pr += T.V[j][bb] * td[bb];
-        ps += T.D[j][bb] * tp[bb];
-      }
-      const R Gx = gc[0][j] * pr + gc[2][j] * ps;
-      const R Gy = gc[1][j] * pr + gc[3][j] * ps;
-#pragma unroll
-      for (int bb = 0; bb < NP1; ++bb) {
-        cx[bb] += T.V[j][bb] * Gx;
-        cy[bb] += T.V[j][bb] * Gy;
-      }
-    }
-#pragma unroll
-    for (int bb = 0; bb < NP1; ++bb)
-#pragma unroll
-      for (int a = 0; a < NP1; ++a) {
-        bu[a + NP1 * bb] -= T.V[i][a] * cx[bb];
-        bv[a + NP1 * bb] -= T.V[i][a] * cy[bb];
-      }
-    pin(bu);
-    pin(bv);
-#pragma unroll
-    for (int g = 0; g < 4; ++g)
-#pragma unroll
-      for (int j = 0; j < NQ; ++j) gc[g][j] = gn[g][j];
   }
 
-  // a1 + a3
-#pragma unroll
-  for (int f = 0; f < 4; ++f) {
+  // a4 + a5; the velocity wave reuses the weights (1/J) for both fields and
+  // requests the second residual before the first field's stores
+  order();
+  R dq[NP];
+  wadg_inverse<R, N, NQ>(b0, w, dq);
+  if constexpr (PRESSURE) {
+    finish_field<R, NP, RHS>(k, B.qout, B.res, P, 0, kb, active, resv, dq);
+  } else {
+    R resv2[NP];
+    load_res<R, NP, RHS>(k, B.res, 2, kb, resv2);
     order();
-    R pn[NP1], un[NP1], vn[NP1], fg[3][NQ];
-    face_data<R, N, NQ>(B, f, kb, pn, un, vn, fg);
-#pragma unroll
-    for (int j = 0; j < NQ; ++j) {
-      R pm = R(0), um = R(0), vm = R(0), pp = R(0), up = R(0), vp = R(0);
-#pragma unroll
-      for (int m = 0; m < NP1; ++m) {
-        pm += T.V[j][m] * P(fnode<N>(f, m));
-        um += T.V[j][m] * U(fnode<N>(f, m));
-        vm += T.V[j][m] * V(fnode<N>(f, m));
-        pp += T.V[j][m] * pn[m];
-        up += T.V[j][m] * un[m];
-        vp += T.V[j][m] * vn[m];
-      }
-      const R nx = fg[0][j], ny = fg[1][j], wsJ = fg[2][j];
-      const R fu = R(0.5) * wsJ * ((pp - pm) - k.tau_u * ((up - um) * nx + (vp - vm) * ny));
-      const R fx = fu * nx, fy = fu * ny;
-#pragma unroll
-      for (int m = 0; m < NP1; ++m) {
-        bu[fnode<N>(f, m)] -= T.V[j][m] * fx;
-        bv[fnode<N>(f, m)] -= T.V[j][m] * fy;
-      }
-    }
-    pin(bu);
-    pin(bv);
+    finish_field<R, NP, RHS>(k, B.qout, B.res, P, 1, kb, active, resv, dq);
+    order();
+    wadg_inverse<R, N, NQ>(b1, w, dq);
+    finish_field<R, NP, RHS>(k, B.qout, B.res, P, 2, kb, active, resv2, dq);
   }
-
-  // a4 + a5, one field at a time
-  order();
-  R resv[NP], dq[NP];
-  load_res<R, NP, RHS>(k, B, 1, kb, resv);
-  wadg_inverse<R, N, NQ>(bu, B, 5 * NQ2, kb, dq);
-  finish_field<R, NP, RHS>(k, B, tq, 1, kb, lane, active, resv, dq);
-  order();
-  load_res<R, NP, RHS>(k, B, 2, kb, resv);
-  wadg_inverse<R, N, NQ>(bv, B, 5 * NQ2, kb, dq);
-  finish_field<R, NP, RHS>(k, B, tq, 2, kb, lane, active, resv, dq);
 }
 
 }  // namespace
@@ -468,12 +191,7 @@ __global__ __launch_bounds__(2 * kWave) void stage_kernel(const StageParams p) {
   constexpr unsigned KP = kWave * sizeof(R);
   __shared__ __attribute__((aligned(16))) R tq[tile];
 
-  // workgroup -> work item (XCD-aware): XCD x = bid % 8 receives the
-  // contiguous logical range [x q8 + min(x, r8), ...) in launch order
-  const int nb = gridDim.x, bid = blockIdx.x;
-  const int q8 = nb >> 3, r8 = nb & 7;
-  const int xcd = bid & 7, jx = bid >> 3;
-  const int w = xcd * q8 + (xcd < r8 ? xcd : r8) + jx;
+  const int w = xcd_remap(blockIdx.x, gridDim.x);
   // work item -> (slice, element group): tiles of Be element groups x Bs
   // slices, ordered (slice block, element block), slice-major inside a tile
   const int Be = p.tile_groups, Bs = p.tile_slices, nEG = p.nEG;
@@ -502,27 +220,36 @@ __global__ __launch_bounds__(2 * kWave) void stage_kernel(const StageParams p) {
                      12u * NQ * KP);
   B.nbr = make_rsrc(p.nbr + (size_t)eg * 8 * kWave, 8u * kWave * 4u);
 
-  // stage the input tile in LDS: 16-byte chunks, consecutive threads on
-  // consecutive chunks
+  // stage the input tile in LDS (16-byte chunks, consecutive threads on
+  // consecutive chunks); the neighbour offsets and the metric terms of
+  // volume column 0 are requested while the tile is in flight
   constexpr unsigned chunks = tile * sizeof(R) / 16;
-  for (unsigned c = tid; c < chunks; c += 2 * kWave) {
-    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(B.qin, c * 16u, 0, 0);
-    *reinterpret_cast<u32x4*>(reinterpret_cast<char*>(tq) + c * 16u) = v;
+  constexpr unsigned per_thread = (chunks + 2 * kWave - 1) / (2 * kWave);
+  u32x4 v[per_thread];
+#pragma unroll
+  for (unsigned i = 0; i < per_thread; ++i) {
+    const unsigned c = tid + i * 2 * kWave;
+    if (c < chunks) v[i] = ld128(B.qin, c * 16u);
+  }
+  const unsigned kb = (unsigned)lane * sizeof(R);
+  NbrOffsets nbo;
+  load_nbr(B.nbr, lane, nbo);
+  R g0[4][NQ];
+  load_metric_column<R, NQ>(B, 0, kb, g0);
+  order();
+#pragma unroll
+  for (unsigned i = 0; i < per_thread; ++i) {
+    const unsigned c = tid + i * 2 * kWave;
+    if (c < chunks) *reinterpret_cast<u32x4*>(reinterpret_cast<char*>(tq) + c * 16u) = v[i];
   }
   __syncthreads();
 
-  StageScalars<R> k;
-  k.tau_p = (R)p.tau_p;
-  k.tau_u = (R)p.tau_u;
-  k.A = (R)p.rkA;
-  k.B = (R)p.rkB;
-  k.dt = (R)p.dt;
+  const StageScalars<R> k = stage_scalars<R>(p);
   const bool active = eg * kWave + lane < p.K;
-  const unsigned kb = (unsigned)lane * sizeof(R);
   if (wave == 0)
-    pressure_wave<R, N, NQ, RHS>(k, B, tq, kb, lane, active);
+    stage_wave<R, N, NQ, RHS, true>(k, B, tq, kb, lane, active, nbo, g0);
   else
-    velocity_wave<R, N, NQ, RHS>(k, B, tq, kb, lane, active);
+    stage_wave<R, N, NQ, RHS, false>(k, B, tq, kb, lane, active, nbo, g0);
 }
 
 namespace {
@@ -563,11 +290,11 @@ int launch_r(int N, int nq, bool rhs, const StageParams& p, void* stream) {
 
 bool stage_supported(int N, int nq) { return N >= 1 && N <= 4 && nq >= N + 1 && nq <= N + 3; }
 
-int launch_stage(int N, int nq, bool rhs, const StageParams& p, void* stream) {
+int launch_stage_streamed(int N, int nq, bool rhs, const StageParams& p, void* stream) {
   return launch_r<double>(N, nq, rhs, p, stream);
 }
 
-int launch_stage_fp32(int N, int nq, const StageParams& p, void* stream) {
+int launch_stage_streamed_fp32(int N, int nq, const StageParams& p, void* stream) {
   return launch_r<float>(N, nq, false, p, stream);
 }
 

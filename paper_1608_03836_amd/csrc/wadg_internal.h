@@ -82,9 +82,20 @@ struct StageParams {
 
 // Launch one stage (rhs == false: LSRK stage update; rhs == true: write
 // dQ/dt to Qout).  Returns a hipError_t as int.
-int launch_stage(int N, int nq, bool rhs, const StageParams& p, void* stream);
+//
+// Streamed-geometry kernel: one workgroup per (slice, element group), the
+// group's geometry read from global memory; every supported (N, nq).
+int launch_stage_streamed(int N, int nq, bool rhs, const StageParams& p, void* stream);
 // The same LSRK stage in FP32 (arrays of float).
-int launch_stage_fp32(int N, int nq, const StageParams& p, void* stream);
+int launch_stage_streamed_fp32(int N, int nq, const StageParams& p, void* stream);
+// Resident-geometry kernel: one workgroup per (element group, slice range)
+// with the group's geometry held in LDS; grid = nEG * ranges.  Only where
+// resident_supported(N, nq, fp32).
+bool resident_supported(int N, int nq, bool fp32);
+int resident_ranges(int nEG, int S, int cus);
+int launch_stage_resident(int N, int nq, bool rhs, const StageParams& p, int ranges,
+                          void* stream);
+int launch_stage_resident_fp32(int N, int nq, const StageParams& p, int ranges, void* stream);
 // Elementwise precision conversion of n values (FP64 <-> FP32).
 int launch_to_fp32(const double* in, float* out, size_t n, void* stream);
 int launch_to_fp64(const float* in, double* out, size_t n, void* stream);

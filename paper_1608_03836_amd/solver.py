@@ -107,3 +107,10 @@ class Solver:
 
     def set_schedule(self, groups_per_tile, slices_per_tile=0):
         B.wadg_set_schedule(self.ctx, groups_per_tile, slices_per_tile)
+
+    def set_kernel(self, kernel):
+        """WADG_KERNEL_AUTO, _STREAMED or _RESIDENT (see wadg_set_kernel)."""
+        B.wadg_set_kernel(self.ctx, kernel)
+
+    def kernel_in_use(self, fp32=False):
+        return B.wadg_kernel_in_use(self.ctx, fp32)
