@@ -17,6 +17,9 @@ discontinuous Galerkin methods: curvilinear meshes"):
 * ``heat``    -- 1D periodic heat equation by second-order differences, a
                  method-of-lines system whose Fourier modes have closed forms.
 * ``parareal``-- serial-reference parareal iteration over time slices.
+* ``adjoint`` -- gradient of a terminal objective with respect to the start
+                 state and a wave-speed scale, by dense transposition and
+                 tangent-linear sensitivity (small meshes).
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  It shares no code with the HIP path:
@@ -35,3 +38,4 @@ from .lsrk import LSRK54, lsrk_integrate, stability_polynomial_coeffs  # noqa: F
 from .wadg import WADGOracle  # noqa: F401
 from .heat import heat_rhs, heat_integrate, heat_eigenvalues  # noqa: F401
 from .parareal import parareal, wadg_propagators  # noqa: F401
+from .adjoint import TerminalObjective, step_matrix, step_matrix_derivative  # noqa: F401
