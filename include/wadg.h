@@ -190,6 +190,41 @@ int wadg_parareal(wadg_ctx ctx, const double* y0, double* U, void* work, int32_t
                   int32_t nsteps_fine, int32_t nsteps_coarse, int32_t max_iter, double tol,
                   int32_t fine_fp32, int32_t* iterations, double* last_change, void* stream);
 
+/* Wave-speed scale: every later launch of `ctx` uses c^2 = scale * c2q (the
+ * c2q given to wadg_create).  c^2 enters the scheme only through the
+ * pressure mass weights c^2/J (Section 6), which are multiplied by `scale`.
+ * Default 1 (bitwise the unscaled scheme).  Returns WADG_E_INVALID unless
+ * scale is finite and > 0. */
+int wadg_set_c2_scale(wadg_ctx ctx, double scale);
+
+/* Discrete adjoint of the sweep of ONE trajectory (one slice of the state
+ * layout) over S consecutive time slices of nsteps LSRK steps each (the
+ * sensitivity problem: gradient of an objective of the final state).
+ *
+ * wadg_forward_checkpoints: chk (device, S+1 slices of the state layout):
+ *   chk[0] is the start state (in); chk[s+1] = chk[s] advanced by nsteps
+ *   steps of dt (out).  work: device, wadg_adjoint_workspace_bytes bytes.
+ *   Asynchronous on `stream`.
+ *
+ * wadg_adjoint: given chk from wadg_forward_checkpoints (same ctx, dt,
+ *   nsteps, c^2 scale) and seed = dJ/dq(T) (device, one slice), writes
+ *   grad = dJ/dq(0) (device, one slice; may alias seed) and the host scalar
+ *   dJ_dscale = gamma dJ/dgamma for c^2 = gamma c2q at the current scale
+ *   gamma.  It runs the reverse sweep of the 2N-storage LSRK recursion
+ *   (Section 4.2.1) with the transposed operator L^T = D A D Mtilde^{-1},
+ *   D = diag(1,-1,-1) (the strong-weak DG operator A of Section 4.1 has
+ *   skew p-u coupling and symmetric penalty blocks; Mtilde^{-1} is the
+ *   symmetric WADG inverse of Section 4), recomputing each slice's forward
+ *   states from its checkpoint.  Padding entries of seed must be zero; grad
+ *   padding is unspecified.  Synchronises `stream` once at the end.
+ *   Returns WADG_E_NONFINITE if dJ_dscale is not finite.  work must not
+ *   overlap chk, seed or grad. */
+int wadg_adjoint_workspace_bytes(wadg_ctx ctx, int32_t nsteps, size_t* bytes);
+int wadg_forward_checkpoints(wadg_ctx ctx, double* chk, void* work, int32_t S, double dt,
+                             int32_t nsteps, void* stream);
+int wadg_adjoint(wadg_ctx ctx, const double* chk, const double* seed, double* grad, void* work,
+                 int32_t S, double dt, int32_t nsteps, double* dJ_dscale, void* stream);
+
 /* Per-slice reductions (the norms the convergence checks use):
  *   out[s][0] = ||A_s - B_s||_2,  out[s][1] = ||B_s||_2,
  *   out[s][2] = max |A_s - B_s|,  out[s][3] = 1 if every A_s entry is finite

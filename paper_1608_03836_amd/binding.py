@@ -84,6 +84,12 @@ def _load():
         "wadg_norms": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, _c_double_p, vp]),
         "wadg_set_schedule": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32]),
         "wadg_set_kernel": (ctypes.c_int, [vp, ctypes.c_int32]),
+        "wadg_set_c2_scale": (ctypes.c_int, [vp, ctypes.c_double]),
+        "wadg_adjoint_workspace_bytes": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.POINTER(sz)]),
+        "wadg_forward_checkpoints": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, ctypes.c_double,
+                                                    ctypes.c_int32, vp]),
+        "wadg_adjoint": (ctypes.c_int, [vp, vp, vp, vp, vp, ctypes.c_int32, ctypes.c_double,
+                                        ctypes.c_int32, ctypes.POINTER(ctypes.c_double), vp]),
         "wadg_kernel_in_use": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
         "wadg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "wadg_last_error": (ctypes.c_char_p, []),
@@ -101,6 +107,8 @@ EXPORTED = ("wadg_quadrature_points", "wadg_geometry", "wadg_create", "wadg_dest
             "wadg_workspace_bytes_fp32", "wadg_integrate_fp32",
             "wadg_parareal_workspace_bytes", "wadg_parareal",
             "wadg_norms", "wadg_set_schedule", "wadg_set_kernel", "wadg_kernel_in_use",
+            "wadg_set_c2_scale", "wadg_adjoint_workspace_bytes", "wadg_forward_checkpoints",
+            "wadg_adjoint",
             "wadg_status_string", "wadg_last_error")
 
 
@@ -263,6 +271,29 @@ def wadg_set_kernel(ctx, kernel):
 def wadg_kernel_in_use(ctx, fp32=False):
     out = ctypes.c_int32()
     _check(LIB.wadg_kernel_in_use(ctx, 1 if fp32 else 0, ctypes.byref(out)))
+    return out.value
+
+
+def wadg_set_c2_scale(ctx, scale):
+    _check(LIB.wadg_set_c2_scale(ctx, float(scale)))
+
+
+def wadg_adjoint_workspace_bytes(ctx, nsteps):
+    out = ctypes.c_size_t()
+    _check(LIB.wadg_adjoint_workspace_bytes(ctx, int(nsteps), ctypes.byref(out)))
+    return out.value
+
+
+def wadg_forward_checkpoints(ctx, chk, work, S, dt, nsteps, stream=None):
+    _check(LIB.wadg_forward_checkpoints(ctx, _ptr(chk), _ptr(work), int(S), float(dt),
+                                        int(nsteps), _stream(stream)))
+
+
+def wadg_adjoint(ctx, chk, seed, grad, work, S, dt, nsteps, stream=None):
+    """Returns dJ_dscale (gamma dJ/dgamma); grad is written on the device."""
+    out = ctypes.c_double()
+    _check(LIB.wadg_adjoint(ctx, _ptr(chk), _ptr(seed), _ptr(grad), _ptr(work), int(S),
+                            float(dt), int(nsteps), ctypes.byref(out), _stream(stream)))
     return out.value
 
 

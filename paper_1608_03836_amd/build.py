@@ -14,8 +14,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libwadg.so")
 
-SOURCES = ["reference.cpp", "stage_kernel.hip", "resident_kernel.hip", "norms_kernel.hip",
-           "convert_kernel.hip", "parareal_kernel.hip", "api.hip"]
+SOURCES = ["reference.cpp", "stage_kernel.hip", "resident_kernel.hip", "adjoint_kernel.hip",
+           "norms_kernel.hip", "convert_kernel.hip", "parareal_kernel.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -87,6 +87,7 @@ struct wadg_ctx_s {
   int tile_slices = 0;   // slices per tile (0: all)
   int kernel = WADG_KERNEL_AUTO;
   int cus = 256;         // compute units of the device
+  double c2_scale = 1.0; // multiplies c^2 (wadg_set_c2_scale)
   double* d_vol = nullptr;
   double* d_face = nullptr;
   float* d_vol32 = nullptr;      // geometry rounded to FP32 (FP32-bulk path)
@@ -140,14 +141,14 @@ int kernel_path(wadg_ctx c, bool fp32) {
   return WADG_KERNEL_RESIDENT;
 }
 
-int launch_stage(wadg_ctx c, bool rhs, bool fp32, const wadg::StageParams& p, void* stream) {
-  if (kernel_path(c, fp32) == WADG_KERNEL_RESIDENT) {
+int launch_stage(wadg_ctx c, int mode, bool fp32, const wadg::StageParams& p, void* stream) {
+  if (mode != wadg::kApplyA && kernel_path(c, fp32) == WADG_KERNEL_RESIDENT) {
     const int ranges = wadg::resident_ranges(p.nEG, p.S, c->cus);
     return fp32 ? wadg::launch_stage_resident_fp32(c->N, c->nq1, p, ranges, stream)
-                : wadg::launch_stage_resident(c->N, c->nq1, rhs, p, ranges, stream);
+                : wadg::launch_stage_resident(c->N, c->nq1, mode, p, ranges, stream);
   }
   return fp32 ? wadg::launch_stage_streamed_fp32(c->N, c->nq1, p, stream)
-              : wadg::launch_stage_streamed(c->N, c->nq1, rhs, p, stream);
+              : wadg::launch_stage_streamed(c->N, c->nq1, mode, p, stream);
 }
 
 wadg::StageParams base_params(wadg_ctx c, int32_t S) {
@@ -162,6 +163,8 @@ wadg::StageParams base_params(wadg_ctx c, int32_t S) {
   p.tile_slices = (c->tile_slices == 0 || c->tile_slices > S) ? S : c->tile_slices;
   p.tau_p = c->tau_p;
   p.tau_u = c->tau_u;
+  p.c2_scale = c->c2_scale;
+  p.res_out = nullptr;
   return p;
 }
 
@@ -294,6 +297,14 @@ int wadg_set_kernel(wadg_ctx ctx, int32_t kernel) {
   return WADG_OK;
 }
 
+int wadg_set_c2_scale(wadg_ctx ctx, double scale) {
+  if (!ctx) return fail(WADG_E_INVALID, "context is NULL");
+  if (!(scale > 0.0) || !std::isfinite(scale))
+    return fail(WADG_E_INVALID, "the c^2 scale must be finite and > 0");
+  ctx->c2_scale = scale;
+  return WADG_OK;
+}
+
 int wadg_kernel_in_use(wadg_ctx ctx, int32_t fp32, int32_t* kernel) {
   if (!ctx) return fail(WADG_E_INVALID, "context is NULL");
   if (!kernel) return fail(WADG_E_INVALID, "kernel is NULL");
@@ -313,7 +324,7 @@ int wadg_rhs(wadg_ctx ctx, const double* Q, double* dQdt, int32_t S, void* strea
   p.Qin = Q;
   p.Qout = dQdt;
   p.res = nullptr;
-  int e = launch_stage(ctx, true, false, p, stream);
+  int e = launch_stage(ctx, wadg::kRhs, false, p, stream);
   if (e) return hip_fail((hipError_t)e, "stage kernel launch");
   return WADG_OK;
 }
@@ -343,7 +354,7 @@ int wadg_integrate(wadg_ctx ctx, double* Q, double* work, int32_t S, double dt, 
       p.Qout = (cur == Q) ? other : Q;
       p.rkA = kRkA[i];
       p.rkB = kRkB[i];
-      int e = launch_stage(ctx, false, false, p, stream);
+      int e = launch_stage(ctx, wadg::kStage, false, p, stream);
       if (e) return hip_fail((hipError_t)e, "stage kernel launch");
       cur = static_cast<double*>(p.Qout);
     }
@@ -391,7 +402,7 @@ int wadg_integrate_fp32(wadg_ctx ctx, double* Q, void* work, int32_t S, double d
       p.Qout = (cur == q0) ? q1 : q0;
       p.rkA = kRkA[i];
       p.rkB = kRkB[i];
-      e = launch_stage(ctx, false, true, p, stream);
+      e = launch_stage(ctx, wadg::kStage, true, p, stream);
       if (e) return hip_fail((hipError_t)e, "stage kernel launch");
       cur = static_cast<float*>(p.Qout);
     }
@@ -501,6 +512,148 @@ int wadg_parareal(wadg_ctx ctx, const double* y0, double* U, void* work, int32_t
   }
   *iterations = it;
   *last_change = change;
+  return WADG_OK;
+}
+
+namespace {
+// Adjoint workspace: nsteps step-start states, 5 stage residuals, two
+// ping-pong states, ybar, rbar, z (one slice each), then the per-workgroup
+// sensitivity partials.
+size_t adjoint_bytes(wadg_ctx ctx, int32_t nsteps) {
+  const size_t n1 = ctx->slice_doubles();
+  return ((size_t)nsteps + 10) * n1 * sizeof(double) + (size_t)ctx->groups() * sizeof(double);
+}
+
+// One LSRK step of one slice from `in` to `out` (distinct), through t0, t1.
+int one_step(wadg_ctx ctx, const double* in, double* out, double* t0, double* t1, double* res,
+             double dt, void* stream) {
+  wadg::StageParams p = base_params(ctx, 1);
+  p.res = res;
+  p.dt = dt;
+  const double* cur = in;
+  for (int i = 0; i < 5; ++i) {
+    p.Qin = cur;
+    p.Qout = i == 4 ? out : (i % 2 == 0 ? t0 : t1);
+    p.rkA = kRkA[i];
+    p.rkB = kRkB[i];
+    int e = launch_stage(ctx, wadg::kStage, false, p, stream);
+    if (e) return hip_fail((hipError_t)e, "stage kernel launch");
+    cur = static_cast<const double*>(p.Qout);
+  }
+  return WADG_OK;
+}
+}  // namespace
+
+int wadg_adjoint_workspace_bytes(wadg_ctx ctx, int32_t nsteps, size_t* bytes) {
+  if (!ctx) return fail(WADG_E_INVALID, "context is NULL");
+  if (!bytes) return fail(WADG_E_INVALID, "bytes is NULL");
+  if (nsteps < 1) return fail(WADG_E_INVALID, "nsteps must be >= 1");
+  *bytes = adjoint_bytes(ctx, nsteps);
+  return WADG_OK;
+}
+
+int wadg_forward_checkpoints(wadg_ctx ctx, double* chk, void* work, int32_t S, double dt,
+                             int32_t nsteps, void* stream) {
+  if (!ctx) return fail(WADG_E_INVALID, "context is NULL");
+  if (!chk || !work) return fail(WADG_E_INVALID, "chk and work must not be NULL");
+  if (S < 1 || nsteps < 1) return fail(WADG_E_INVALID, "S >= 1 and nsteps >= 1 required");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(WADG_E_INVALID, "dt must be finite and > 0");
+  const size_t n1 = ctx->slice_doubles();
+  if (overlaps(chk, (S + 1) * n1 * sizeof(double), work, adjoint_bytes(ctx, nsteps)))
+    return fail(WADG_E_INVALID, "work must not alias chk");
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select the context's device");
+  double* w = static_cast<double*>(work);
+  double *t0 = w, *t1 = w + n1, *res = w + 2 * n1, *t2 = w + 3 * n1;
+  for (int s = 0; s < S; ++s) {
+    const double* cur = chk + s * n1;
+    for (int m = 0; m < nsteps; ++m) {
+      double* out = m == nsteps - 1 ? chk + (s + 1) * n1 : (m % 2 == 0 ? t2 : t0 + 4 * n1);
+      int st = one_step(ctx, cur, out, t0, t1, res, dt, stream);
+      if (st) return st;
+      cur = out;
+    }
+  }
+  return WADG_OK;
+}
+
+int wadg_adjoint(wadg_ctx ctx, const double* chk, const double* seed, double* grad, void* work,
+                 int32_t S, double dt, int32_t nsteps, double* dJ_dscale, void* stream) {
+  if (!ctx) return fail(WADG_E_INVALID, "context is NULL");
+  if (!chk || !seed || !grad || !work || !dJ_dscale)
+    return fail(WADG_E_INVALID, "chk, seed, grad, work and dJ_dscale must not be NULL");
+  if (S < 1 || nsteps < 1) return fail(WADG_E_INVALID, "S >= 1 and nsteps >= 1 required");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(WADG_E_INVALID, "dt must be finite and > 0");
+  const size_t n1 = ctx->slice_doubles();
+  const size_t sb = n1 * sizeof(double);
+  const size_t wb = adjoint_bytes(ctx, nsteps);
+  if (overlaps(chk, (S + 1) * sb, work, wb) || overlaps(seed, sb, work, wb) ||
+      overlaps(grad, sb, work, wb))
+    return fail(WADG_E_INVALID, "work must not alias chk, seed or grad");
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select the context's device");
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+
+  double* X = static_cast<double*>(work);       // step-start states of a slice
+  double* R = X + (size_t)nsteps * n1;           // stage residuals r_1..r_5
+  double* t0 = R + 5 * n1;
+  double* t1 = t0 + n1;
+  double* yb = t1 + n1;
+  double* rb = yb + n1;
+  double* z = rb + n1;
+  double* part = z + n1;
+  const int G = ctx->groups();
+  WADG_HIP(hipMemsetAsync(part, 0, (size_t)G * sizeof(double), hs));
+  WADG_HIP(hipMemcpyAsync(yb, seed, sb, hipMemcpyDeviceToDevice, hs));
+
+  wadg::StageParams p = base_params(ctx, 1);
+  p.dt = dt;
+  for (int s = S - 1; s >= 0; --s) {
+    // step-start states of slice s, recomputed from its checkpoint
+    WADG_HIP(hipMemcpyAsync(X, chk + s * n1, sb, hipMemcpyDeviceToDevice, hs));
+    for (int m = 1; m < nsteps; ++m) {
+      int st = one_step(ctx, X + (m - 1) * n1, X + m * n1, t0, t1, R, dt, stream);
+      if (st) return st;
+    }
+    for (int m = nsteps - 1; m >= 0; --m) {
+      // the five stages of step m again, each residual kept
+      const double* cur = X + m * n1;
+      for (int i = 0; i < 5; ++i) {
+        p.Qin = cur;
+        p.Qout = i % 2 == 0 ? t0 : t1;
+        p.res = i == 0 ? R : R + (i - 1) * n1;
+        p.res_out = R + i * n1;
+        p.rkA = kRkA[i];
+        p.rkB = kRkB[i];
+        int e = launch_stage(ctx, wadg::kStage, false, p, stream);
+        if (e) return hip_fail((hipError_t)e, "stage kernel launch");
+        cur = static_cast<const double*>(p.Qout);
+      }
+      p.res_out = nullptr;
+      // reverse stages: rbar += B_i ybar; ybar += dt L^T rbar; rbar *= A_i
+      for (int i = 4; i >= 0; --i) {
+        int e = wadg::launch_adjoint_mass(ctx->N, ctx->nq1, p, rb, yb, z, R + i * n1,
+                                          i > 0 ? R + (i - 1) * n1 : nullptr,
+                                          i == 4 ? 0.0 : kRkA[i + 1], kRkB[i], kRkA[i], part,
+                                          stream);
+        if (e) return hip_fail((hipError_t)e, "adjoint mass kernel launch");
+        wadg::StageParams q = p;
+        q.Qin = z;
+        q.res = yb;
+        q.Qout = yb;
+        e = launch_stage(ctx, wadg::kApplyA, false, q, stream);
+        if (e) return hip_fail((hipError_t)e, "stage kernel launch (apply A)");
+      }
+    }
+  }
+  if (grad != yb) WADG_HIP(hipMemcpyAsync(grad, yb, sb, hipMemcpyDeviceToDevice, hs));
+  std::vector<double> h(G);
+  WADG_HIP(hipMemcpyAsync(h.data(), part, (size_t)G * sizeof(double), hipMemcpyDeviceToHost, hs));
+  WADG_HIP(hipStreamSynchronize(hs));
+  double acc = 0.0;
+  for (int g = 0; g < G; ++g) acc += h[g];
+  *dJ_dscale = acc;
+  if (!std::isfinite(acc)) return fail(WADG_E_NONFINITE, "non-finite sensitivity");
   return WADG_OK;
 }
 

@@ -54,11 +54,11 @@ struct Resident {
 // Field c of a tile (NP values), read without a branch: the residual
 // resource is empty (reads return zero) in the first LSRK stage, whose
 // residual buffer may hold anything.  Zeros in right-hand-side mode.
-template <typename R, int NP, bool RHS>
+template <typename R, int NP, int MODE>
 __device__ __forceinline__ void load_field(rsrc_t r, int c, unsigned kb, R (&v)[NP]) {
   constexpr unsigned KP = kWave * sizeof(R);
 #pragma unroll
-  for (int n = 0; n < NP; ++n) v[n] = RHS ? R(0) : ldr<R>(r, kb, (c * NP + n) * KP);
+  for (int n = 0; n < NP; ++n) v[n] = MODE == kRhs ? R(0) : ldr<R>(r, kb, (c * NP + n) * KP);
 }
 
 // One work item of a pressure (PRESSURE) or velocity wave.  `tq` is the
@@ -67,7 +67,7 @@ __device__ __forceinline__ void load_field(rsrc_t r, int c, unsigned kb, R (&v)[
 // in the first LSRK stage) and for writing; `qn` the next tile of the pair
 // (empty resource when there is none), fetched into `pre` by the pressure
 // wave.
-template <typename R, int N, int NQ, bool RHS, bool PRESSURE>
+template <typename R, int N, int NQ, int MODE, bool PRESSURE>
 __device__ __forceinline__ void resident_item(const StageScalars<R>& k, rsrc_t qs, rsrc_t qo,
                                               rsrc_t rr, rsrc_t rw, rsrc_t qn, const R* tq,
                                               const R* gv,
@@ -87,7 +87,7 @@ __device__ __forceinline__ void resident_item(const StageScalars<R>& k, rsrc_t q
 #pragma unroll
   for (int f = 0; f < 4; ++f) gather_trace<R, N>(qs, nbo, f, tr[f]);
   R res0[NP];
-  load_field<R, NP, RHS>(rr, PRESSURE ? 0 : 1, kb, res0);
+  load_field<R, NP, MODE>(rr, PRESSURE ? 0 : 1, kb, res0);
   order();
 
   // a2
@@ -118,7 +118,7 @@ __device__ __forceinline__ void resident_item(const StageScalars<R>& k, rsrc_t q
 #pragma unroll
     for (unsigned c = 0; c < L::pre; ++c) pre[c] = ld128(qn, (c * kWave + lane) * 16u);
   } else {
-    load_field<R, NP, RHS>(rr, 2, kb, res1);
+    load_field<R, NP, MODE>(rr, 2, kb, res1);
   }
   order();
 
@@ -143,16 +143,17 @@ __device__ __forceinline__ void resident_item(const StageScalars<R>& k, rsrc_t q
   // a4 + a5
   R w[NQ2];
 #pragma unroll
-  for (int q = 0; q < NQ2; ++q) w[q] = G((PRESSURE ? 4 : 5) * NQ2 + q);
+  for (int q = 0; q < NQ2; ++q)
+    w[q] = PRESSURE ? k.c2s * G(4 * NQ2 + q) : G(5 * NQ2 + q);
   R dq[NP];
   wadg_inverse<R, N, NQ>(b0, w, dq);
   if constexpr (PRESSURE) {
-    finish_field<R, NP, RHS>(k, qo, rw, P, 0, kb, active, res0, dq);
+    finish_field<R, NP, MODE>(k, qo, rw, P, 0, kb, active, res0, dq);
   } else {
-    finish_field<R, NP, RHS>(k, qo, rw, P, 1, kb, active, res0, dq);
+    finish_field<R, NP, MODE>(k, qo, rw, P, 1, kb, active, res0, dq);
     order();
     wadg_inverse<R, N, NQ>(b1, w, dq);
-    finish_field<R, NP, RHS>(k, qo, rw, P, 2, kb, active, res1, dq);
+    finish_field<R, NP, MODE>(k, qo, rw, P, 2, kb, active, res1, dq);
   }
 }
 
@@ -176,8 +177,10 @@ __device__ __forceinline__ void copy_to_lds(rsrc_t src, void* dst, int tid) {
 
 }  // namespace
 
-template <typename R, int N, int NQ, bool RHS>
+template <typename R, int N, int NQ, int MODE>
 __global__ __launch_bounds__(kResidentWaves * kWave) void resident_kernel(const StageParams p) {
+  static_assert(MODE == kStage || MODE == kRhs, "stage and right-hand-side modes only");
+  constexpr bool RHS = MODE == kRhs;
   using L = Resident<R, N, NQ>;
   constexpr unsigned tile = L::tile;
   constexpr unsigned tile_bytes = tile * sizeof(R);
@@ -224,6 +227,7 @@ __global__ __launch_bounds__(kResidentWaves * kWave) void resident_kernel(const 
   const bool active = eg * kWave + lane < p.K;
   R* const Qout = static_cast<R*>(p.Qout);
   R* const Res = static_cast<R*>(RHS ? p.Qout : p.res);
+  R* const ResW = static_cast<R*>(RHS ? p.Qout : (p.res_out ? p.res_out : p.res));
   u32x4 pre[L::pre];
 
   for (int it = 0; it < items; ++it) {
@@ -231,16 +235,16 @@ __global__ __launch_bounds__(kResidentWaves * kWave) void resident_kernel(const 
     if (s < s1) {
       const rsrc_t qs = make_rsrc(Qin + (size_t)s * slice_vals, (unsigned)(slice_vals * sizeof(R)));
       const rsrc_t qo = tile_rsrc(Qout, s);
-      R* const rp = Res + (size_t)s * slice_vals + goff;
-      const rsrc_t rr = make_rsrc(rp, (RHS || k.A == R(0)) ? 0u : tile_bytes);
-      const rsrc_t rw = make_rsrc(rp, RHS ? 0u : tile_bytes);
+      const size_t toff = (size_t)s * slice_vals + goff;
+      const rsrc_t rr = make_rsrc(Res + toff, (RHS || k.A == R(0)) ? 0u : tile_bytes);
+      const rsrc_t rw = make_rsrc(ResW + toff, RHS ? 0u : tile_bytes);
       const rsrc_t qn = tile_rsrc(Qin, s + 2);
       if (pressure)
-        resident_item<R, N, NQ, RHS, true>(k, qs, qo, rr, rw, qn, tq, gv, gf, nbo, lane, active,
-                                           pre);
+        resident_item<R, N, NQ, MODE, true>(k, qs, qo, rr, rw, qn, tq, gv, gf, nbo, lane,
+                                            active, pre);
       else
-        resident_item<R, N, NQ, RHS, false>(k, qs, qo, rr, rw, qn, tq, gv, gf, nbo, lane, active,
-                                            pre);
+        resident_item<R, N, NQ, MODE, false>(k, qs, qo, rr, rw, qn, tq, gv, gf, nbo, lane,
+                                             active, pre);
     }
     __syncthreads();
     if (pressure && s + 2 < s1) {
@@ -258,37 +262,39 @@ __global__ __launch_bounds__(kResidentWaves * kWave) void resident_kernel(const 
 namespace {
 
 template <typename R, int N, int NQ>
-int launch_nq(bool rhs, const StageParams& p, int ranges, void* stream) {
+int launch_nq(int mode, const StageParams& p, int ranges, void* stream) {
   if constexpr (!Resident<R, N, NQ>::fits) {
     return (int)hipErrorInvalidValue;
   } else {
     const dim3 grid(p.nEG * ranges), block(kResidentWaves * kWave);
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (rhs)
-      hipLaunchKernelGGL((resident_kernel<R, N, NQ, true>), grid, block, 0, st, p);
+    if (mode == kStage)
+      hipLaunchKernelGGL((resident_kernel<R, N, NQ, kStage>), grid, block, 0, st, p);
+    else if (mode == kRhs && sizeof(R) == sizeof(double))
+      hipLaunchKernelGGL((resident_kernel<R, N, NQ, kRhs>), grid, block, 0, st, p);
     else
-      hipLaunchKernelGGL((resident_kernel<R, N, NQ, false>), grid, block, 0, st, p);
+      return (int)hipErrorInvalidValue;
     return (int)hipGetLastError();
   }
 }
 
 template <typename R, int N>
-int launch_n(int nq, bool rhs, const StageParams& p, int ranges, void* stream) {
+int launch_n(int nq, int mode, const StageParams& p, int ranges, void* stream) {
   switch (nq - N) {
-    case 1: return launch_nq<R, N, N + 1>(rhs, p, ranges, stream);
-    case 2: return launch_nq<R, N, N + 2>(rhs, p, ranges, stream);
-    case 3: return launch_nq<R, N, N + 3>(rhs, p, ranges, stream);
+    case 1: return launch_nq<R, N, N + 1>(mode, p, ranges, stream);
+    case 2: return launch_nq<R, N, N + 2>(mode, p, ranges, stream);
+    case 3: return launch_nq<R, N, N + 3>(mode, p, ranges, stream);
     default: return (int)hipErrorInvalidValue;
   }
 }
 
 template <typename R>
-int launch_r(int N, int nq, bool rhs, const StageParams& p, int ranges, void* stream) {
+int launch_r(int N, int nq, int mode, const StageParams& p, int ranges, void* stream) {
   switch (N) {
-    case 1: return launch_n<R, 1>(nq, rhs, p, ranges, stream);
-    case 2: return launch_n<R, 2>(nq, rhs, p, ranges, stream);
-    case 3: return launch_n<R, 3>(nq, rhs, p, ranges, stream);
-    case 4: return launch_n<R, 4>(nq, rhs, p, ranges, stream);
+    case 1: return launch_n<R, 1>(nq, mode, p, ranges, stream);
+    case 2: return launch_n<R, 2>(nq, mode, p, ranges, stream);
+    case 3: return launch_n<R, 3>(nq, mode, p, ranges, stream);
+    case 4: return launch_n<R, 4>(nq, mode, p, ranges, stream);
     default: return (int)hipErrorInvalidValue;
   }
 }
@@ -316,13 +322,13 @@ int resident_ranges(int nEG, int S, int cus) {
   return r < 1 ? 1 : r;
 }
 
-int launch_stage_resident(int N, int nq, bool rhs, const StageParams& p, int ranges,
+int launch_stage_resident(int N, int nq, int mode, const StageParams& p, int ranges,
                           void* stream) {
-  return launch_r<double>(N, nq, rhs, p, ranges, stream);
+  return launch_r<double>(N, nq, mode, p, ranges, stream);
 }
 
 int launch_stage_resident_fp32(int N, int nq, const StageParams& p, int ranges, void* stream) {
-  return launch_r<float>(N, nq, false, p, ranges, stream);
+  return launch_r<float>(N, nq, kStage, p, ranges, stream);
 }
 
 }  // namespace wadg

@@ -24,8 +24,16 @@
 #include "reference_tables.h"
 #include "wadg_internal.h"
 
+// Every multiply-add below is an explicit fused multiply-add in a fixed
+// order, and the compiler forms no others: the stage kernels, which inline
+// these helpers into different contexts, then round identically.
+#pragma clang fp contract(off)
+
 namespace wadg {
 namespace dev {
+
+__device__ __forceinline__ double mad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float mad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
 // Memory access through buffer resources: the base address and size of an
 // array live in four scalar registers, the per-plane offset (node, field,
@@ -88,7 +96,7 @@ __device__ constexpr int fnode(int f, int m) {
 // Stage-wide constants of one launch.
 template <typename R>
 struct StageScalars {
-  R tau_p, tau_u, A, B, dt;
+  R tau_p, tau_u, A, B, dt, c2s;
 };
 
 template <typename R>
@@ -99,6 +107,7 @@ __device__ __forceinline__ StageScalars<R> stage_scalars(const StageParams& p) {
   k.A = (R)p.rkA;
   k.B = (R)p.rkB;
   k.dt = (R)p.dt;
+  k.c2s = (R)p.c2_scale;
   return k;
 }
 
@@ -159,8 +168,8 @@ __device__ __forceinline__ void pressure_volume_column(int i, const FU& U, const
     R su = R(0), sv = R(0);
 #pragma unroll
     for (int a = 0; a < NP1; ++a) {
-      su += T.V[i][a] * U(a + NP1 * bb);
-      sv += T.V[i][a] * V(a + NP1 * bb);
+      su = mad(T.V[i][a], U(a + NP1 * bb), su);
+      sv = mad(T.V[i][a], V(a + NP1 * bb), sv);
     }
     tu[bb] = su;
     tv[bb] = sv;
@@ -173,21 +182,22 @@ __device__ __forceinline__ void pressure_volume_column(int i, const FU& U, const
     R uq = R(0), vq = R(0);
 #pragma unroll
     for (int bb = 0; bb < NP1; ++bb) {
-      uq += T.V[j][bb] * tu[bb];
-      vq += T.V[j][bb] * tv[bb];
+      uq = mad(T.V[j][bb], tu[bb], uq);
+      vq = mad(T.V[j][bb], tv[bb], vq);
     }
-    const R Ur = g[0][j] * uq + g[1][j] * vq;
-    const R Us = g[2][j] * uq + g[3][j] * vq;
+    const R Ur = mad(g[0][j], uq, g[1][j] * vq);
+    const R Us = mad(g[2][j], uq, g[3][j] * vq);
 #pragma unroll
     for (int bb = 0; bb < NP1; ++bb) {
-      cr[bb] += T.V[j][bb] * Ur;
-      cs[bb] += T.D[j][bb] * Us;
+      cr[bb] = mad(T.V[j][bb], Ur, cr[bb]);
+      cs[bb] = mad(T.D[j][bb], Us, cs[bb]);
     }
   }
 #pragma unroll
   for (int bb = 0; bb < NP1; ++bb)
 #pragma unroll
-    for (int a = 0; a < NP1; ++a) bp[a + NP1 * bb] += T.D[i][a] * cr[bb] + T.V[i][a] * cs[bb];
+    for (int a = 0; a < NP1; ++a)
+      bp[a + NP1 * bb] = mad(T.D[i][a], cr[bb], mad(T.V[i][a], cs[bb], bp[a + NP1 * bb]));
 }
 
 // Velocity volume term, quadrature column i:  (bu, bv) -= sum_j w J l grad p.
@@ -204,8 +214,8 @@ __device__ __forceinline__ void velocity_volume_column(int i, const FP& P, const
 #pragma unroll
     for (int a = 0; a < NP1; ++a) {
       const R pa = P(a + NP1 * bb);
-      sd += T.D[i][a] * pa;
-      sp += T.V[i][a] * pa;
+      sd = mad(T.D[i][a], pa, sd);
+      sp = mad(T.V[i][a], pa, sp);
     }
     td[bb] = sd;
     tp[bb] = sp;
@@ -218,23 +228,23 @@ __device__ __forceinline__ void velocity_volume_column(int i, const FP& P, const
     R pr = R(0), ps = R(0);
 #pragma unroll
     for (int bb = 0; bb < NP1; ++bb) {
-      pr += T.V[j][bb] * td[bb];
-      ps += T.D[j][bb] * tp[bb];
+      pr = mad(T.V[j][bb], td[bb], pr);
+      ps = mad(T.D[j][bb], tp[bb], ps);
     }
-    const R Gx = g[0][j] * pr + g[2][j] * ps;
-    const R Gy = g[1][j] * pr + g[3][j] * ps;
+    const R Gx = mad(g[0][j], pr, g[2][j] * ps);
+    const R Gy = mad(g[1][j], pr, g[3][j] * ps);
 #pragma unroll
     for (int bb = 0; bb < NP1; ++bb) {
-      cx[bb] += T.V[j][bb] * Gx;
-      cy[bb] += T.V[j][bb] * Gy;
+      cx[bb] = mad(T.V[j][bb], Gx, cx[bb]);
+      cy[bb] = mad(T.V[j][bb], Gy, cy[bb]);
     }
   }
 #pragma unroll
   for (int bb = 0; bb < NP1; ++bb)
 #pragma unroll
     for (int a = 0; a < NP1; ++a) {
-      bu[a + NP1 * bb] -= T.V[i][a] * cx[bb];
-      bv[a + NP1 * bb] -= T.V[i][a] * cy[bb];
+      bu[a + NP1 * bb] = mad(-T.V[i][a], cx[bb], bu[a + NP1 * bb]);
+      bv[a + NP1 * bb] = mad(-T.V[i][a], cy[bb], bv[a + NP1 * bb]);
     }
 }
 
@@ -247,12 +257,12 @@ __device__ __forceinline__ void face_point(int f, int j, const FP& P, const FU& 
   pm = um = vm = pp = up = vp = R(0);
 #pragma unroll
   for (int m = 0; m <= N; ++m) {
-    pm += T.V[j][m] * P(fnode<N>(f, m));
-    um += T.V[j][m] * U(fnode<N>(f, m));
-    vm += T.V[j][m] * V(fnode<N>(f, m));
-    pp += T.V[j][m] * t.p[m];
-    up += T.V[j][m] * t.u[m];
-    vp += T.V[j][m] * t.v[m];
+    pm = mad(T.V[j][m], P(fnode<N>(f, m)), pm);
+    um = mad(T.V[j][m], U(fnode<N>(f, m)), um);
+    vm = mad(T.V[j][m], V(fnode<N>(f, m)), vm);
+    pp = mad(T.V[j][m], t.p[m], pp);
+    up = mad(T.V[j][m], t.u[m], up);
+    vp = mad(T.V[j][m], t.v[m], vp);
   }
 }
 
@@ -268,9 +278,10 @@ __device__ __forceinline__ void pressure_face(int f, const FP& P, const FU& U, c
     R pm, um, vm, pp, up, vp;
     face_point<R, N, NQ>(f, j, P, U, V, t, pm, um, vm, pp, up, vp);
     const R nx = g[0][j], ny = g[1][j], wsJ = g[2][j];
-    const R fp = R(0.5) * wsJ * ((up + um) * nx + (vp + vm) * ny - tau_p * (pp - pm));
+    const R un = mad(up + um, nx, (vp + vm) * ny);          // 2 {u}.n
+    const R fp = (R(0.5) * wsJ) * mad(-tau_p, pp - pm, un);
 #pragma unroll
-    for (int m = 0; m <= N; ++m) bp[fnode<N>(f, m)] -= T.V[j][m] * fp;
+    for (int m = 0; m <= N; ++m) bp[fnode<N>(f, m)] = mad(-T.V[j][m], fp, bp[fnode<N>(f, m)]);
   }
 }
 
@@ -287,12 +298,13 @@ __device__ __forceinline__ void velocity_face(int f, const FP& P, const FU& U, c
     R pm, um, vm, pp, up, vp;
     face_point<R, N, NQ>(f, j, P, U, V, t, pm, um, vm, pp, up, vp);
     const R nx = g[0][j], ny = g[1][j], wsJ = g[2][j];
-    const R fu = R(0.5) * wsJ * ((pp - pm) - tau_u * ((up - um) * nx + (vp - vm) * ny));
+    const R jn = mad(up - um, nx, (vp - vm) * ny);          // [u].n
+    const R fu = (R(0.5) * wsJ) * mad(-tau_u, jn, pp - pm);
     const R fx = fu * nx, fy = fu * ny;
 #pragma unroll
     for (int m = 0; m <= N; ++m) {
-      bu[fnode<N>(f, m)] -= T.V[j][m] * fx;
-      bv[fnode<N>(f, m)] -= T.V[j][m] * fy;
+      bu[fnode<N>(f, m)] = mad(-T.V[j][m], fx, bu[fnode<N>(f, m)]);
+      bv[fnode<N>(f, m)] = mad(-T.V[j][m], fy, bv[fnode<N>(f, m)]);
     }
   }
 }
@@ -314,7 +326,7 @@ __device__ __forceinline__ void wadg_inverse(const R (&b)[(N + 1) * (N + 1)],
     for (int bb = 0; bb < NP1; ++bb) {
       R acc = R(0);
 #pragma unroll
-      for (int a = 0; a < NP1; ++a) acc += T.Vt[i][a] * b[a + NP1 * bb];
+      for (int a = 0; a < NP1; ++a) acc = mad(T.Vt[i][a], b[a + NP1 * bb], acc);
       t[bb] = acc;
     }
     R c[NP1];
@@ -324,27 +336,28 @@ __device__ __forceinline__ void wadg_inverse(const R (&b)[(N + 1) * (N + 1)],
     for (int j = 0; j < NQ; ++j) {
       R rq = R(0);
 #pragma unroll
-      for (int bb = 0; bb < NP1; ++bb) rq += T.Vt[j][bb] * t[bb];
+      for (int bb = 0; bb < NP1; ++bb) rq = mad(T.Vt[j][bb], t[bb], rq);
       rq *= w[i + NQ * j];
 #pragma unroll
-      for (int bb = 0; bb < NP1; ++bb) c[bb] += T.P[bb][j] * rq;
+      for (int bb = 0; bb < NP1; ++bb) c[bb] = mad(T.P[bb][j], rq, c[bb]);
     }
 #pragma unroll
     for (int bb = 0; bb < NP1; ++bb)
 #pragma unroll
-      for (int a = 0; a < NP1; ++a) dq[a + NP1 * bb] += T.P[a][i] * c[bb];
+      for (int a = 0; a < NP1; ++a) dq[a + NP1 * bb] = mad(T.P[a][i], c[bb], dq[a + NP1 * bb]);
     pin(dq);
   }
 }
 
-// Residual of field c (NP values), or zeros when A = 0 (first stage) or in
-// right-hand-side mode, where it is not read at all.
-template <typename R, int NP, bool RHS>
+// The per-field operand of the final update: the residual in stage mode
+// (zeros, not read, when A = 0 -- the first stage), the adjoint state ybar
+// in apply-A mode, nothing in right-hand-side mode.
+template <typename R, int NP, int MODE>
 __device__ __forceinline__ void load_res(const StageScalars<R>& k, rsrc_t res, int c,
                                          unsigned kb, R (&resv)[NP]) {
   constexpr unsigned KP = kWave * sizeof(R);
-  if constexpr (!RHS) {
-    if (k.A != R(0)) {
+  if constexpr (MODE != kRhs) {
+    if (MODE == kApplyA || k.A != R(0)) {
 #pragma unroll
       for (int n = 0; n < NP; ++n) resv[n] = ldr<R>(res, kb, (c * NP + n) * KP);
       return;
@@ -354,24 +367,30 @@ __device__ __forceinline__ void load_res(const StageScalars<R>& k, rsrc_t res, i
   for (int n = 0; n < NP; ++n) resv[n] = R(0);
 }
 
-// a5 for field c: res <- A res + dt dq; Qout <- Qin + B res (stage mode), or
-// Qout <- dq (right-hand-side mode).  `qin(n)` is the input value of node n.
-template <typename R, int NP, bool RHS, typename FQ>
-__device__ __forceinline__ void finish_field(const StageScalars<R>& k, rsrc_t qout, rsrc_t res,
+// a5 for field c.  Stage mode: res <- A res + dt dq (written through
+// `resw`), Qout <- Qin + B res.  Right-hand-side mode: Qout <- dq.  Apply-A
+// mode: Qout <- ybar + dt D dq with dq the load vector and D = diag(1,-1,-1).
+// `qin(n)` is the input value of node n.
+template <typename R, int NP, int MODE, typename FQ>
+__device__ __forceinline__ void finish_field(const StageScalars<R>& k, rsrc_t qout, rsrc_t resw,
                                              const FQ& qin, int c, unsigned kb, bool active,
                                              const R (&resv)[NP], const R (&dq)[NP]) {
   constexpr unsigned KP = kWave * sizeof(R);
   if (!active) return;
-  if constexpr (RHS) {
+  if constexpr (MODE == kRhs) {
 #pragma unroll
     for (int n = 0; n < NP; ++n) st(qout, kb, (c * NP + n) * KP, dq[n]);
+  } else if constexpr (MODE == kApplyA) {
+    const R sdt = c == 0 ? k.dt : -k.dt;
+#pragma unroll
+    for (int n = 0; n < NP; ++n) st(qout, kb, (c * NP + n) * KP, mad(sdt, dq[n], resv[n]));
   } else {
 #pragma unroll
     for (int n = 0; n < NP; ++n) {
       const unsigned so = (c * NP + n) * KP;
-      const R r = k.A * resv[n] + k.dt * dq[n];
-      st(res, kb, so, r);
-      st(qout, kb, so, qin(c * NP + n) + k.B * r);
+      const R r = mad(k.A, resv[n], k.dt * dq[n]);
+      st(resw, kb, so, r);
+      st(qout, kb, so, mad(k.B, r, qin(c * NP + n)));
     }
   }
 }

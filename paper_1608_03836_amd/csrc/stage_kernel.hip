@@ -54,7 +54,7 @@ using namespace dev;
 // Buffer resources of one workgroup: the group's tiles of the state arrays
 // and of the geometry, and the whole input slice for neighbour gathers.
 struct Bufs {
-  rsrc_t qin, qout, res, qslice, vol, face, nbr;
+  rsrc_t qin, qout, res, resw, qslice, vol, face, nbr;
 };
 
 // The NQ^2 weights of the weight-adjusted inverse (geometry plane `wplane`).
@@ -98,7 +98,7 @@ __device__ __forceinline__ void load_metric_column(const Bufs& B, int i, unsigne
 
 // One wave's share of a work item: the pressure equation (wave 0) or the two
 // velocity equations (wave 1).
-template <typename R, int N, int NQ, bool RHS, bool PRESSURE>
+template <typename R, int N, int NQ, int MODE, bool PRESSURE>
 __device__ __forceinline__ void stage_wave(const StageScalars<R>& k, const Bufs& B, const R* tq,
                                            unsigned kb, int lane, bool active,
                                            const NbrOffsets& nbo, const R (&g0)[4][NQ]) {
@@ -148,8 +148,8 @@ __device__ __forceinline__ void stage_wave(const StageScalars<R>& k, const Bufs&
     if (f + 1 < 4) {
       load_face<R, N, NQ>(B, nbo, f + 1, kb, fd[(f + 1) & 1]);
     } else {
-      load_weights<R, NQ>(B, (PRESSURE ? 4 : 5) * NQ2, kb, w);
-      load_res<R, NP, RHS>(k, B.res, PRESSURE ? 0 : 1, kb, resv);
+      if constexpr (MODE != kApplyA) load_weights<R, NQ>(B, (PRESSURE ? 4 : 5) * NQ2, kb, w);
+      load_res<R, NP, MODE>(k, B.res, PRESSURE ? 0 : 1, kb, resv);
     }
     order();
     const FaceData<R, N, NQ>& d = fd[f & 1];
@@ -164,26 +164,42 @@ __device__ __forceinline__ void stage_wave(const StageScalars<R>& k, const Bufs&
   }
 
   // a4 + a5; the velocity wave reuses the weights (1/J) for both fields and
-  // requests the second residual before the first field's stores
+  // requests the second residual before the first field's stores.  The
+  // pressure weights c^2/J carry the wave-speed scale.  Apply-A mode (the
+  // transposed operator's outer factor) takes the load vector itself.
   order();
+  if constexpr (PRESSURE && MODE != kApplyA) {
+#pragma unroll
+    for (int q = 0; q < NQ2; ++q) w[q] *= k.c2s;
+  }
   R dq[NP];
-  wadg_inverse<R, N, NQ>(b0, w, dq);
+  if constexpr (MODE == kApplyA) {
+#pragma unroll
+    for (int n = 0; n < NP; ++n) dq[n] = b0[n];
+  } else {
+    wadg_inverse<R, N, NQ>(b0, w, dq);
+  }
   if constexpr (PRESSURE) {
-    finish_field<R, NP, RHS>(k, B.qout, B.res, P, 0, kb, active, resv, dq);
+    finish_field<R, NP, MODE>(k, B.qout, B.resw, P, 0, kb, active, resv, dq);
   } else {
     R resv2[NP];
-    load_res<R, NP, RHS>(k, B.res, 2, kb, resv2);
+    load_res<R, NP, MODE>(k, B.res, 2, kb, resv2);
     order();
-    finish_field<R, NP, RHS>(k, B.qout, B.res, P, 1, kb, active, resv, dq);
+    finish_field<R, NP, MODE>(k, B.qout, B.resw, P, 1, kb, active, resv, dq);
     order();
-    wadg_inverse<R, N, NQ>(b1, w, dq);
-    finish_field<R, NP, RHS>(k, B.qout, B.res, P, 2, kb, active, resv2, dq);
+    if constexpr (MODE == kApplyA) {
+#pragma unroll
+      for (int n = 0; n < NP; ++n) dq[n] = b1[n];
+    } else {
+      wadg_inverse<R, N, NQ>(b1, w, dq);
+    }
+    finish_field<R, NP, MODE>(k, B.qout, B.resw, P, 2, kb, active, resv2, dq);
   }
 }
 
 }  // namespace
 
-template <typename R, int N, int NQ, bool RHS>
+template <typename R, int N, int NQ, int MODE>
 __global__ __launch_bounds__(2 * kWave) void stage_kernel(const StageParams p) {
   constexpr int NP = (N + 1) * (N + 1);
   constexpr int NQ2 = NQ * NQ;
@@ -213,7 +229,9 @@ __global__ __launch_bounds__(2 * kWave) void stage_kernel(const StageParams p) {
   Bufs B;
   B.qin = make_rsrc(Qin + grp, tile * sizeof(R));
   B.qout = make_rsrc(static_cast<R*>(p.Qout) + grp, tile * sizeof(R));
-  B.res = make_rsrc(static_cast<R*>(RHS ? p.Qout : p.res) + grp, tile * sizeof(R));
+  B.res = make_rsrc(static_cast<R*>(MODE == kRhs ? p.Qout : p.res) + grp, tile * sizeof(R));
+  B.resw = make_rsrc(static_cast<R*>(p.res_out ? p.res_out : p.res) + grp,
+                     MODE == kStage ? tile * sizeof(R) : 0u);
   B.qslice = make_rsrc(Qin + slice, (unsigned)p.nEG * tile * sizeof(R));
   B.vol = make_rsrc(static_cast<const R*>(p.vol) + (size_t)eg * 6 * NQ2 * kWave, 6u * NQ2 * KP);
   B.face = make_rsrc(static_cast<const R*>(p.face) + (size_t)eg * 12 * NQ * kWave,
@@ -247,41 +265,49 @@ __global__ __launch_bounds__(2 * kWave) void stage_kernel(const StageParams p) {
   const StageScalars<R> k = stage_scalars<R>(p);
   const bool active = eg * kWave + lane < p.K;
   if (wave == 0)
-    stage_wave<R, N, NQ, RHS, true>(k, B, tq, kb, lane, active, nbo, g0);
+    stage_wave<R, N, NQ, MODE, true>(k, B, tq, kb, lane, active, nbo, g0);
   else
-    stage_wave<R, N, NQ, RHS, false>(k, B, tq, kb, lane, active, nbo, g0);
+    stage_wave<R, N, NQ, MODE, false>(k, B, tq, kb, lane, active, nbo, g0);
 }
 
 namespace {
 
 template <typename R, int N, int NQ>
-int launch_nq(bool rhs, const StageParams& p, void* stream) {
-  const int nwg = p.nEG * p.S;
+int launch_nq(int mode, const StageParams& p, void* stream) {
+  const dim3 grid(p.nEG * p.S), block(2 * kWave);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (rhs)
-    hipLaunchKernelGGL((stage_kernel<R, N, NQ, true>), dim3(nwg), dim3(2 * kWave), 0, st, p);
-  else
-    hipLaunchKernelGGL((stage_kernel<R, N, NQ, false>), dim3(nwg), dim3(2 * kWave), 0, st, p);
+  if (mode == kStage) {
+    hipLaunchKernelGGL((stage_kernel<R, N, NQ, kStage>), grid, block, 0, st, p);
+  } else if constexpr (sizeof(R) == sizeof(double)) {
+    if (mode == kRhs)
+      hipLaunchKernelGGL((stage_kernel<R, N, NQ, kRhs>), grid, block, 0, st, p);
+    else if (mode == kApplyA)
+      hipLaunchKernelGGL((stage_kernel<R, N, NQ, kApplyA>), grid, block, 0, st, p);
+    else
+      return (int)hipErrorInvalidValue;
+  } else {
+    return (int)hipErrorInvalidValue;
+  }
   return (int)hipGetLastError();
 }
 
 template <typename R, int N>
-int launch_n(int nq, bool rhs, const StageParams& p, void* stream) {
+int launch_n(int nq, int mode, const StageParams& p, void* stream) {
   switch (nq - N) {
-    case 1: return launch_nq<R, N, N + 1>(rhs, p, stream);
-    case 2: return launch_nq<R, N, N + 2>(rhs, p, stream);
-    case 3: return launch_nq<R, N, N + 3>(rhs, p, stream);
+    case 1: return launch_nq<R, N, N + 1>(mode, p, stream);
+    case 2: return launch_nq<R, N, N + 2>(mode, p, stream);
+    case 3: return launch_nq<R, N, N + 3>(mode, p, stream);
     default: return (int)hipErrorInvalidValue;
   }
 }
 
 template <typename R>
-int launch_r(int N, int nq, bool rhs, const StageParams& p, void* stream) {
+int launch_r(int N, int nq, int mode, const StageParams& p, void* stream) {
   switch (N) {
-    case 1: return launch_n<R, 1>(nq, rhs, p, stream);
-    case 2: return launch_n<R, 2>(nq, rhs, p, stream);
-    case 3: return launch_n<R, 3>(nq, rhs, p, stream);
-    case 4: return launch_n<R, 4>(nq, rhs, p, stream);
+    case 1: return launch_n<R, 1>(nq, mode, p, stream);
+    case 2: return launch_n<R, 2>(nq, mode, p, stream);
+    case 3: return launch_n<R, 3>(nq, mode, p, stream);
+    case 4: return launch_n<R, 4>(nq, mode, p, stream);
     default: return (int)hipErrorInvalidValue;
   }
 }
@@ -290,12 +316,12 @@ int launch_r(int N, int nq, bool rhs, const StageParams& p, void* stream) {
 
 bool stage_supported(int N, int nq) { return N >= 1 && N <= 4 && nq >= N + 1 && nq <= N + 3; }
 
-int launch_stage_streamed(int N, int nq, bool rhs, const StageParams& p, void* stream) {
-  return launch_r<double>(N, nq, rhs, p, stream);
+int launch_stage_streamed(int N, int nq, int mode, const StageParams& p, void* stream) {
+  return launch_r<double>(N, nq, mode, p, stream);
 }
 
 int launch_stage_streamed_fp32(int N, int nq, const StageParams& p, void* stream) {
-  return launch_r<float>(N, nq, false, p, stream);
+  return launch_r<float>(N, nq, kStage, p, stream);
 }
 
 }  // namespace wadg

@@ -69,8 +69,10 @@ void quadrature_points(const MeshIn& m, const RefOps& ops, double* xq, double* y
 // FP32-bulk propagator) except the int32 neighbour offsets.
 struct StageParams {
   const void* Qin;       // [S][G][3][Np][64]
-  void* Qout;            // [S][G][3][Np][64]  (rhs mode: dQ/dt)
-  void* res;             // [S][G][3][Np][64]  LSRK residual (stage mode)
+  void* Qout;            // [S][G][3][Np][64]  (rhs mode: dQ/dt; adjoint mode: ybar out)
+  void* res;             // [S][G][3][Np][64]  LSRK residual read (stage mode; adjoint
+                         //                    mode: ybar in)
+  void* res_out;         // residual written (stage mode); NULL: same as res
   const void* vol;       // [G][6][Nq][64]
   const void* face;      // [G][3][4][nq][64]
   const int32_t* nbr;    // [G][2][4][64]
@@ -78,14 +80,22 @@ struct StageParams {
   int32_t tile_groups, tile_slices;   // schedule tile (clamped to nEG, S)
   double tau_p, tau_u;
   double rkA, rkB, dt;
+  double c2_scale;       // c^2 multiplier (pressure mass weights)
 };
+
+// What a stage-kernel launch computes from the load vector b = A Qin:
+//   kStage   LSRK stage: res_out <- A res + dt M^-1 b; Qout <- Qin + B res_out
+//   kRhs     Qout <- M^-1 b
+//   kApplyA  adjoint stage part: Qout <- res + dt D b, D = diag(1, -1, -1)
+//            (no mass inverse; streamed kernel only)
+enum StageMode { kStage = 0, kRhs = 1, kApplyA = 2 };
 
 // Launch one stage (rhs == false: LSRK stage update; rhs == true: write
 // dQ/dt to Qout).  Returns a hipError_t as int.
 //
 // Streamed-geometry kernel: one workgroup per (slice, element group), the
 // group's geometry read from global memory; every supported (N, nq).
-int launch_stage_streamed(int N, int nq, bool rhs, const StageParams& p, void* stream);
+int launch_stage_streamed(int N, int nq, int mode, const StageParams& p, void* stream);
 // The same LSRK stage in FP32 (arrays of float).
 int launch_stage_streamed_fp32(int N, int nq, const StageParams& p, void* stream);
 // Resident-geometry kernel: one workgroup per (element group, slice range)
@@ -93,8 +103,16 @@ int launch_stage_streamed_fp32(int N, int nq, const StageParams& p, void* stream
 // resident_supported(N, nq, fp32).
 bool resident_supported(int N, int nq, bool fp32);
 int resident_ranges(int nEG, int S, int cus);
-int launch_stage_resident(int N, int nq, bool rhs, const StageParams& p, int ranges,
+int launch_stage_resident(int N, int nq, int mode, const StageParams& p, int ranges,
                           void* stream);
+// Adjoint mass step, elementwise (one workgroup per (slice, element group)):
+//   rbar <- a rbar + b ybar   (rbar not read when a == 0)
+//   z    <- D Mtilde^-1 rbar  (WADG inverse per field, c2_scale on p)
+//   part[w] += sum over p entries of rbar * (r_i - a_i r_prev)   (r_prev not
+//            read when a_i == 0), w = slice * nEG + group, one slot per workgroup
+int launch_adjoint_mass(int N, int nq, const StageParams& p, double* rbar, const double* ybar,
+                        double* z, const double* r_i, const double* r_prev, double a_next,
+                        double b_i, double a_i, double* part, void* stream);
 int launch_stage_resident_fp32(int N, int nq, const StageParams& p, int ranges, void* stream);
 // Elementwise precision conversion of n values (FP64 <-> FP32).
 int launch_to_fp32(const double* in, float* out, size_t n, void* stream);

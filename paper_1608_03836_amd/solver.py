@@ -114,3 +114,29 @@ class Solver:
 
     def kernel_in_use(self, fp32=False):
         return B.wadg_kernel_in_use(self.ctx, fp32)
+
+    # -- sensitivities ---------------------------------------------------
+    def set_c2_scale(self, gamma):
+        """Use c^2 = gamma * c2 (the wave speed given at construction)."""
+        B.wadg_set_c2_scale(self.ctx, gamma)
+
+    def adjoint_workspace(self, nsteps):
+        n = B.wadg_adjoint_workspace_bytes(self.ctx, nsteps) // 8 + 1
+        return self.torch.empty(n, dtype=self.torch.float64, device=self.device)
+
+    def forward_checkpoints(self, y0, S, dt, nsteps, work=None, stream=None):
+        """One trajectory from the device state y0 (one slice) over S slices of
+        nsteps steps; returns the S+1 slice-boundary states (device tensor)."""
+        chk = self.empty_state(S + 1)
+        chk[: self.slice_doubles].copy_(y0.reshape(-1)[: self.slice_doubles])
+        work = self.adjoint_workspace(nsteps) if work is None else work
+        B.wadg_forward_checkpoints(self.ctx, chk, work, S, dt, nsteps, stream)
+        return chk
+
+    def adjoint(self, chk, seed, S, dt, nsteps, work=None, stream=None):
+        """Reverse sweep: (dJ/dq(0) device tensor, gamma dJ/dgamma) for
+        seed = dJ/dq(T) and the checkpoints of ``forward_checkpoints``."""
+        grad = self.empty_state(1)
+        work = self.adjoint_workspace(nsteps) if work is None else work
+        d = B.wadg_adjoint(self.ctx, chk, seed.contiguous(), grad, work, S, dt, nsteps, stream)
+        return grad, d

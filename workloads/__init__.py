@@ -18,4 +18,5 @@ from .fields import (  # noqa: F401
     wave_modes, PlaneWaveSolution, smooth_pressure, uniform_pressure,
     c2_constant, c2_layered, pack_state, unpack_state, heat_initial,
 )
-from .configs import CONFIGS, make_problem, make_heat_problem  # noqa: F401
+from .configs import (CONFIGS, SENSITIVITY, make_problem, make_heat_problem,  # noqa: F401
+                      make_sensitivity_problem, SensitivityProblem)

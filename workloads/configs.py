@@ -20,6 +20,14 @@ together.
            c^2 = 1 + 0.5 sin(2 pi x) sin(4 pi y), tau=1, S=256 slices of 10
            steps (dt = 0.5/256/10); slice s starts from nodal p ~ U[-0.1,0.1]
            with seed 3+s and u = 0.
+  adj128   sensitivity problem: one trajectory on 128x128 elements, N=3,
+           eps=0.05, c^2 = gamma (1 + 0.5 sin(2 pi x) sin(4 pi y)), gamma = 1,
+           tau=1, T=0.25 over S=128 checkpointed slices of 10 steps
+           (dt = 0.25/1280); start state p0 = 32 modes (seed 5), u = 0;
+           target p = 32 modes (seed 6); objective sum over nodes (p(T) -
+           p_target)^2.
+  adj4     the same on 4x4 elements, S=3 slices of 2 steps (dt = 0.01),
+           8 modes (seeds 5 and 6), gamma = 1.3 (oracle-sized).
 """
 
 from dataclasses import dataclass, field
@@ -41,6 +49,56 @@ CONFIGS = {
     "wadg128": dict(kind="wadg", K1D=128, N=3, eps=0.05, c2="layered", tau=1.0, T=0.5,
                     S=256, steps_per_slice=10, seed=3, init="uniform"),
 }
+
+
+SENSITIVITY = {
+    "adj128": dict(K1D=128, N=3, eps=0.05, tau=1.0, gamma=1.0, T=0.25, S=128,
+                   steps_per_slice=10, modes=32, seed_p0=5, seed_target=6),
+    "adj4": dict(K1D=4, N=3, eps=0.05, tau=1.0, gamma=1.3, T=0.06, S=3,
+                 steps_per_slice=2, modes=8, seed_p0=5, seed_target=6),
+}
+
+
+@dataclass
+class SensitivityProblem:
+    name: str
+    mesh: QuadMesh
+    c0: Callable                # base c^2; the sweep uses gamma * c0
+    gamma: float
+    tau_p: float
+    tau_u: float
+    nq1: int
+    S: int                      # checkpointed slices of one trajectory
+    nsteps: int                 # steps per slice
+    dt: float
+    y0: np.ndarray              # [3][Np][K] start state
+    p_target: np.ndarray        # [Np][K]
+
+    @property
+    def N(self):
+        return self.mesh.N
+
+    @property
+    def K(self):
+        return self.mesh.K
+
+
+def make_sensitivity_problem(name, **overrides):
+    cfg = dict(SENSITIVITY[name])
+    cfg.update(overrides)
+    N, K1D = cfg["N"], cfg["K1D"]
+    mesh = periodic_quad_mesh(K1D, N, eps=cfg["eps"])
+    Np = (N + 1) ** 2
+    p0, _, _ = smooth_pressure(mesh, cfg["modes"], cfg["seed_p0"])(mesh.x, mesh.y, 0.0)
+    pt, _, _ = smooth_pressure(mesh, cfg["modes"], cfg["seed_target"])(mesh.x, mesh.y, 0.0)
+    fields = np.zeros((1, 3, mesh.K, Np))
+    fields[0, 0] = p0
+    y0 = pack_state(fields)[0]
+    nsteps = cfg["steps_per_slice"]
+    return SensitivityProblem(name=name, mesh=mesh, c0=c2_layered, gamma=cfg["gamma"],
+                              tau_p=cfg["tau"], tau_u=cfg["tau"], nq1=N + 2, S=cfg["S"],
+                              nsteps=nsteps, dt=cfg["T"] / (cfg["S"] * nsteps), y0=y0,
+                              p_target=np.ascontiguousarray(pt.T))
 
 
 @dataclass
