@@ -53,6 +53,27 @@ def stage_bytes(K, S, N, nq1):
     return K * (S * per_elem_slice + per_elem)
 
 
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated) from the
+    rocprofv3 counter runs recorded in profiles/hbm_traffic.json, or None when
+    there is no record for this kernel and workload or the kernel's sources
+    have changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    for rec in json.load(open(path))["records"]:
+        if rec["kernel"] != kernel or rec["workload"] != workload:
+            continue
+        h = hashlib.sha1()
+        for src in rec["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() == rec["sources_sha1"]:
+            return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    return None
+
+
 def cpu_baseline(prob, seconds):
     """The oracle, as it stands, on a bounded sample: whole slices of the same
     workload, one after another, on one host thread."""
@@ -143,7 +164,7 @@ def main():
     bytes_launch = stage_bytes(K, S, N, prob.nq1)
     achieved = bytes_launch / (stage_ms * 1e-3) / 1e9
 
-    traffic = None
+    traffic = measured_traffic(kname, prob.name)
     line = {
         "metric": "grid-point-steps/sec",
         "value": value,
