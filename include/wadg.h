@@ -69,6 +69,7 @@ extern "C" {
 #define WADG_KERNEL_RESIDENT 2  /* geometry held in LDS per element group    */
 
 typedef struct wadg_ctx_s* wadg_ctx;
+typedef struct wadg_batch_s* wadg_batch;
 
 /* Mesh and problem description.  All pointers are host memory, read during
  * the call only (the library copies what it needs).
@@ -224,6 +225,55 @@ int wadg_forward_checkpoints(wadg_ctx ctx, double* chk, void* work, int32_t S, d
                              int32_t nsteps, void* stream);
 int wadg_adjoint(wadg_ctx ctx, const double* chk, const double* seed, double* grad, void* work,
                  int32_t S, double dt, int32_t nsteps, double* dJ_dscale, void* stream);
+
+/* Batches of independent problems (many meshes of one degree, each with
+ * its own slices and dt), advanced together: one launch per LSRK stage
+ * covers every (problem, slice, 64-element group) work item -- Section 5.1's
+ * batching of elements per workgroup, taken across problems.
+ *
+ * wadg_batch_create: meshes[nprob] (host; all with the same N, nq1, tau_p,
+ *   tau_u; validated like wadg_create), S[nprob] slices per problem.  A mesh
+ *   of K <= 32 elements is stored as P = floor(64 / K) disjoint copies in
+ *   one 64-lane group, so that P slices share one work item.  Returns
+ *   WADG_E_GEOMETRY / WADG_E_INVALID naming the offending problem.
+ * wadg_batch_layout: offset[nprob + 1] (host out, int64) -- problem i
+ *   occupies doubles [offset[i], offset[i+1]) of the batch state;
+ *   pack[nprob] (host out) -- P_i.  Problem i is stored as ceil(S_i / P_i)
+ *   virtual slices in the tiled state layout of a virtual mesh of P_i K_i
+ *   elements: slice s is copy s % P_i of virtual slice s / P_i, and its
+ *   element k is virtual element (s % P_i) K_i + k.  Either pointer may be
+ *   NULL.
+ * wadg_batch_workspace_bytes: device workspace for integrate (2 states).
+ * wadg_batch_integrate: every problem advanced by nsteps LSRK steps of its
+ *   own dt[i] (host array, finite > 0), all slices at once.  Q (device):
+ *   the batch state, in/out; work: device workspace.  Asynchronous.
+ * wadg_batch_set_schedule: persistent workgroups per CU (1..64; 0 = one
+ *   workgroup per work item) and work-list order (0 problem-major, 1
+ *   round-robin over problems).  Results are bitwise independent of it.
+ *   Defaults 2, 0.
+ * wadg_batch_tune: the autotuner -- times one stage of every schedule
+ *   candidate (1, 2, 4, 8 workgroups per CU or one per item, both orders)
+ *   reps times on the device, keeps the fastest and returns it (host out:
+ *   wg_per_cu, order, best_us per stage).  Q is read only; work is scratch.
+ *   Synchronises `stream`.
+ * wadg_batch_capture: records the whole nsteps sweep of wadg_batch_integrate
+ *   for these Q, work and dt into a HIP graph (on a stream of its own);
+ *   wadg_batch_replay launches it on `stream` (each replay advances Q by
+ *   nsteps steps again).  wadg_batch_release_graph frees it; set_schedule
+ *   and tune refuse while a graph is held. */
+int wadg_batch_create(const wadg_mesh* meshes, int32_t nprob, const int32_t* S, int32_t device,
+                      wadg_batch* out);
+void wadg_batch_destroy(wadg_batch b);
+int wadg_batch_layout(wadg_batch b, int64_t* offset, int32_t* pack);
+int wadg_batch_workspace_bytes(wadg_batch b, size_t* bytes);
+int wadg_batch_integrate(wadg_batch b, double* Q, double* work, const double* dt, int32_t nsteps,
+                         void* stream);
+int wadg_batch_set_schedule(wadg_batch b, int32_t wg_per_cu, int32_t order);
+int wadg_batch_tune(wadg_batch b, const double* Q, double* work, const double* dt, int32_t reps,
+                    int32_t* wg_per_cu, int32_t* order, double* best_us, void* stream);
+int wadg_batch_capture(wadg_batch b, double* Q, double* work, const double* dt, int32_t nsteps);
+int wadg_batch_replay(wadg_batch b, void* stream);
+int wadg_batch_release_graph(wadg_batch b);
 
 /* Per-slice reductions (the norms the convergence checks use):
  *   out[s][0] = ||A_s - B_s||_2,  out[s][1] = ||B_s||_2,

@@ -15,4 +15,4 @@ from .binding import (  # noqa: F401
     WADG_KERNEL_RESIDENT, wadg_set_c2_scale, wadg_adjoint_workspace_bytes,
     wadg_forward_checkpoints, wadg_adjoint, wadg_status_string, wadg_last_error, MeshDesc, WadgError, tile_state, untile_state,
 )
-from .solver import Solver  # noqa: F401
+from .solver import Solver, Batch  # noqa: F401

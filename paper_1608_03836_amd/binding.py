@@ -85,6 +85,18 @@ def _load():
         "wadg_set_schedule": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32]),
         "wadg_set_kernel": (ctypes.c_int, [vp, ctypes.c_int32]),
         "wadg_set_c2_scale": (ctypes.c_int, [vp, ctypes.c_double]),
+        "wadg_batch_create": (ctypes.c_int, [ctypes.POINTER(wadg_mesh), ctypes.c_int32,
+                                             _c_int32_p, ctypes.c_int32, ctypes.POINTER(vp)]),
+        "wadg_batch_destroy": (None, [vp]),
+        "wadg_batch_layout": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int64), _c_int32_p]),
+        "wadg_batch_workspace_bytes": (ctypes.c_int, [vp, ctypes.POINTER(sz)]),
+        "wadg_batch_integrate": (ctypes.c_int, [vp, vp, vp, _c_double_p, ctypes.c_int32, vp]),
+        "wadg_batch_set_schedule": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32]),
+        "wadg_batch_tune": (ctypes.c_int, [vp, vp, vp, _c_double_p, ctypes.c_int32, _c_int32_p,
+                                           _c_int32_p, _c_double_p, vp]),
+        "wadg_batch_capture": (ctypes.c_int, [vp, vp, vp, _c_double_p, ctypes.c_int32]),
+        "wadg_batch_replay": (ctypes.c_int, [vp, vp]),
+        "wadg_batch_release_graph": (ctypes.c_int, [vp]),
         "wadg_adjoint_workspace_bytes": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.POINTER(sz)]),
         "wadg_forward_checkpoints": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, ctypes.c_double,
                                                     ctypes.c_int32, vp]),
@@ -108,7 +120,10 @@ EXPORTED = ("wadg_quadrature_points", "wadg_geometry", "wadg_create", "wadg_dest
             "wadg_parareal_workspace_bytes", "wadg_parareal",
             "wadg_norms", "wadg_set_schedule", "wadg_set_kernel", "wadg_kernel_in_use",
             "wadg_set_c2_scale", "wadg_adjoint_workspace_bytes", "wadg_forward_checkpoints",
-            "wadg_adjoint",
+            "wadg_adjoint", "wadg_batch_create", "wadg_batch_destroy", "wadg_batch_layout",
+            "wadg_batch_workspace_bytes", "wadg_batch_integrate", "wadg_batch_set_schedule",
+            "wadg_batch_tune", "wadg_batch_capture", "wadg_batch_replay",
+            "wadg_batch_release_graph",
             "wadg_status_string", "wadg_last_error")
 
 
@@ -295,6 +310,92 @@ def wadg_adjoint(ctx, chk, seed, grad, work, S, dt, nsteps, stream=None):
     _check(LIB.wadg_adjoint(ctx, _ptr(chk), _ptr(seed), _ptr(grad), _ptr(work), int(S),
                             float(dt), int(nsteps), ctypes.byref(out), _stream(stream)))
     return out.value
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_c_double_p)
+
+
+def wadg_batch_create(meshes, S, device=-1):
+    """meshes: list of MeshDesc (same N, nq1, tau); S: slices per problem."""
+    arr = (wadg_mesh * len(meshes))(*[m.struct() for m in meshes])
+    s = np.ascontiguousarray(S, dtype=np.int32)
+    h = ctypes.c_void_p()
+    _check(LIB.wadg_batch_create(arr, len(meshes), s.ctypes.data_as(_c_int32_p), int(device),
+                                 ctypes.byref(h)))
+    return h
+
+
+def wadg_batch_destroy(b):
+    LIB.wadg_batch_destroy(b)
+
+
+def wadg_batch_layout(b, nprob):
+    off = np.zeros(nprob + 1, dtype=np.int64)
+    pack = np.zeros(nprob, dtype=np.int32)
+    _check(LIB.wadg_batch_layout(b, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                 pack.ctypes.data_as(_c_int32_p)))
+    return off, pack
+
+
+def wadg_batch_workspace_bytes(b):
+    out = ctypes.c_size_t()
+    _check(LIB.wadg_batch_workspace_bytes(b, ctypes.byref(out)))
+    return out.value
+
+
+def wadg_batch_integrate(b, Q, work, dt, nsteps, stream=None):
+    d, dp = _f64(dt)
+    _check(LIB.wadg_batch_integrate(b, _ptr(Q), _ptr(work), dp, int(nsteps), _stream(stream)))
+
+
+def wadg_batch_set_schedule(b, wg_per_cu, order):
+    _check(LIB.wadg_batch_set_schedule(b, int(wg_per_cu), int(order)))
+
+
+def wadg_batch_tune(b, Q, work, dt, reps=3, stream=None):
+    d, dp = _f64(dt)
+    wg, order, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    _check(LIB.wadg_batch_tune(b, _ptr(Q), _ptr(work), dp, int(reps), ctypes.byref(wg),
+                               ctypes.byref(order), ctypes.byref(us), _stream(stream)))
+    return wg.value, order.value, us.value
+
+
+def wadg_batch_capture(b, Q, work, dt, nsteps):
+    d, dp = _f64(dt)
+    _check(LIB.wadg_batch_capture(b, _ptr(Q), _ptr(work), dp, int(nsteps)))
+
+
+def wadg_batch_replay(b, stream=None):
+    _check(LIB.wadg_batch_replay(b, _stream(stream)))
+
+
+def wadg_batch_release_graph(b):
+    _check(LIB.wadg_batch_release_graph(b))
+
+
+def pack_batch_problem(Qn, pack):
+    """Natural [S][3][Np][K] states of one problem -> its packed tiled
+    values ([ceil(S/P)] virtual slices of P side-by-side copies)."""
+    Qn = np.asarray(Qn, dtype=np.float64)
+    S, _, Np, K = Qn.shape
+    P = int(pack)
+    Sv = -(-S // P)
+    q = np.zeros((Sv * P, 3, Np, K))
+    q[:S] = Qn
+    q = q.reshape(Sv, P, 3, Np, K).transpose(0, 2, 3, 1, 4).reshape(Sv, 3, Np, P * K)
+    return tile_state(q).reshape(-1)
+
+
+def unpack_batch_problem(vals, S, K, Np, pack):
+    """Inverse of pack_batch_problem."""
+    P = int(pack)
+    Sv = -(-S // P)
+    G = -(-(P * K) // TILE_LANES)
+    q = untile_state(np.asarray(vals).reshape(Sv, G, 3, Np, TILE_LANES), P * K)
+    q = q.reshape(Sv, 3, Np, P, K).transpose(0, 3, 1, 2, 4).reshape(Sv * P, 3, Np, K)
+    return q[:S]
 
 
 def wadg_status_string(status):

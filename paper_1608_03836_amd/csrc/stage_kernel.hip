@@ -270,7 +270,96 @@ __global__ __launch_bounds__(2 * kWave) void stage_kernel(const StageParams p) {
     stage_wave<R, N, NQ, MODE, false>(k, B, tq, kb, lane, active, nbo, g0);
 }
 
+// Batched LSRK stage over a work list of (problem, slice, element group)
+// items of many independent problems: the same per-item work as
+// stage_kernel, the problem's state offset, geometry groups and dt taken
+// from its descriptor.  Persistent: workgroup w takes items w, w + grid, ...
+// (w XCD-remapped, so each XCD sweeps a contiguous range of the list at
+// every round); with grid = nitems it is one item per workgroup.
+template <int N, int NQ>
+__global__ __launch_bounds__(2 * kWave) void batch_stage_kernel(const BatchParams bp) {
+  using R = double;
+  constexpr int NP = (N + 1) * (N + 1);
+  constexpr int NQ2 = NQ * NQ;
+  constexpr unsigned tile = 3u * NP * kWave;
+  constexpr unsigned KP = kWave * sizeof(R);
+  constexpr unsigned chunks = tile * sizeof(R) / 16;
+  constexpr unsigned per_thread = (chunks + 2 * kWave - 1) / (2 * kWave);
+  __shared__ __attribute__((aligned(16))) R tq[tile];
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & (kWave - 1);
+  const unsigned kb = (unsigned)lane * sizeof(R);
+
+  for (int it = xcd_remap(blockIdx.x, gridDim.x); it < bp.nitems; it += gridDim.x) {
+    const int pi = bp.items[2 * it], local = bp.items[2 * it + 1];
+    const BatchProb pr = bp.prob[pi];
+    const int s = local / pr.nEG, eg = local - s * pr.nEG;
+    const size_t slice = (size_t)pr.qoff + (size_t)s * pr.nEG * tile;
+    const size_t grp = slice + (size_t)eg * tile;
+    const size_t gg = (size_t)pr.g0 + eg;
+    Bufs B;
+    B.qin = make_rsrc(bp.Qin + grp, tile * sizeof(R));
+    B.qout = make_rsrc(bp.Qout + grp, tile * sizeof(R));
+    B.res = make_rsrc(bp.res + grp, tile * sizeof(R));
+    B.resw = B.res;
+    B.qslice = make_rsrc(bp.Qin + slice, (unsigned)pr.nEG * tile * sizeof(R));
+    B.vol = make_rsrc(bp.vol + gg * 6 * NQ2 * kWave, 6u * NQ2 * KP);
+    B.face = make_rsrc(bp.face + gg * 12 * NQ * kWave, 12u * NQ * KP);
+    B.nbr = make_rsrc(bp.nbr + gg * 8 * kWave, 8u * kWave * 4u);
+
+    u32x4 v[per_thread];
+#pragma unroll
+    for (unsigned i = 0; i < per_thread; ++i) {
+      const unsigned c = tid + i * 2 * kWave;
+      if (c < chunks) v[i] = ld128(B.qin, c * 16u);
+    }
+    NbrOffsets nbo;
+    load_nbr(B.nbr, lane, nbo);
+    R g0[4][NQ];
+    load_metric_column<R, NQ>(B, 0, kb, g0);
+    order();
+#pragma unroll
+    for (unsigned i = 0; i < per_thread; ++i) {
+      const unsigned c = tid + i * 2 * kWave;
+      if (c < chunks) *reinterpret_cast<u32x4*>(reinterpret_cast<char*>(tq) + c * 16u) = v[i];
+    }
+    __syncthreads();
+
+    StageScalars<R> k;
+    k.tau_p = bp.tau_p;
+    k.tau_u = bp.tau_u;
+    k.A = bp.rkA;
+    k.B = bp.rkB;
+    k.dt = pr.dt;
+    k.c2s = 1.0;
+    const bool active = eg * kWave + lane < pr.K;
+    if (wave == 0)
+      stage_wave<R, N, NQ, kStage, true>(k, B, tq, kb, lane, active, nbo, g0);
+    else
+      stage_wave<R, N, NQ, kStage, false>(k, B, tq, kb, lane, active, nbo, g0);
+    __syncthreads();   // the tile is rewritten by the next item
+  }
+}
+
 namespace {
+
+template <int N, int NQ>
+int launch_batch_nq(const BatchParams& p, int grid, void* stream) {
+  hipLaunchKernelGGL((batch_stage_kernel<N, NQ>), dim3(grid), dim3(2 * kWave), 0,
+                     static_cast<hipStream_t>(stream), p);
+  return (int)hipGetLastError();
+}
+
+template <int N>
+int launch_batch_n(int nq, const BatchParams& p, int grid, void* stream) {
+  switch (nq - N) {
+    case 1: return launch_batch_nq<N, N + 1>(p, grid, stream);
+    case 2: return launch_batch_nq<N, N + 2>(p, grid, stream);
+    case 3: return launch_batch_nq<N, N + 3>(p, grid, stream);
+    default: return (int)hipErrorInvalidValue;
+  }
+}
 
 template <typename R, int N, int NQ>
 int launch_nq(int mode, const StageParams& p, void* stream) {
@@ -322,6 +411,17 @@ int launch_stage_streamed(int N, int nq, int mode, const StageParams& p, void* s
 
 int launch_stage_streamed_fp32(int N, int nq, const StageParams& p, void* stream) {
   return launch_r<float>(N, nq, kStage, p, stream);
+}
+
+int launch_batch_stage(int N, int nq, const BatchParams& p, int grid, void* stream) {
+  if (p.nitems <= 0) return 0;
+  switch (N) {
+    case 1: return launch_batch_n<1>(nq, p, grid, stream);
+    case 2: return launch_batch_n<2>(nq, p, grid, stream);
+    case 3: return launch_batch_n<3>(nq, p, grid, stream);
+    case 4: return launch_batch_n<4>(nq, p, grid, stream);
+    default: return (int)hipErrorInvalidValue;
+  }
 }
 
 }  // namespace wadg

@@ -119,6 +119,30 @@ int launch_to_fp32(const double* in, float* out, size_t n, void* stream);
 int launch_to_fp64(const float* in, double* out, size_t n, void* stream);
 bool stage_supported(int N, int nq);
 
+// Batched stage over many independent problems (same N, nq, penalties):
+// one work item = one 64-element group of one slice of one problem.
+struct BatchProb {
+  int64_t qoff;          // first value of the problem in the batch state arrays
+  int32_t nEG, S, K;     // element groups per slice, slices, elements (lanes in use)
+  int32_t g0;            // first element group of the problem in the geometry arrays
+  double dt;
+};
+struct BatchParams {
+  const BatchProb* prob;
+  const int32_t* items;  // [nitems][2]: problem, slice * nEG + group
+  int32_t nitems;
+  const double* Qin;
+  double* Qout;
+  double* res;
+  const double* vol;     // [all groups][6][Nq][64]
+  const double* face;    // [all groups][3][4][nq][64]
+  const int32_t* nbr;    // [all groups][2][4][64]
+  double tau_p, tau_u, rkA, rkB;
+};
+// grid = number of persistent workgroups (each loops over items with stride
+// grid), or nitems for one workgroup per item.
+int launch_batch_stage(int N, int nq, const BatchParams& p, int grid, void* stream);
+
 // Per-slice norms over the tiled layout (padding skipped): partial sums into
 // `partials` [S][nblk][4] then a fixed-order reduction into `out` [S][4].
 int launch_norms(const double* A, const double* B, int32_t S, int64_t n_per_slice, int32_t tile,

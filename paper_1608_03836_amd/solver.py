@@ -140,3 +140,84 @@ class Solver:
         work = self.adjoint_workspace(nsteps) if work is None else work
         d = B.wadg_adjoint(self.ctx, chk, seed.contiguous(), grad, work, S, dt, nsteps, stream)
         return grad, d
+
+
+class Batch:
+    """Many independent problems (same degree and quadrature) advanced
+    together through the batch C ABI.
+
+    ``meshes``: list of meshes (as for ``Solver``); ``S``: slices per
+    problem; ``c2``: optional callable evaluated at each mesh's volume
+    quadrature points.
+    """
+
+    def __init__(self, meshes, S, nq1=None, c2=None, tau_p=1.0, tau_u=1.0, device=0):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        N = int(meshes[0].N)
+        nq1 = N + 2 if nq1 is None else int(nq1)
+        descs = []
+        for m in meshes:
+            d = B.MeshDesc(N, nq1, m.x, m.y, m.etoe, m.etof, None, tau_p, tau_u)
+            if c2 is not None:
+                xq, yq = B.wadg_quadrature_points(d)
+                d = B.MeshDesc(N, nq1, m.x, m.y, m.etoe, m.etof,
+                               np.asarray(c2(xq, yq), dtype=np.float64), tau_p, tau_u)
+            descs.append(d)
+        self.N, self.nq1, self.Np = N, nq1, (N + 1) ** 2
+        self.S = [int(s) for s in S]
+        self.K = [d.K for d in descs]
+        with torch.cuda.device(self.device):
+            self.b = B.wadg_batch_create(descs, self.S, device)
+        self.offset, self.pack = B.wadg_batch_layout(self.b, len(descs))
+        self.total = int(self.offset[-1])
+
+    def close(self):
+        if getattr(self, "b", None) is not None:
+            B.wadg_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self):
+        n = B.wadg_batch_workspace_bytes(self.b) // 8
+        return self.torch.empty(n, dtype=self.torch.float64, device=self.device)
+
+    def upload(self, Q0):
+        """Q0: list of natural [S_i][3][Np][K_i] host arrays -> batch state."""
+        h = np.zeros(self.total)
+        for i, q in enumerate(Q0):
+            h[self.offset[i]:self.offset[i + 1]] = B.pack_batch_problem(q, self.pack[i])
+        return self.torch.from_numpy(h).to(self.device)
+
+    def download(self, Q, which=None):
+        h = Q.detach().cpu().numpy()
+        idx = range(len(self.S)) if which is None else which
+        return [B.unpack_batch_problem(h[self.offset[i]:self.offset[i + 1]], self.S[i], self.K[i],
+                                       self.Np, self.pack[i]) for i in idx]
+
+    def integrate(self, Q, dt, nsteps, work=None, stream=None):
+        work = self.workspace() if work is None else work
+        B.wadg_batch_integrate(self.b, Q, work, dt, nsteps, stream)
+        return Q
+
+    def set_schedule(self, wg_per_cu, order=0):
+        B.wadg_batch_set_schedule(self.b, wg_per_cu, order)
+
+    def tune(self, Q, dt, work=None, reps=3, stream=None):
+        work = self.workspace() if work is None else work
+        return B.wadg_batch_tune(self.b, Q, work, dt, reps, stream)
+
+    def capture(self, Q, work, dt, nsteps):
+        B.wadg_batch_capture(self.b, Q, work, dt, nsteps)
+
+    def replay(self, stream=None):
+        B.wadg_batch_replay(self.b, stream)
+
+    def release_graph(self):
+        B.wadg_batch_release_graph(self.b)

@@ -19,4 +19,5 @@ from .fields import (  # noqa: F401
     c2_constant, c2_layered, pack_state, unpack_state, heat_initial,
 )
 from .configs import (CONFIGS, SENSITIVITY, make_problem, make_heat_problem,  # noqa: F401
-                      make_sensitivity_problem, SensitivityProblem)
+                      make_sensitivity_problem, SensitivityProblem, BATCHES, BatchMember,
+                      batch_shapes, make_batch)

@@ -28,6 +28,14 @@ together.
            p_target)^2.
   adj4     the same on 4x4 elements, S=3 slices of 2 steps (dt = 0.01),
            8 modes (seeds 5 and 6), gamma = 1.3 (oracle-sized).
+  batch1000  1000 independent acoustic problems, N=3, eps=0.05, c^2=1,
+           tau=1: nodes per field n ~ log-uniform[64, 4096] -> K1D =
+           clip(round(sqrt(n)/4), 2, 16); S ~ U{8..128} slices of 4 steps,
+           dt = 0.025/K1D (CFL 0.4); p = 4 lowest standing waves with
+           a ~ N(0,1), phi ~ U[0, 2 pi) from the problem's spawned generator;
+           slice s starts from the exact solution at t = 4 s dt.  Draw order
+           from default_rng(4): all n, then all S, then one spawned child
+           per problem.
 """
 
 from dataclasses import dataclass, field
@@ -37,7 +45,7 @@ import numpy as np
 
 from .mesh import periodic_quad_mesh, QuadMesh
 from .fields import (smooth_pressure, uniform_pressure, c2_constant, c2_layered,
-                     pack_state, heat_initial)
+                     pack_state, heat_initial, wave_modes, PlaneWaveSolution)
 
 
 CONFIGS = {
@@ -170,3 +178,58 @@ def make_heat_problem(name="heat64"):
     return dict(y0=y0, amps=amps, phases=phases, n=cfg["n"], T=cfg["T"],
                 slices=cfg["slices"], steps_per_slice=cfg["steps_per_slice"],
                 dt=cfg["T"] / total_steps)
+
+
+BATCHES = {
+    "batch1000": dict(count=1000, N=3, eps=0.05, tau=1.0, nodes=(64, 4096), K1D=(2, 16),
+                      S=(8, 128), steps_per_slice=4, modes=4, cfl=0.4, seed=4),
+}
+
+
+@dataclass
+class BatchMember:
+    mesh: QuadMesh
+    S: int
+    dt: float
+    nsteps: int
+    Q0: np.ndarray              # [S][3][Np][K] start states
+    exact: object
+
+
+def batch_shapes(name="batch1000", count=None):
+    """(K1D, S) of every problem of the batch, without building anything."""
+    cfg = BATCHES[name]
+    n = cfg["count"] if count is None else count
+    rng = np.random.default_rng(cfg["seed"])
+    lo, hi = np.log(cfg["nodes"][0]), np.log(cfg["nodes"][1])
+    nodes = np.exp(rng.uniform(lo, hi, cfg["count"]))
+    S = rng.integers(cfg["S"][0], cfg["S"][1] + 1, cfg["count"])
+    k1d = np.clip(np.round(np.sqrt(nodes) / 4.0), cfg["K1D"][0], cfg["K1D"][1]).astype(int)
+    return k1d[:n], S[:n], rng
+
+
+def make_batch(name="batch1000", count=None, members=None):
+    """Build the batch (or its first ``count`` problems, or the problems with
+    the indices in ``members``).  Every problem draws from its own spawned
+    generator, so a subset is identical to the same problems of the full
+    batch."""
+    cfg = BATCHES[name]
+    k1d, S, rng = batch_shapes(name)
+    children = rng.spawn(cfg["count"])
+    idx = range(cfg["count"] if count is None else count) if members is None else members
+    out = []
+    for i in idx:
+        mesh = periodic_quad_mesh(int(k1d[i]), cfg["N"], eps=cfg["eps"])
+        r = children[i]
+        modes = wave_modes(cfg["modes"])
+        amps = r.standard_normal(cfg["modes"])
+        phases = r.uniform(0.0, 2.0 * np.pi, cfg["modes"])
+        exact = PlaneWaveSolution(modes, amps, phases)
+        dt = cfg["cfl"] / ((cfg["N"] + 1) ** 2 * int(k1d[i]))
+        nsteps = cfg["steps_per_slice"]
+        fields = np.zeros((int(S[i]), 3, mesh.K, (cfg["N"] + 1) ** 2))
+        for s in range(int(S[i])):
+            fields[s] = np.stack(exact(mesh.x, mesh.y, s * nsteps * dt))
+        out.append(BatchMember(mesh=mesh, S=int(S[i]), dt=dt, nsteps=nsteps,
+                               Q0=pack_state(fields), exact=exact))
+    return out
