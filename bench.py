@@ -119,7 +119,7 @@ def main():
         sol.set_schedule(args.tile_groups, args.tile_slices)
     sol.set_kernel({"auto": W.WADG_KERNEL_AUTO, "streamed": W.WADG_KERNEL_STREAMED,
                     "resident": W.WADG_KERNEL_RESIDENT}[args.kernel])
-    resident = sol.kernel_in_use() == W.WADG_KERNEL_RESIDENT
+    resident = sol.kernel_in_use(prob.S) == W.WADG_KERNEL_RESIDENT
     kname = ("resident_kernel" if resident else "stage_kernel") + f"<double,{prob.N},{prob.nq1},false>"
     S, K, N = prob.S, prob.K, prob.N
     Q = sol.upload(prob.Q0)

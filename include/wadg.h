@@ -301,18 +301,22 @@ int wadg_set_schedule(wadg_ctx ctx, int32_t groups_per_tile, int32_t slices_per_
  * memory for each; it follows wadg_set_schedule.  WADG_KERNEL_RESIDENT
  * launches 256-thread workgroups that each hold one element group's
  * geometry in LDS (up to 160 KiB) and sweep a range of its slices; it
- * ignores wadg_set_schedule.  WADG_KERNEL_AUTO (default) takes the resident
- * kernel wherever the geometry fits (FP64: N <= 2, or N = 3 with
- * nq1 <= 5; the FP32-bulk propagator decides separately, with its smaller
- * footprint).  All variants give bitwise-identical results.  Returns
- * WADG_E_INVALID for an unknown value and WADG_E_UNSUPPORTED when the
- * resident kernel is requested for an (N, nq1) whose FP64 geometry does
- * not fit. */
+ * ignores wadg_set_schedule.  WADG_KERNEL_AUTO (default): FP64 launches
+ * take the resident kernel where the geometry fits (N <= 2, or N = 3 with
+ * nq1 <= 5) and each pair of its waves sweeps at least 16 slices (a pair
+ * sweeps ceil(ceil(S / R) / 2) slices, with R = min(max(1, CUs / G),
+ * ceil(S / 2)) slice ranges per element group and G = ceil(K / 64)), else
+ * the streamed one; FP32-bulk launches take the streamed kernel (an explicit
+ * WADG_KERNEL_RESIDENT applies to them too).  All variants give
+ * bitwise-identical results.  Returns WADG_E_INVALID for an unknown value
+ * and WADG_E_UNSUPPORTED when the resident kernel is requested for an
+ * (N, nq1) whose FP64 geometry does not fit. */
 int wadg_set_kernel(wadg_ctx ctx, int32_t kernel);
 
-/* The kernel variant the stage launches of `ctx` use: for the FP64 path
- * (fp32 == 0) or the FP32-bulk path (fp32 != 0).  kernel: host out. */
-int wadg_kernel_in_use(wadg_ctx ctx, int32_t fp32, int32_t* kernel);
+/* The kernel variant the stage launches of `ctx` over S slices use, for the
+ * FP64 path (fp32 == 0) or the FP32-bulk path (fp32 != 0).  kernel: host
+ * out. */
+int wadg_kernel_in_use(wadg_ctx ctx, int32_t S, int32_t fp32, int32_t* kernel);
 
 /* Static description of a status code; never NULL. */
 const char* wadg_status_string(int status);

@@ -102,7 +102,8 @@ def _load():
                                                     ctypes.c_int32, vp]),
         "wadg_adjoint": (ctypes.c_int, [vp, vp, vp, vp, vp, ctypes.c_int32, ctypes.c_double,
                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_double), vp]),
-        "wadg_kernel_in_use": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+        "wadg_kernel_in_use": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.POINTER(ctypes.c_int32)]),
         "wadg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "wadg_last_error": (ctypes.c_char_p, []),
     }
@@ -283,9 +284,9 @@ def wadg_set_kernel(ctx, kernel):
     _check(LIB.wadg_set_kernel(ctx, int(kernel)))
 
 
-def wadg_kernel_in_use(ctx, fp32=False):
+def wadg_kernel_in_use(ctx, S, fp32=False):
     out = ctypes.c_int32()
-    _check(LIB.wadg_kernel_in_use(ctx, 1 if fp32 else 0, ctypes.byref(out)))
+    _check(LIB.wadg_kernel_in_use(ctx, int(S), 1 if fp32 else 0, ctypes.byref(out)))
     return out.value
 
 

@@ -135,15 +135,29 @@ int check_slices(wadg_ctx c, int32_t S) {
   return WADG_OK;
 }
 
-// Kernel variant that runs for this context and precision.
-int kernel_path(wadg_ctx c, bool fp32) {
+// Slices each resident pair sweeps per launch at which the resident kernel's
+// once-per-workgroup geometry load is amortised (measured crossover).
+constexpr int kResidentMinItems = 16;
+
+// Kernel variant that runs for this context, precision and slice count.
+// Automatic choice: FP64 takes the resident-geometry kernel where the
+// geometry fits in LDS and each pair of waves sweeps at least
+// kResidentMinItems slices; FP32-bulk takes the streamed kernel (faster on
+// every measured workload: half-size tiles leave LDS and registers for two
+// waves per SIMD).
+int kernel_path(wadg_ctx c, bool fp32, int32_t S) {
   const bool fits = wadg::resident_supported(c->N, c->nq1, fp32);
   if (c->kernel == WADG_KERNEL_STREAMED || !fits) return WADG_KERNEL_STREAMED;
-  return WADG_KERNEL_RESIDENT;
+  if (c->kernel == WADG_KERNEL_RESIDENT) return WADG_KERNEL_RESIDENT;
+  if (fp32) return WADG_KERNEL_STREAMED;
+  const int nEG = c->groups();
+  const int ranges = wadg::resident_ranges(nEG, S, c->cus);
+  const int spr = (S + ranges - 1) / ranges;
+  return (spr + 1) / 2 >= kResidentMinItems ? WADG_KERNEL_RESIDENT : WADG_KERNEL_STREAMED;
 }
 
 int launch_stage(wadg_ctx c, int mode, bool fp32, const wadg::StageParams& p, void* stream) {
-  if (mode != wadg::kApplyA && kernel_path(c, fp32) == WADG_KERNEL_RESIDENT) {
+  if (mode != wadg::kApplyA && kernel_path(c, fp32, p.S) == WADG_KERNEL_RESIDENT) {
     const int ranges = wadg::resident_ranges(p.nEG, p.S, c->cus);
     return fp32 ? wadg::launch_stage_resident_fp32(c->N, c->nq1, p, ranges, stream)
                 : wadg::launch_stage_resident(c->N, c->nq1, mode, p, ranges, stream);
@@ -306,10 +320,11 @@ int wadg_set_c2_scale(wadg_ctx ctx, double scale) {
   return WADG_OK;
 }
 
-int wadg_kernel_in_use(wadg_ctx ctx, int32_t fp32, int32_t* kernel) {
+int wadg_kernel_in_use(wadg_ctx ctx, int32_t S, int32_t fp32, int32_t* kernel) {
   if (!ctx) return fail(WADG_E_INVALID, "context is NULL");
   if (!kernel) return fail(WADG_E_INVALID, "kernel is NULL");
-  *kernel = kernel_path(ctx, fp32 != 0);
+  if (S < 1) return fail(WADG_E_INVALID, "S must be >= 1");
+  *kernel = kernel_path(ctx, fp32 != 0, S);
   return WADG_OK;
 }
 

@@ -50,7 +50,8 @@ def test_streamed_and_resident_bitwise(W, N, dq, K1D, S, nsteps):
     out = {}
     for kern in (W.WADG_KERNEL_STREAMED, W.WADG_KERNEL_RESIDENT):
         sol.set_kernel(kern)
-        assert sol.kernel_in_use() == kern
+        assert sol.kernel_in_use(S) == kern
+        assert sol.kernel_in_use(S, fp32=True) == kern
         Q = sol.upload(Q0)
         sol.integrate(Q, S, dt, nsteps)
         dQ = sol.rhs(sol.upload(Q0), S)
@@ -70,7 +71,8 @@ def test_resident_matches_oracle_many_slices_per_pair(W):
     S, nsteps, dt = 40, 2, 0.1 / (32 * 16)
     Q0 = _states(mesh, S, seed=9)
     sol = W.Solver(mesh, c2=c2_layered)
-    assert sol.kernel_in_use() == W.WADG_KERNEL_RESIDENT
+    sol.set_kernel(W.WADG_KERNEL_RESIDENT)
+    assert sol.kernel_in_use(S) == W.WADG_KERNEL_RESIDENT
     Q = sol.upload(Q0)
     sol.integrate(Q, S, dt, nsteps)
     got = sol.download(Q, S)
@@ -82,19 +84,29 @@ def test_resident_matches_oracle_many_slices_per_pair(W):
 
 
 def test_kernel_selection_rules(W):
-    """AUTO takes the resident kernel where the FP64 geometry fits in LDS
-    (N = 3 with nq1 <= 5) and the streamed one otherwise; requesting the
-    resident kernel where it does not fit is rejected."""
+    """AUTO: FP64 takes the resident kernel where the geometry fits in LDS
+    (N = 3 with nq1 <= 5) and each pair sweeps >= 16 slices (64 x 64
+    elements: 64 groups x 4 slice ranges of ceil(S / 4) slices, so
+    S >= 121), else the streamed kernel; FP32-bulk takes the streamed
+    kernel.  An explicit choice
+    applies to both precisions; the resident kernel is refused where the
+    FP64 geometry does not fit."""
     _print_case(test="kernel-selection")
-    mesh3 = periodic_quad_mesh(4, 3, eps=0.05, warp="skew")
-    s5 = W.Solver(mesh3, nq1=5)
-    assert s5.kernel_in_use() == W.WADG_KERNEL_RESIDENT
-    assert s5.kernel_in_use(fp32=True) == W.WADG_KERNEL_RESIDENT
-    s6 = W.Solver(mesh3, nq1=6)
-    assert s6.kernel_in_use() == W.WADG_KERNEL_STREAMED
-    assert s6.kernel_in_use(fp32=True) == W.WADG_KERNEL_RESIDENT
+    mesh = periodic_quad_mesh(64, 3, eps=0.05, warp="skew")
+    s5 = W.Solver(mesh, nq1=5)
+    assert s5.kernel_in_use(64) == W.WADG_KERNEL_STREAMED
+    assert s5.kernel_in_use(120) == W.WADG_KERNEL_STREAMED
+    assert s5.kernel_in_use(121) == W.WADG_KERNEL_RESIDENT
+    assert s5.kernel_in_use(128) == W.WADG_KERNEL_RESIDENT
+    assert s5.kernel_in_use(128, fp32=True) == W.WADG_KERNEL_STREAMED
+    s5.set_kernel(W.WADG_KERNEL_RESIDENT)
+    assert s5.kernel_in_use(1) == W.WADG_KERNEL_RESIDENT
+    assert s5.kernel_in_use(1, fp32=True) == W.WADG_KERNEL_RESIDENT
+    s5.set_kernel(W.WADG_KERNEL_STREAMED)
+    assert s5.kernel_in_use(1000) == W.WADG_KERNEL_STREAMED
+    small = periodic_quad_mesh(4, 3, eps=0.05, warp="skew")
+    s6 = W.Solver(small, nq1=6)
+    assert s6.kernel_in_use(1000) == W.WADG_KERNEL_STREAMED
     with pytest.raises(W.WadgError) as e:
         s6.set_kernel(W.WADG_KERNEL_RESIDENT)
     assert e.value.status == W.binding.WADG_E_UNSUPPORTED
-    s5.set_kernel(W.WADG_KERNEL_STREAMED)
-    assert s5.kernel_in_use() == W.WADG_KERNEL_STREAMED
