@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--tile-groups", type=int, default=None,
                     help="schedule: element groups per tile (default: library default)")
     ap.add_argument("--tile-slices", type=int, default=0)
-    ap.add_argument("--kernel", choices=("auto", "streamed", "resident"), default="auto",
+    ap.add_argument("--kernel", choices=("auto", "streamed", "resident", "split"), default="auto",
                     help="stage-kernel variant (default: the library's choice)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size before the timed "
@@ -118,9 +118,10 @@ def main():
     if args.tile_groups:
         sol.set_schedule(args.tile_groups, args.tile_slices)
     sol.set_kernel({"auto": W.WADG_KERNEL_AUTO, "streamed": W.WADG_KERNEL_STREAMED,
-                    "resident": W.WADG_KERNEL_RESIDENT}[args.kernel])
-    resident = sol.kernel_in_use(prob.S) == W.WADG_KERNEL_RESIDENT
-    kname = ("resident_kernel" if resident else "stage_kernel") + f"<double,{prob.N},{prob.nq1},false>"
+                    "resident": W.WADG_KERNEL_RESIDENT, "split": W.WADG_KERNEL_SPLIT}[args.kernel])
+    kname = {W.WADG_KERNEL_STREAMED: "stage_kernel", W.WADG_KERNEL_RESIDENT: "resident_kernel",
+             W.WADG_KERNEL_SPLIT: "split_kernel"}[sol.kernel_in_use()]
+    kname += f"<double,{prob.N},{prob.nq1},false>"
     S, K, N = prob.S, prob.K, prob.N
     Q = sol.upload(prob.Q0)
     work = sol.workspace(S)

@@ -67,6 +67,7 @@ extern "C" {
 #define WADG_KERNEL_AUTO 0      /* resident where it fits, else streamed      */
 #define WADG_KERNEL_STREAMED 1  /* geometry read from global memory per item */
 #define WADG_KERNEL_RESIDENT 2  /* geometry held in LDS per element group    */
+#define WADG_KERNEL_SPLIT 3     /* one work item over four waves            */
 
 typedef struct wadg_ctx_s* wadg_ctx;
 typedef struct wadg_batch_s* wadg_batch;
@@ -296,27 +297,31 @@ int wadg_norms(wadg_ctx ctx, const double* A, const double* B, int32_t S, double
 int wadg_set_schedule(wadg_ctx ctx, int32_t groups_per_tile, int32_t slices_per_tile);
 
 /* Tuning: which stage kernel runs (Section 5.4's volume, surface and update
- * kernels, fused).  WADG_KERNEL_STREAMED launches one 128-thread workgroup
- * per (slice, 64-element group) and reads the group's geometry from global
- * memory for each; it follows wadg_set_schedule.  WADG_KERNEL_RESIDENT
- * launches 256-thread workgroups that each hold one element group's
- * geometry in LDS (up to 160 KiB) and sweep a range of its slices; it
- * ignores wadg_set_schedule.  WADG_KERNEL_AUTO (default): FP64 launches
- * take the resident kernel where the geometry fits (N <= 2, or N = 3 with
- * nq1 <= 5) and each pair of its waves sweeps at least 16 slices (a pair
- * sweeps ceil(ceil(S / R) / 2) slices, with R = min(max(1, CUs / G),
- * ceil(S / 2)) slice ranges per element group and G = ceil(K / 64)), else
- * the streamed one; FP32-bulk launches take the streamed kernel (an explicit
- * WADG_KERNEL_RESIDENT applies to them too).  All variants give
- * bitwise-identical results.  Returns WADG_E_INVALID for an unknown value
- * and WADG_E_UNSUPPORTED when the resident kernel is requested for an
- * (N, nq1) whose FP64 geometry does not fit. */
+ * kernels, fused).
+ *   WADG_KERNEL_STREAMED: one 128-thread workgroup (two waves) per (slice,
+ *     64-element group), the group's geometry read from global memory for
+ *     each; follows wadg_set_schedule.
+ *   WADG_KERNEL_SPLIT: the same work item over a 256-thread workgroup of
+ *     four waves (pressure volume, velocity volume, two face waves), two
+ *     workgroups per CU; follows wadg_set_schedule.
+ *   WADG_KERNEL_RESIDENT: 256-thread workgroups that each hold one element
+ *     group's geometry in LDS (up to 160 KiB) and sweep a range of its
+ *     slices; ignores wadg_set_schedule.  Its FP64 geometry fits for N <= 2,
+ *     or N = 3 with nq1 <= 5; elsewhere a RESIDENT request falls back to
+ *     the streamed kernel for that precision.
+ *   WADG_KERNEL_AUTO (default): LSRK stages (FP64 and FP32) take the split
+ *     kernel, right-hand-side launches the resident kernel where it fits,
+ *     else the split kernel -- the fastest measured on MI355X.
+ * All variants give bitwise-identical results.  The adjoint's operator
+ * launches always use the streamed kernel.  Returns WADG_E_INVALID for an
+ * unknown value and WADG_E_UNSUPPORTED when the resident kernel is
+ * requested for an (N, nq1) whose FP64 geometry does not fit. */
 int wadg_set_kernel(wadg_ctx ctx, int32_t kernel);
 
-/* The kernel variant the stage launches of `ctx` over S slices use, for the
- * FP64 path (fp32 == 0) or the FP32-bulk path (fp32 != 0).  kernel: host
- * out. */
-int wadg_kernel_in_use(wadg_ctx ctx, int32_t S, int32_t fp32, int32_t* kernel);
+/* The kernel variant that `ctx` launches for LSRK stages (rhs == 0; FP64
+ * for fp32 == 0, FP32-bulk for fp32 != 0) or for wadg_rhs (rhs != 0,
+ * fp32 == 0).  kernel: host out. */
+int wadg_kernel_in_use(wadg_ctx ctx, int32_t rhs, int32_t fp32, int32_t* kernel);
 
 /* Static description of a status code; never NULL. */
 const char* wadg_status_string(int status);

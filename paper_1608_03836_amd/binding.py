@@ -28,6 +28,7 @@ WADG_MAX_N = 4
 WADG_KERNEL_AUTO = 0
 WADG_KERNEL_STREAMED = 1
 WADG_KERNEL_RESIDENT = 2
+WADG_KERNEL_SPLIT = 3
 TILE_LANES = 64
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
@@ -284,9 +285,9 @@ def wadg_set_kernel(ctx, kernel):
     _check(LIB.wadg_set_kernel(ctx, int(kernel)))
 
 
-def wadg_kernel_in_use(ctx, S, fp32=False):
+def wadg_kernel_in_use(ctx, rhs=False, fp32=False):
     out = ctypes.c_int32()
-    _check(LIB.wadg_kernel_in_use(ctx, int(S), 1 if fp32 else 0, ctypes.byref(out)))
+    _check(LIB.wadg_kernel_in_use(ctx, 1 if rhs else 0, 1 if fp32 else 0, ctypes.byref(out)))
     return out.value
 
 

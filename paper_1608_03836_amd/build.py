@@ -14,7 +14,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libwadg.so")
 
-SOURCES = ["reference.cpp", "stage_kernel.hip", "resident_kernel.hip", "adjoint_kernel.hip",
+SOURCES = ["reference.cpp", "stage_kernel.hip", "resident_kernel.hip", "split_kernel.hip",
+           "adjoint_kernel.hip",
            "norms_kernel.hip", "convert_kernel.hip", "parareal_kernel.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -27,16 +28,30 @@ FLAGS = [
 ]
 
 
-def build(verbose=False, extra_flags=()):
-    """Compile every source into ``libwadg.so`` next to this file.  Always
-    recompiles; raises CalledProcessError on failure."""
-    srcs = []
-    for s in SOURCES:
-        path = os.path.join(CSRC, s)
-        # .cpp host sources are compiled as HIP too (one toolchain, one link)
-        srcs += ["-x", "hip", path] if s.endswith(".cpp") else [path]
+def build(verbose=False, extra_flags=(), jobs=None):
+    """Compile every source into ``libwadg.so`` next to this file: one
+    relocatable device-and-host object per source, compiled in parallel, then
+    one link.  Always recompiles; raises CalledProcessError on failure."""
+    from concurrent.futures import ThreadPoolExecutor
+    objdir = os.path.join(PKG, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    common = [f for f in FLAGS if f != "-shared"] + list(extra_flags) + ["-I", INCLUDE, "-I", CSRC]
+
+    def compile_one(src):
+        path = os.path.join(CSRC, src)
+        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
+        lang = ["-x", "hip"] if src.endswith(".cpp") else []
+        cmd = [HIPCC] + common + ["-c"] + lang + [path, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        return obj
+
+    n = jobs or min(len(SOURCES), max(1, os.cpu_count() or 1))
+    with ThreadPoolExecutor(max_workers=n) as ex:
+        objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + list(extra_flags) + ["-I", INCLUDE, "-I", CSRC] + srcs + ["-o", tmp]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

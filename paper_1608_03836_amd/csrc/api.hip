@@ -135,29 +135,28 @@ int check_slices(wadg_ctx c, int32_t S) {
   return WADG_OK;
 }
 
-// Slices each resident pair sweeps per launch at which the resident kernel's
-// once-per-workgroup geometry load is amortised (measured crossover).
-constexpr int kResidentMinItems = 16;
-
-// Kernel variant that runs for this context, precision and slice count.
-// Automatic choice: FP64 takes the resident-geometry kernel where the
-// geometry fits in LDS and each pair of waves sweeps at least
-// kResidentMinItems slices; FP32-bulk takes the streamed kernel (faster on
-// every measured workload: half-size tiles leave LDS and registers for two
-// waves per SIMD).
-int kernel_path(wadg_ctx c, bool fp32, int32_t S) {
+// Kernel variant that runs for this context, precision and launch mode.
+// Automatic choice, from measurement on MI355X (64x64 and 128x128
+// elements, N = 3, FP64 and FP32): LSRK stages take the split-work kernel;
+// right-hand-side launches take the resident-geometry kernel where the
+// geometry fits in LDS, else the split-work kernel.  (The apply-A mode of
+// the adjoint exists in the streamed kernel only.)
+int kernel_path(wadg_ctx c, bool fp32, int mode) {
   const bool fits = wadg::resident_supported(c->N, c->nq1, fp32);
-  if (c->kernel == WADG_KERNEL_STREAMED || !fits) return WADG_KERNEL_STREAMED;
-  if (c->kernel == WADG_KERNEL_RESIDENT) return WADG_KERNEL_RESIDENT;
-  if (fp32) return WADG_KERNEL_STREAMED;
-  const int nEG = c->groups();
-  const int ranges = wadg::resident_ranges(nEG, S, c->cus);
-  const int spr = (S + ranges - 1) / ranges;
-  return (spr + 1) / 2 >= kResidentMinItems ? WADG_KERNEL_RESIDENT : WADG_KERNEL_STREAMED;
+  if (mode == wadg::kApplyA) return WADG_KERNEL_STREAMED;
+  if (c->kernel == WADG_KERNEL_RESIDENT && fits) return WADG_KERNEL_RESIDENT;
+  if (c->kernel != WADG_KERNEL_AUTO) return c->kernel == WADG_KERNEL_RESIDENT
+                                                ? WADG_KERNEL_STREAMED : c->kernel;
+  if (mode == wadg::kRhs && fits) return WADG_KERNEL_RESIDENT;
+  return WADG_KERNEL_SPLIT;
 }
 
 int launch_stage(wadg_ctx c, int mode, bool fp32, const wadg::StageParams& p, void* stream) {
-  if (mode != wadg::kApplyA && kernel_path(c, fp32, p.S) == WADG_KERNEL_RESIDENT) {
+  const int path = kernel_path(c, fp32, mode);
+  if (path == WADG_KERNEL_SPLIT)
+    return fp32 ? wadg::launch_stage_split_fp32(c->N, c->nq1, p, stream)
+                : wadg::launch_stage_split(c->N, c->nq1, mode, p, stream);
+  if (path == WADG_KERNEL_RESIDENT) {
     const int ranges = wadg::resident_ranges(p.nEG, p.S, c->cus);
     return fp32 ? wadg::launch_stage_resident_fp32(c->N, c->nq1, p, ranges, stream)
                 : wadg::launch_stage_resident(c->N, c->nq1, mode, p, ranges, stream);
@@ -304,7 +303,7 @@ int wadg_set_schedule(wadg_ctx ctx, int32_t groups_per_tile, int32_t slices_per_
 int wadg_set_kernel(wadg_ctx ctx, int32_t kernel) {
   if (!ctx) return fail(WADG_E_INVALID, "context is NULL");
   if (kernel != WADG_KERNEL_AUTO && kernel != WADG_KERNEL_STREAMED &&
-      kernel != WADG_KERNEL_RESIDENT)
+      kernel != WADG_KERNEL_RESIDENT && kernel != WADG_KERNEL_SPLIT)
     return fail(WADG_E_INVALID, "unknown kernel variant");
   if (kernel == WADG_KERNEL_RESIDENT && !wadg::resident_supported(ctx->N, ctx->nq1, false))
     return fail(WADG_E_UNSUPPORTED, "the element group's geometry does not fit in LDS");
@@ -320,11 +319,11 @@ int wadg_set_c2_scale(wadg_ctx ctx, double scale) {
   return WADG_OK;
 }
 
-int wadg_kernel_in_use(wadg_ctx ctx, int32_t S, int32_t fp32, int32_t* kernel) {
+int wadg_kernel_in_use(wadg_ctx ctx, int32_t rhs, int32_t fp32, int32_t* kernel) {
   if (!ctx) return fail(WADG_E_INVALID, "context is NULL");
   if (!kernel) return fail(WADG_E_INVALID, "kernel is NULL");
-  if (S < 1) return fail(WADG_E_INVALID, "S must be >= 1");
-  *kernel = kernel_path(ctx, fp32 != 0, S);
+  if (rhs && fp32) return fail(WADG_E_INVALID, "there is no FP32 right-hand-side launch");
+  *kernel = kernel_path(ctx, fp32 != 0, rhs ? wadg::kRhs : wadg::kStage);
   return WADG_OK;
 }
 
@@ -374,9 +373,10 @@ int wadg_integrate(wadg_ctx ctx, double* Q, double* work, int32_t S, double dt, 
       if (e) return hip_fail((hipError_t)e, "stage kernel launch");
       cur = static_cast<double*>(p.Qout);
     }
-  if (cur != Q)
-    WADG_HIP(hipMemcpyAsync(Q, cur, n * sizeof(double), hipMemcpyDeviceToDevice,
-                            static_cast<hipStream_t>(stream)));
+  if (cur != Q) {
+    int e = wadg::launch_copy(cur, Q, n, stream);
+    if (e) return hip_fail((hipError_t)e, "copy kernel launch");
+  }
   return WADG_OK;
 }
 
@@ -796,9 +796,10 @@ int batch_sweep(wadg_batch b, double* Q, double* work, int32_t nsteps, void* str
       if (st) return st;
       cur = out;
     }
-  if (cur != Q)
-    WADG_HIP(hipMemcpyAsync(Q, cur, n * sizeof(double), hipMemcpyDeviceToDevice,
-                            static_cast<hipStream_t>(stream)));
+  if (cur != Q) {   // a kernel, not a runtime copy: the sweep is captured into graphs
+    int e = wadg::launch_copy(cur, Q, n, stream);
+    if (e) return hip_fail((hipError_t)e, "copy kernel launch");
+  }
   return WADG_OK;
 }
 

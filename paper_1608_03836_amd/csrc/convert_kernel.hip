@@ -1,5 +1,7 @@
 // Precision conversion between the FP64 boundary state and the FP32 copy the
-// FP32-bulk propagator advances (same tiled layout, elementwise).
+// FP32-bulk propagator advances (same tiled layout, elementwise), and the
+// plain FP64 copy a sweep with an odd number of stages ends with (a kernel,
+// so that a captured sweep holds kernel nodes only).
 
 #include <hip/hip_runtime.h>
 
@@ -32,6 +34,9 @@ int launch_to_fp32(const double* in, float* out, size_t n, void* stream) {
   return launch(in, out, n, stream);
 }
 int launch_to_fp64(const float* in, double* out, size_t n, void* stream) {
+  return launch(in, out, n, stream);
+}
+int launch_copy(const double* in, double* out, size_t n, void* stream) {
   return launch(in, out, n, stream);
 }
 

@@ -1,0 +1,307 @@
+// Fused WADG stage kernel for gfx950, split-work variant.
+//
+// The same stage (or right-hand side) and the same arithmetic as the other
+// stage kernels (stage_common.h), with one 64-element group of one slice
+// spread over four waves instead of two, so that each wave carries about
+// a quarter of the item and two workgroups share a CU (two waves per SIMD):
+//
+//   wave 0  pressure volume term (Section 4.1), then the pressure mass
+//           inverse and update;
+//   wave 1  velocity volume term, then the u mass inverse and update;
+//   wave 2  traces, fluxes and lifts of faces 0 and 2 for all three fields
+//           (Section 5.4: each face's traces interpolated once), then the
+//           v mass inverse and update;
+//   wave 3  the same for faces 1 and 3.
+//
+// The face waves leave each face's terms in LDS; the volume waves add them
+// in face order 0..3 (as every stage kernel does) and wave 1 hands b_v to
+// wave 2 through LDS.  Three workgroup barriers per item: the input tile,
+// the face terms, b_v.  Global operands are requested ahead of use as in
+// the streamed kernel: metric column i+1 during column i, the face waves'
+// two faces (neighbour traces and face geometry) with the tile.
+//
+// Workgroup -> (slice, element group): the streamed kernel's XCD-aware tile
+// order (wadg_set_schedule).
+
+#include <hip/hip_runtime.h>
+
+#include "stage_common.h"
+
+namespace wadg {
+namespace {
+
+using namespace dev;
+
+template <typename R, int N, int NQ>
+struct Split {
+  static constexpr int NP1 = N + 1, NP = NP1 * NP1, NQ2 = NQ * NQ;
+  static constexpr unsigned tile = 3u * NP * kWave;        // input tile [3][NP][64]
+  static constexpr unsigned xf = 4u * 3 * NP1 * kWave;     // face terms [4][3][NP1][64]
+  static constexpr unsigned xv = (unsigned)NP * kWave;     // b_v [NP][64]
+};
+
+// Global geometry and state resources of one work item.
+struct SplitBufs {
+  rsrc_t qin, qout, res, resw, qslice, vol, face, nbr;
+};
+
+template <typename R, int NQ>
+__device__ __forceinline__ void split_metric_column(const SplitBufs& B, int i, unsigned kb,
+                                                    R (&g)[4][NQ]) {
+  constexpr unsigned KP = kWave * sizeof(R);
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) g[p][j] = ldr<R>(B.vol, kb, (p * NQ * NQ + i + NQ * j) * KP);
+}
+
+template <typename R, int NQ>
+__device__ __forceinline__ void split_weights(const SplitBufs& B, unsigned wplane, unsigned kb,
+                                              R (&w)[NQ * NQ]) {
+  constexpr unsigned KP = kWave * sizeof(R);
+#pragma unroll
+  for (int q = 0; q < NQ * NQ; ++q) w[q] = ldr<R>(B.vol, kb, (wplane + q) * KP);
+}
+
+// Volume waves: the volume term of field group PRESSURE (b0 = b_p) or the
+// velocity (b0 = b_u, b1 = b_v), metric terms one column ahead.
+template <typename R, int N, int NQ, bool PRESSURE, typename FP, typename FU, typename FV>
+__device__ __forceinline__ void split_volume(const SplitBufs& B, unsigned kb, const FP& P,
+                                             const FU& U, const FV& V, R (&b0)[(N + 1) * (N + 1)],
+                                             R (&b1)[(N + 1) * (N + 1)]) {
+  constexpr int NP = (N + 1) * (N + 1);
+#pragma unroll
+  for (int n = 0; n < NP; ++n) b0[n] = b1[n] = R(0);
+  R gc[4][NQ], gn[4][NQ];
+  split_metric_column<R, NQ>(B, 0, kb, gc);
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    if (i + 1 < NQ) split_metric_column<R, NQ>(B, i + 1, kb, gn);
+    order();
+    if constexpr (PRESSURE) {
+      pressure_volume_column<R, N, NQ>(i, U, V, gc, b0);
+      pin(b0);
+    } else {
+      velocity_volume_column<R, N, NQ>(i, P, gc, b0, b1);
+      pin(b0);
+      pin(b1);
+    }
+    if (i + 1 < NQ) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) gc[g][j] = gn[g][j];
+    }
+  }
+}
+
+// Face waves: the terms of faces FA and FB for all three fields, into LDS.
+template <typename R, int N, int NQ, int FA, int FB, typename FP, typename FU, typename FV>
+__device__ __forceinline__ void split_faces(const StageScalars<R>& k, const SplitBufs& B,
+                                            unsigned kb, int lane, const FP& P, const FU& U,
+                                            const FV& V, R* xf) {
+  constexpr int NP1 = N + 1;
+  constexpr unsigned KP = kWave * sizeof(R);
+  NbrOffsets nbo;
+  load_nbr(B.nbr, lane, nbo);
+  Trace<R, N> tr[2];
+  R g[2][3][NQ];
+  gather_trace<R, N>(B.qslice, nbo, FA, tr[0]);
+  gather_trace<R, N>(B.qslice, nbo, FB, tr[1]);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) {
+      g[0][c][j] = ldr<R>(B.face, kb, (c * 4 * NQ + FA * NQ + j) * KP);
+      g[1][c][j] = ldr<R>(B.face, kb, (c * 4 * NQ + FB * NQ + j) * KP);
+    }
+  order();
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int f = q == 0 ? FA : FB;
+    R sp[NP1], su[NP1], sv[NP1];
+    face_terms<R, N, NQ, true, true>(f, P, U, V, tr[q], g[q], k.tau_p, k.tau_u, sp, su, sv);
+#pragma unroll
+    for (int m = 0; m < NP1; ++m) {
+      xf[((f * 3 + 0) * NP1 + m) * kWave + lane] = sp[m];
+      xf[((f * 3 + 1) * NP1 + m) * kWave + lane] = su[m];
+      xf[((f * 3 + 2) * NP1 + m) * kWave + lane] = sv[m];
+    }
+  }
+}
+
+// Add the four faces' terms of field c to b, in face order.
+template <typename R, int N>
+__device__ __forceinline__ void add_face_terms(const R* xf, int c, int lane,
+                                               R (&b)[(N + 1) * (N + 1)]) {
+  constexpr int NP1 = N + 1;
+#pragma unroll
+  for (int f = 0; f < 4; ++f)
+#pragma unroll
+    for (int m = 0; m < NP1; ++m) b[fnode<N>(f, m)] += xf[((f * 3 + c) * NP1 + m) * kWave + lane];
+}
+
+}  // namespace
+
+template <typename R, int N, int NQ, int MODE>
+__global__ __launch_bounds__(4 * kWave) void split_kernel(const StageParams p) {
+  static_assert(MODE == kStage || MODE == kRhs, "stage and right-hand-side modes only");
+  using L = Split<R, N, NQ>;
+  constexpr int NP = L::NP, NQ2 = L::NQ2;
+  constexpr unsigned tile = L::tile;
+  constexpr unsigned KP = kWave * sizeof(R);
+  __shared__ __attribute__((aligned(16))) R tq[tile];
+  __shared__ __attribute__((aligned(16))) R xf[L::xf];
+  __shared__ __attribute__((aligned(16))) R xv[L::xv];
+
+  const int w = xcd_remap(blockIdx.x, gridDim.x);
+  const int Be = p.tile_groups, Bs = p.tile_slices, nEG = p.nEG;
+  const int sb = w / (Bs * nEG);
+  const int r = w - sb * Bs * nEG;
+  const int bs = min(Bs, p.S - sb * Bs);
+  const int eb = r / (Be * bs);
+  const int r2 = r - eb * Be * bs;
+  const int be = min(Be, nEG - eb * Be);
+  const int s = sb * Bs + r2 / be;
+  const int eg = eb * Be + r2 % be;
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & (kWave - 1);
+  const unsigned kb = (unsigned)lane * sizeof(R);
+
+  const R* Qin = static_cast<const R*>(p.Qin);
+  const size_t slice = (size_t)s * p.nEG * tile;
+  const size_t grp = slice + (size_t)eg * tile;
+  SplitBufs B;
+  B.qin = make_rsrc(Qin + grp, tile * sizeof(R));
+  B.qout = make_rsrc(static_cast<R*>(p.Qout) + grp, tile * sizeof(R));
+  B.res = make_rsrc(static_cast<R*>(MODE == kRhs ? p.Qout : p.res) + grp, tile * sizeof(R));
+  B.resw = make_rsrc(static_cast<R*>(p.res_out ? p.res_out : p.res) + grp,
+                     MODE == kStage ? tile * sizeof(R) : 0u);
+  B.qslice = make_rsrc(Qin + slice, (unsigned)p.nEG * tile * sizeof(R));
+  B.vol = make_rsrc(static_cast<const R*>(p.vol) + (size_t)eg * 6 * NQ2 * kWave, 6u * NQ2 * KP);
+  B.face = make_rsrc(static_cast<const R*>(p.face) + (size_t)eg * 12 * NQ * kWave,
+                     12u * NQ * KP);
+  B.nbr = make_rsrc(p.nbr + (size_t)eg * 8 * kWave, 8u * kWave * 4u);
+
+  // the input tile into LDS, 16-byte chunks over all four waves
+  constexpr unsigned chunks = tile * sizeof(R) / 16;
+  constexpr unsigned per_thread = (chunks + 4 * kWave - 1) / (4 * kWave);
+  {
+    u32x4 v[per_thread];
+#pragma unroll
+    for (unsigned i = 0; i < per_thread; ++i) {
+      const unsigned c = tid + i * 4 * kWave;
+      if (c < chunks) v[i] = ld128(B.qin, c * 16u);
+    }
+#pragma unroll
+    for (unsigned i = 0; i < per_thread; ++i) {
+      const unsigned c = tid + i * 4 * kWave;
+      if (c < chunks) *reinterpret_cast<u32x4*>(reinterpret_cast<char*>(tq) + c * 16u) = v[i];
+    }
+  }
+  __syncthreads();
+
+  const StageScalars<R> k = stage_scalars<R>(p);
+  const bool active = eg * kWave + lane < p.K;
+  auto P = [&](int n) { return tq[n * kWave + lane]; };
+  auto U = [&](int n) { return tq[(NP + n) * kWave + lane]; };
+  auto V = [&](int n) { return tq[(2 * NP + n) * kWave + lane]; };
+
+  if (wave <= 1) {
+    R b0[NP], b1[NP];
+    if (wave == 0)
+      split_volume<R, N, NQ, true>(B, kb, P, U, V, b0, b1);
+    else
+      split_volume<R, N, NQ, false>(B, kb, P, U, V, b0, b1);
+    __syncthreads();                                   // face terms ready
+    R w[NQ2], resv[NP], dq[NP];
+    if (wave == 0) {
+      split_weights<R, NQ>(B, 4 * NQ2, kb, w);
+      load_res<R, NP, MODE>(k, B.res, 0, kb, resv);
+      add_face_terms<R, N>(xf, 0, lane, b0);
+      __syncthreads();                                 // b_v handed over
+#pragma unroll
+      for (int q = 0; q < NQ2; ++q) w[q] *= k.c2s;
+      wadg_inverse<R, N, NQ>(b0, w, dq);
+      finish_field<R, NP, MODE>(k, B.qout, B.resw, P, 0, kb, active, resv, dq);
+    } else {
+      split_weights<R, NQ>(B, 5 * NQ2, kb, w);
+      load_res<R, NP, MODE>(k, B.res, 1, kb, resv);
+      add_face_terms<R, N>(xf, 1, lane, b0);
+      add_face_terms<R, N>(xf, 2, lane, b1);
+#pragma unroll
+      for (int n = 0; n < NP; ++n) xv[n * kWave + lane] = b1[n];
+      __syncthreads();                                 // b_v handed over
+      wadg_inverse<R, N, NQ>(b0, w, dq);
+      finish_field<R, NP, MODE>(k, B.qout, B.resw, P, 1, kb, active, resv, dq);
+    }
+  } else {
+    if (wave == 2)
+      split_faces<R, N, NQ, 0, 2>(k, B, kb, lane, P, U, V, xf);
+    else
+      split_faces<R, N, NQ, 1, 3>(k, B, kb, lane, P, U, V, xf);
+    R w[NQ2], resv[NP];
+    if (wave == 2) {
+      split_weights<R, NQ>(B, 5 * NQ2, kb, w);
+      load_res<R, NP, MODE>(k, B.res, 2, kb, resv);
+    }
+    __syncthreads();                                   // face terms ready
+    __syncthreads();                                   // b_v handed over
+    if (wave == 2) {
+      R bv[NP], dq[NP];
+#pragma unroll
+      for (int n = 0; n < NP; ++n) bv[n] = xv[n * kWave + lane];
+      wadg_inverse<R, N, NQ>(bv, w, dq);
+      finish_field<R, NP, MODE>(k, B.qout, B.resw, P, 2, kb, active, resv, dq);
+    }
+  }
+}
+
+namespace {
+
+template <typename R, int N, int NQ>
+int launch_nq(int mode, const StageParams& p, void* stream) {
+  const dim3 grid(p.nEG * p.S), block(4 * kWave);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (mode == kStage)
+    hipLaunchKernelGGL((split_kernel<R, N, NQ, kStage>), grid, block, 0, st, p);
+  else if (mode == kRhs && sizeof(R) == sizeof(double))
+    hipLaunchKernelGGL((split_kernel<R, N, NQ, kRhs>), grid, block, 0, st, p);
+  else
+    return (int)hipErrorInvalidValue;
+  return (int)hipGetLastError();
+}
+
+template <typename R, int N>
+int launch_n(int nq, int mode, const StageParams& p, void* stream) {
+  switch (nq - N) {
+    case 1: return launch_nq<R, N, N + 1>(mode, p, stream);
+    case 2: return launch_nq<R, N, N + 2>(mode, p, stream);
+    case 3: return launch_nq<R, N, N + 3>(mode, p, stream);
+    default: return (int)hipErrorInvalidValue;
+  }
+}
+
+template <typename R>
+int launch_r(int N, int nq, int mode, const StageParams& p, void* stream) {
+  switch (N) {
+    case 1: return launch_n<R, 1>(nq, mode, p, stream);
+    case 2: return launch_n<R, 2>(nq, mode, p, stream);
+    case 3: return launch_n<R, 3>(nq, mode, p, stream);
+    case 4: return launch_n<R, 4>(nq, mode, p, stream);
+    default: return (int)hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+int launch_stage_split(int N, int nq, int mode, const StageParams& p, void* stream) {
+  return launch_r<double>(N, nq, mode, p, stream);
+}
+
+int launch_stage_split_fp32(int N, int nq, const StageParams& p, void* stream) {
+  return launch_r<float>(N, nq, kStage, p, stream);
+}
+
+}  // namespace wadg

@@ -266,46 +266,83 @@ __device__ __forceinline__ void face_point(int f, int j, const FP& P, const FU& 
   }
 }
 
-// Pressure surface term of face f:
-//   bp -= int 1/2 (2{u}.n - tau_p [p]) l sJ,   g[c][j] = nx, ny, w sJ.
-template <typename R, int N, int NQ, typename FP, typename FU, typename FV>
-__device__ __forceinline__ void pressure_face(int f, const FP& P, const FU& U, const FV& V,
-                                              const Trace<R, N>& t, const R (&g)[3][NQ], R tau_p,
-                                              R (&bp)[(N + 1) * (N + 1)]) {
+// Flux at face Gauss point j and its lifting weight: the pressure flux
+//   fp = 1/2 w sJ (2{u}.n - tau_p [p])
+// and the velocity flux vector (fx, fy) = 1/2 w sJ ([p] - tau_u [u].n) n,
+// g[c][j] = nx, ny, w sJ.
+template <typename R, int NQ>
+__device__ __forceinline__ R pressure_flux(int j, R pm, R um, R vm, R pp, R up, R vp,
+                                           const R (&g)[3][NQ], R tau_p) {
+  const R nx = g[0][j], ny = g[1][j], wsJ = g[2][j];
+  const R un = mad(up + um, nx, (vp + vm) * ny);          // 2 {u}.n
+  return (R(0.5) * wsJ) * mad(-tau_p, pp - pm, un);
+}
+template <typename R, int NQ>
+__device__ __forceinline__ void velocity_flux(int j, R pm, R um, R vm, R pp, R up, R vp,
+                                              const R (&g)[3][NQ], R tau_u, R& fx, R& fy) {
+  const R nx = g[0][j], ny = g[1][j], wsJ = g[2][j];
+  const R jn = mad(up - um, nx, (vp - vm) * ny);          // [u].n
+  const R fu = (R(0.5) * wsJ) * mad(-tau_u, jn, pp - pm);
+  fx = fu * nx;
+  fy = fu * ny;
+}
+
+// Surface terms of face f at the face's nodes m = 0..N (node fnode(f, m)):
+//   sp[m] = -sum_j V[j][m] fp_j,  (su, sv)[m] = -sum_j V[j][m] (fx, fy)_j,
+// each summed over the face's Gauss points on its own; the caller adds the
+// faces' terms to the load vector in face order 0..3.
+template <typename R, int N, int NQ, bool PRESS, bool VEL, typename FP, typename FU, typename FV>
+__device__ __forceinline__ void face_terms(int f, const FP& P, const FU& U, const FV& V,
+                                           const Trace<R, N>& t, const R (&g)[3][NQ], R tau_p,
+                                           R tau_u, R (&sp)[N + 1], R (&su)[N + 1],
+                                           R (&sv)[N + 1]) {
   constexpr ct::Ops<R, N, NQ> T = ct::make_ops<R, N, NQ>();
+#pragma unroll
+  for (int m = 0; m <= N; ++m) sp[m] = su[m] = sv[m] = R(0);
 #pragma unroll
   for (int j = 0; j < NQ; ++j) {
     R pm, um, vm, pp, up, vp;
     face_point<R, N, NQ>(f, j, P, U, V, t, pm, um, vm, pp, up, vp);
-    const R nx = g[0][j], ny = g[1][j], wsJ = g[2][j];
-    const R un = mad(up + um, nx, (vp + vm) * ny);          // 2 {u}.n
-    const R fp = (R(0.5) * wsJ) * mad(-tau_p, pp - pm, un);
+    if constexpr (PRESS) {
+      const R fp = pressure_flux<R, NQ>(j, pm, um, vm, pp, up, vp, g, tau_p);
 #pragma unroll
-    for (int m = 0; m <= N; ++m) bp[fnode<N>(f, m)] = mad(-T.V[j][m], fp, bp[fnode<N>(f, m)]);
+      for (int m = 0; m <= N; ++m) sp[m] = mad(-T.V[j][m], fp, sp[m]);
+    }
+    if constexpr (VEL) {
+      R fx, fy;
+      velocity_flux<R, NQ>(j, pm, um, vm, pp, up, vp, g, tau_u, fx, fy);
+#pragma unroll
+      for (int m = 0; m <= N; ++m) {
+        su[m] = mad(-T.V[j][m], fx, su[m]);
+        sv[m] = mad(-T.V[j][m], fy, sv[m]);
+      }
+    }
   }
 }
 
-// Velocity surface term of face f:
-//   (bu, bv) -= int 1/2 ([p] - tau_u [u].n) n l sJ.
+// Pressure surface term of face f added to bp.
+template <typename R, int N, int NQ, typename FP, typename FU, typename FV>
+__device__ __forceinline__ void pressure_face(int f, const FP& P, const FU& U, const FV& V,
+                                              const Trace<R, N>& t, const R (&g)[3][NQ], R tau_p,
+                                              R (&bp)[(N + 1) * (N + 1)]) {
+  R sp[N + 1], su[N + 1], sv[N + 1];
+  face_terms<R, N, NQ, true, false>(f, P, U, V, t, g, tau_p, R(0), sp, su, sv);
+#pragma unroll
+  for (int m = 0; m <= N; ++m) bp[fnode<N>(f, m)] += sp[m];
+}
+
+// Velocity surface terms of face f added to (bu, bv).
 template <typename R, int N, int NQ, typename FP, typename FU, typename FV>
 __device__ __forceinline__ void velocity_face(int f, const FP& P, const FU& U, const FV& V,
                                               const Trace<R, N>& t, const R (&g)[3][NQ], R tau_u,
                                               R (&bu)[(N + 1) * (N + 1)],
                                               R (&bv)[(N + 1) * (N + 1)]) {
-  constexpr ct::Ops<R, N, NQ> T = ct::make_ops<R, N, NQ>();
+  R sp[N + 1], su[N + 1], sv[N + 1];
+  face_terms<R, N, NQ, false, true>(f, P, U, V, t, g, R(0), tau_u, sp, su, sv);
 #pragma unroll
-  for (int j = 0; j < NQ; ++j) {
-    R pm, um, vm, pp, up, vp;
-    face_point<R, N, NQ>(f, j, P, U, V, t, pm, um, vm, pp, up, vp);
-    const R nx = g[0][j], ny = g[1][j], wsJ = g[2][j];
-    const R jn = mad(up - um, nx, (vp - vm) * ny);          // [u].n
-    const R fu = (R(0.5) * wsJ) * mad(-tau_u, jn, pp - pm);
-    const R fx = fu * nx, fy = fu * ny;
-#pragma unroll
-    for (int m = 0; m <= N; ++m) {
-      bu[fnode<N>(f, m)] = mad(-T.V[j][m], fx, bu[fnode<N>(f, m)]);
-      bv[fnode<N>(f, m)] = mad(-T.V[j][m], fy, bv[fnode<N>(f, m)]);
-    }
+  for (int m = 0; m <= N; ++m) {
+    bu[fnode<N>(f, m)] += su[m];
+    bv[fnode<N>(f, m)] += sv[m];
   }
 }
 

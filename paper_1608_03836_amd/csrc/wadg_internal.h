@@ -98,6 +98,10 @@ enum StageMode { kStage = 0, kRhs = 1, kApplyA = 2 };
 int launch_stage_streamed(int N, int nq, int mode, const StageParams& p, void* stream);
 // The same LSRK stage in FP32 (arrays of float).
 int launch_stage_streamed_fp32(int N, int nq, const StageParams& p, void* stream);
+// Split-work kernel: the streamed kernel's work item spread over four
+// waves (volume p, volume u/v, faces 0+2, faces 1+3); stage and rhs modes.
+int launch_stage_split(int N, int nq, int mode, const StageParams& p, void* stream);
+int launch_stage_split_fp32(int N, int nq, const StageParams& p, void* stream);
 // Resident-geometry kernel: one workgroup per (element group, slice range)
 // with the group's geometry held in LDS; grid = nEG * ranges.  Only where
 // resident_supported(N, nq, fp32).
@@ -117,6 +121,8 @@ int launch_stage_resident_fp32(int N, int nq, const StageParams& p, int ranges, 
 // Elementwise precision conversion of n values (FP64 <-> FP32).
 int launch_to_fp32(const double* in, float* out, size_t n, void* stream);
 int launch_to_fp64(const float* in, double* out, size_t n, void* stream);
+// Device copy of n doubles as a kernel (capture-safe; no runtime copy node).
+int launch_copy(const double* in, double* out, size_t n, void* stream);
 bool stage_supported(int N, int nq);
 
 // Batched stage over many independent problems (same N, nq, penalties):

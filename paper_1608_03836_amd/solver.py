@@ -112,8 +112,8 @@ class Solver:
         """WADG_KERNEL_AUTO, _STREAMED or _RESIDENT (see wadg_set_kernel)."""
         B.wadg_set_kernel(self.ctx, kernel)
 
-    def kernel_in_use(self, S, fp32=False):
-        return B.wadg_kernel_in_use(self.ctx, S, fp32)
+    def kernel_in_use(self, rhs=False, fp32=False):
+        return B.wadg_kernel_in_use(self.ctx, rhs, fp32)
 
     # -- sensitivities ---------------------------------------------------
     def set_c2_scale(self, gamma):

@@ -84,16 +84,17 @@ def test_schedules_and_tuner_bitwise_invariant(W, small):
     for wg, order in ((2, 0), (0, 0), (1, 1), (8, 1), (4, 0)):
         batch.set_schedule(wg, order)
         Q = batch.upload([p.Q0 for p in probs])
-        batch.integrate(Q, dts, 2)
-        outs.append(Q.cpu().numpy())
+        batch.integrate(Q, dts, 3)
+        outs.append(batch.download(Q))
     Q0 = batch.upload([p.Q0 for p in probs])
     wg, order, us = batch.tune(Q0, dts, reps=2)
     assert wg in (0, 1, 2, 4, 8) and order in (0, 1) and us > 0
     assert np.array_equal(Q0.cpu().numpy(), batch.upload([p.Q0 for p in probs]).cpu().numpy())
-    batch.integrate(Q0, dts, 2)
-    outs.append(Q0.cpu().numpy())
+    batch.integrate(Q0, dts, 3)
+    outs.append(batch.download(Q0))
     for o in outs[1:]:
-        assert np.array_equal(o, outs[0])
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b)
     batch.set_schedule(2, 0)
 
 
@@ -112,7 +113,9 @@ def test_graph_replays_equal_eager(W, small):
             torch.cuda.synchronize()
             batch.replay()
             torch.cuda.synchronize()
-            assert torch.equal(Qe, Qg), r
+            # padding lanes are unspecified on output; compare the problems' values
+            for a, b in zip(batch.download(Qe), batch.download(Qg)):
+                assert np.array_equal(a, b), r
     finally:
         batch.release_graph()
 

@@ -1,5 +1,5 @@
-"""GPU: the two stage-kernel variants (streamed geometry, LDS-resident
-geometry) compute bit-identical results, on shapes that exercise the
+"""GPU: the three stage-kernel variants (streamed geometry, LDS-resident
+geometry, split work) compute bit-identical results, on shapes that exercise the
 resident kernel's work split -- several slices per pair, an odd slice count
 (a pair with nothing to do in its last iteration), workgroups whose slice
 range is empty, a ragged last element group -- in stage and right-hand-side
@@ -48,19 +48,21 @@ def test_streamed_and_resident_bitwise(W, N, dq, K1D, S, nsteps):
     Q0 = _states(mesh, S, seed=K1D + S)
     dt = 0.1 / (K1D * (N + 1) ** 2)
     out = {}
-    for kern in (W.WADG_KERNEL_STREAMED, W.WADG_KERNEL_RESIDENT):
+    kerns = (W.WADG_KERNEL_STREAMED, W.WADG_KERNEL_RESIDENT, W.WADG_KERNEL_SPLIT)
+    for kern in kerns:
         sol.set_kernel(kern)
-        assert sol.kernel_in_use(S) == kern
-        assert sol.kernel_in_use(S, fp32=True) == kern
+        assert sol.kernel_in_use() == kern
+        assert sol.kernel_in_use(fp32=True) == kern
         Q = sol.upload(Q0)
         sol.integrate(Q, S, dt, nsteps)
         dQ = sol.rhs(sol.upload(Q0), S)
         Q32 = sol.upload(Q0)
         sol.integrate_fp32(Q32, S, dt, nsteps)
         out[kern] = (sol.download(Q, S), sol.download(dQ, S), sol.download(Q32, S))
-    for a, b in zip(out[W.WADG_KERNEL_STREAMED], out[W.WADG_KERNEL_RESIDENT]):
-        assert np.all(np.isfinite(a))
-        assert np.array_equal(a, b)
+    for kern in kerns[1:]:
+        for a, b in zip(out[W.WADG_KERNEL_STREAMED], out[kern]):
+            assert np.all(np.isfinite(a))
+            assert np.array_equal(a, b), kern
 
 
 def test_resident_matches_oracle_many_slices_per_pair(W):
@@ -72,7 +74,7 @@ def test_resident_matches_oracle_many_slices_per_pair(W):
     Q0 = _states(mesh, S, seed=9)
     sol = W.Solver(mesh, c2=c2_layered)
     sol.set_kernel(W.WADG_KERNEL_RESIDENT)
-    assert sol.kernel_in_use(S) == W.WADG_KERNEL_RESIDENT
+    assert sol.kernel_in_use() == W.WADG_KERNEL_RESIDENT
     Q = sol.upload(Q0)
     sol.integrate(Q, S, dt, nsteps)
     got = sol.download(Q, S)
@@ -84,29 +86,24 @@ def test_resident_matches_oracle_many_slices_per_pair(W):
 
 
 def test_kernel_selection_rules(W):
-    """AUTO: FP64 takes the resident kernel where the geometry fits in LDS
-    (N = 3 with nq1 <= 5) and each pair sweeps >= 16 slices (64 x 64
-    elements: 64 groups x 4 slice ranges of ceil(S / 4) slices, so
-    S >= 121), else the streamed kernel; FP32-bulk takes the streamed
-    kernel.  An explicit choice
-    applies to both precisions; the resident kernel is refused where the
-    FP64 geometry does not fit."""
+    """AUTO: LSRK stages (FP64 and FP32) take the split kernel, wadg_rhs the
+    resident kernel where the geometry fits in LDS (N = 3 with nq1 <= 5),
+    else the split kernel.  An explicit choice applies to every launch; the
+    resident kernel is refused where the FP64 geometry does not fit."""
     _print_case(test="kernel-selection")
-    mesh = periodic_quad_mesh(64, 3, eps=0.05, warp="skew")
+    mesh = periodic_quad_mesh(4, 3, eps=0.05, warp="skew")
     s5 = W.Solver(mesh, nq1=5)
-    assert s5.kernel_in_use(64) == W.WADG_KERNEL_STREAMED
-    assert s5.kernel_in_use(120) == W.WADG_KERNEL_STREAMED
-    assert s5.kernel_in_use(121) == W.WADG_KERNEL_RESIDENT
-    assert s5.kernel_in_use(128) == W.WADG_KERNEL_RESIDENT
-    assert s5.kernel_in_use(128, fp32=True) == W.WADG_KERNEL_STREAMED
-    s5.set_kernel(W.WADG_KERNEL_RESIDENT)
-    assert s5.kernel_in_use(1) == W.WADG_KERNEL_RESIDENT
-    assert s5.kernel_in_use(1, fp32=True) == W.WADG_KERNEL_RESIDENT
-    s5.set_kernel(W.WADG_KERNEL_STREAMED)
-    assert s5.kernel_in_use(1000) == W.WADG_KERNEL_STREAMED
-    small = periodic_quad_mesh(4, 3, eps=0.05, warp="skew")
-    s6 = W.Solver(small, nq1=6)
-    assert s6.kernel_in_use(1000) == W.WADG_KERNEL_STREAMED
+    assert s5.kernel_in_use() == W.WADG_KERNEL_SPLIT
+    assert s5.kernel_in_use(fp32=True) == W.WADG_KERNEL_SPLIT
+    assert s5.kernel_in_use(rhs=True) == W.WADG_KERNEL_RESIDENT
+    for kern in (W.WADG_KERNEL_RESIDENT, W.WADG_KERNEL_STREAMED, W.WADG_KERNEL_SPLIT):
+        s5.set_kernel(kern)
+        assert s5.kernel_in_use() == kern
+        assert s5.kernel_in_use(fp32=True) == kern
+        assert s5.kernel_in_use(rhs=True) == kern
+    s6 = W.Solver(mesh, nq1=6)
+    assert s6.kernel_in_use() == W.WADG_KERNEL_SPLIT
+    assert s6.kernel_in_use(rhs=True) == W.WADG_KERNEL_SPLIT
     with pytest.raises(W.WadgError) as e:
         s6.set_kernel(W.WADG_KERNEL_RESIDENT)
     assert e.value.status == W.binding.WADG_E_UNSUPPORTED
