@@ -16,9 +16,17 @@
 // The face waves leave each face's terms in LDS; the volume waves add them
 // in face order 0..3 (as every stage kernel does) and wave 1 hands b_v to
 // wave 2 through LDS.  Three workgroup barriers per item: the input tile,
-// the face terms, b_v.  Global operands are requested ahead of use as in
-// the streamed kernel: metric column i+1 during column i, the face waves'
-// two faces (neighbour traces and face geometry) with the tile.
+// the face terms, b_v.
+//
+// Metric terms.  Both volume waves walk the NQ quadrature columns and need
+// each column's four metric planes; a column of compute is shorter than a
+// global load under full HBM load, so no register prefetch distance that
+// fits hides them.  Instead everything the volume phase reads is requested
+// with the tile: the first and last columns by each volume wave into its
+// own registers, the NQ-2 middle columns by the face waves (which have
+// registers to spare) into LDS, shared by both volume waves.  The staged
+// columns are dead once the face-terms barrier has passed, and b_v reuses
+// their space.
 //
 // Workgroup -> (slice, element group): the streamed kernel's XCD-aware tile
 // order (wadg_set_schedule).
@@ -37,7 +45,10 @@ struct Split {
   static constexpr int NP1 = N + 1, NP = NP1 * NP1, NQ2 = NQ * NQ;
   static constexpr unsigned tile = 3u * NP * kWave;        // input tile [3][NP][64]
   static constexpr unsigned xf = 4u * 3 * NP1 * kWave;     // face terms [4][3][NP1][64]
-  static constexpr unsigned xv = (unsigned)NP * kWave;     // b_v [NP][64]
+  static constexpr int NM = NQ - 2;                        // metric columns staged in LDS
+  // staged metric columns [NM][4][NQ][64], later b_v [NP][64]
+  static constexpr unsigned xm =
+      (unsigned)(NM * 4 * NQ > NP ? NM * 4 * NQ : NP) * kWave;
 };
 
 // Global geometry and state resources of one work item.
@@ -64,36 +75,67 @@ __device__ __forceinline__ void split_weights(const SplitBufs& B, unsigned wplan
 }
 
 // Volume waves: the volume term of field group PRESSURE (b0 = b_p) or the
-// velocity (b0 = b_u, b1 = b_v), metric terms one column ahead.
+// velocity (b0 = b_u, b1 = b_v).  Metric column 0 arrives in ga, column
+// NQ-1 in gb (both requested with the tile), the middle columns from the
+// LDS stage xm; ga is reused for them once column 0 is done.
 template <typename R, int N, int NQ, bool PRESSURE, typename FP, typename FU, typename FV>
-__device__ __forceinline__ void split_volume(const SplitBufs& B, unsigned kb, const FP& P,
-                                             const FU& U, const FV& V, R (&b0)[(N + 1) * (N + 1)],
+__device__ __forceinline__ void split_volume(const R* xm, int lane, const FP& P, const FU& U,
+                                             const FV& V, R (&ga)[4][NQ], const R (&gb)[4][NQ],
+                                             R (&b0)[(N + 1) * (N + 1)],
                                              R (&b1)[(N + 1) * (N + 1)]) {
   constexpr int NP = (N + 1) * (N + 1);
 #pragma unroll
   for (int n = 0; n < NP; ++n) b0[n] = b1[n] = R(0);
-  R gc[4][NQ], gn[4][NQ];
-  split_metric_column<R, NQ>(B, 0, kb, gc);
-#pragma unroll
-  for (int i = 0; i < NQ; ++i) {
-    if (i + 1 < NQ) split_metric_column<R, NQ>(B, i + 1, kb, gn);
-    order();
+  auto column = [&](int i, const R(&g)[4][NQ]) {
     if constexpr (PRESSURE) {
-      pressure_volume_column<R, N, NQ>(i, U, V, gc, b0);
+      pressure_volume_column<R, N, NQ>(i, U, V, g, b0);
       pin(b0);
     } else {
-      velocity_volume_column<R, N, NQ>(i, P, gc, b0, b1);
+      velocity_volume_column<R, N, NQ>(i, P, g, b0, b1);
       pin(b0);
       pin(b1);
     }
-    if (i + 1 < NQ) {
+  };
+  column(0, ga);
 #pragma unroll
-      for (int g = 0; g < 4; ++g)
+  for (int i = 1; i + 1 < NQ; ++i) {
+    order();
 #pragma unroll
-        for (int j = 0; j < NQ; ++j) gc[g][j] = gn[g][j];
-    }
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int j = 0; j < NQ; ++j) ga[q][j] = xm[(((i - 1) * 4 + q) * NQ + j) * kWave + lane];
+    column(i, ga);
   }
+  order();
+  column(NQ - 1, gb);
 }
+
+// Face waves: request metric planes Q0 and Q0+1 of the middle columns
+// (with the tile), and store them into the LDS stage once they arrive.
+template <typename R, int NQ, int Q0>
+struct MetricStage {
+  static constexpr int NM = NQ - 2 > 0 ? NQ - 2 : 1;
+  R v[NM][2][NQ];
+
+  __device__ __forceinline__ void load(const SplitBufs& B, unsigned kb) {
+    constexpr unsigned KP = kWave * sizeof(R);
+#pragma unroll
+    for (int c = 0; c + 2 < NQ; ++c)
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int j = 0; j < NQ; ++j)
+          v[c][q][j] = ldr<R>(B.vol, kb, ((Q0 + q) * NQ * NQ + c + 1 + NQ * j) * KP);
+  }
+  __device__ __forceinline__ void store(R* xm, int lane) const {
+#pragma unroll
+    for (int c = 0; c + 2 < NQ; ++c)
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) xm[((c * 4 + Q0 + q) * NQ + j) * kWave + lane] = v[c][q][j];
+  }
+};
 
 // Face waves: the terms of faces FA and FB for all three fields, into LDS.
 template <typename R, int N, int NQ, int FA, int FB, typename FP, typename FU, typename FV>
@@ -152,7 +194,8 @@ __global__ __launch_bounds__(4 * kWave) void split_kernel(const StageParams p) {
   constexpr unsigned KP = kWave * sizeof(R);
   __shared__ __attribute__((aligned(16))) R tq[tile];
   __shared__ __attribute__((aligned(16))) R xf[L::xf];
-  __shared__ __attribute__((aligned(16))) R xv[L::xv];
+  __shared__ __attribute__((aligned(16))) R xm[L::xm];
+  R* const xv = xm;   // b_v, once the staged metric columns are dead
 
   const int w = xcd_remap(blockIdx.x, gridDim.x);
   const int Be = p.tile_groups, Bs = p.tile_slices, nEG = p.nEG;
@@ -184,23 +227,30 @@ __global__ __launch_bounds__(4 * kWave) void split_kernel(const StageParams p) {
                      12u * NQ * KP);
   B.nbr = make_rsrc(p.nbr + (size_t)eg * 8 * kWave, 8u * kWave * 4u);
 
-  // the input tile into LDS, 16-byte chunks over all four waves
+  // The input tile into LDS, 16-byte chunks over all four waves, and with
+  // it the volume phase's metric terms: columns 0 and NQ-1 into the volume
+  // waves' registers, the middle columns into LDS through the face waves.
+  // Each role runs its own copy of this prologue (the branch is
+  // wave-uniform), so that the registers of one role's loads are not held
+  // live across the other's.
   constexpr unsigned chunks = tile * sizeof(R) / 16;
   constexpr unsigned per_thread = (chunks + 4 * kWave - 1) / (4 * kWave);
-  {
+  auto tile_copy = [&](auto&& more_loads, auto&& more_stores) {
     u32x4 v[per_thread];
 #pragma unroll
     for (unsigned i = 0; i < per_thread; ++i) {
       const unsigned c = tid + i * 4 * kWave;
       if (c < chunks) v[i] = ld128(B.qin, c * 16u);
     }
+    more_loads();
 #pragma unroll
     for (unsigned i = 0; i < per_thread; ++i) {
       const unsigned c = tid + i * 4 * kWave;
       if (c < chunks) *reinterpret_cast<u32x4*>(reinterpret_cast<char*>(tq) + c * 16u) = v[i];
     }
-  }
-  __syncthreads();
+    more_stores();
+    __syncthreads();                                   // tile in LDS
+  };
 
   const StageScalars<R> k = stage_scalars<R>(p);
   const bool active = eg * kWave + lane < p.K;
@@ -209,11 +259,18 @@ __global__ __launch_bounds__(4 * kWave) void split_kernel(const StageParams p) {
   auto V = [&](int n) { return tq[(2 * NP + n) * kWave + lane]; };
 
   if (wave <= 1) {
+    R ga[4][NQ], gb[4][NQ];
+    tile_copy(
+        [&] {
+          split_metric_column<R, NQ>(B, 0, kb, ga);
+          split_metric_column<R, NQ>(B, NQ - 1, kb, gb);
+        },
+        [] {});
     R b0[NP], b1[NP];
     if (wave == 0)
-      split_volume<R, N, NQ, true>(B, kb, P, U, V, b0, b1);
+      split_volume<R, N, NQ, true>(xm, lane, P, U, V, ga, gb, b0, b1);
     else
-      split_volume<R, N, NQ, false>(B, kb, P, U, V, b0, b1);
+      split_volume<R, N, NQ, false>(xm, lane, P, U, V, ga, gb, b0, b1);
     __syncthreads();                                   // face terms ready
     R w[NQ2], resv[NP], dq[NP];
     if (wave == 0) {
@@ -237,6 +294,13 @@ __global__ __launch_bounds__(4 * kWave) void split_kernel(const StageParams p) {
       finish_field<R, NP, MODE>(k, B.qout, B.resw, P, 1, kb, active, resv, dq);
     }
   } else {
+    if (wave == 2) {
+      MetricStage<R, NQ, 0> m;
+      tile_copy([&] { m.load(B, kb); }, [&] { m.store(xm, lane); });
+    } else {
+      MetricStage<R, NQ, 2> m;
+      tile_copy([&] { m.load(B, kb); }, [&] { m.store(xm, lane); });
+    }
     if (wave == 2)
       split_faces<R, N, NQ, 0, 2>(k, B, kb, lane, P, U, V, xf);
     else
