@@ -89,6 +89,7 @@ struct wadg_ctx_s {
   int kernel = WADG_KERNEL_AUTO;
   int cus = 256;         // compute units of the device
   double c2_scale = 1.0; // multiplies c^2 (wadg_set_c2_scale)
+  unsigned order_flip = 0;  // item order of the next stage launch (launch_stage)
   double* d_vol = nullptr;
   double* d_face = nullptr;
   float* d_vol32 = nullptr;      // geometry rounded to FP32 (FP32-bulk path)
@@ -151,8 +152,12 @@ int kernel_path(wadg_ctx c, bool fp32, int mode) {
   return WADG_KERNEL_SPLIT;
 }
 
-int launch_stage(wadg_ctx c, int mode, bool fp32, const wadg::StageParams& p, void* stream) {
+int launch_stage(wadg_ctx c, int mode, bool fp32, const wadg::StageParams& p0, void* stream) {
   const int path = kernel_path(c, fp32, mode);
+  // alternate the item order from one launch to the next (item_of)
+  wadg::StageParams p = p0;
+  c->order_flip ^= 1;
+  p.reverse = (int32_t)c->order_flip;
   if (path == WADG_KERNEL_SPLIT)
     return fp32 ? wadg::launch_stage_split_fp32(c->N, c->nq1, p, stream)
                 : wadg::launch_stage_split(c->N, c->nq1, mode, p, stream);

@@ -190,7 +190,7 @@ __global__ __launch_bounds__(kResidentWaves * kWave) void resident_kernel(const 
   R* const tiles = gf + L::face;       // [2][tile]
 
   // workgroup -> (element group, slice range)
-  const int w = xcd_remap(blockIdx.x, gridDim.x);
+  const int w = item_of(blockIdx.x, gridDim.x, p.reverse);
   const int ranges = gridDim.x / p.nEG;
   const int eg = w / ranges, rg = w - eg * ranges;
   const int spr = (p.S + ranges - 1) / ranges;

@@ -46,9 +46,10 @@ struct Split {
   static constexpr unsigned tile = 3u * NP * kWave;        // input tile [3][NP][64]
   static constexpr unsigned xf = 4u * 3 * NP1 * kWave;     // face terms [4][3][NP1][64]
   static constexpr int NM = NQ - 2;                        // metric columns staged in LDS
-  // staged metric columns [NM][4][NQ][64], later b_v [NP][64]
+  // staged metric columns [NM][4][NQ][64]; after the face-terms barrier
+  // b_v and the residuals of fields 0 and 1, [3][NP][64]
   static constexpr unsigned xm =
-      (unsigned)(NM * 4 * NQ > NP ? NM * 4 * NQ : NP) * kWave;
+      (unsigned)(NM * 4 * NQ > 3 * NP ? NM * 4 * NQ : 3 * NP) * kWave;
 };
 
 // Global geometry and state resources of one work item.
@@ -77,12 +78,15 @@ __device__ __forceinline__ void split_weights(const SplitBufs& B, unsigned wplan
 // Volume waves: the volume term of field group PRESSURE (b0 = b_p) or the
 // velocity (b0 = b_u, b1 = b_v).  Metric column 0 arrives in ga, column
 // NQ-1 in gb (both requested with the tile), the middle columns from the
-// LDS stage xm; ga is reused for them once column 0 is done.
+// LDS stage xm; ga is reused for them once column 0 is done.  The mass
+// weights of the wave's field (plane wplane) are requested before the last
+// column, when ga is free again.
 template <typename R, int N, int NQ, bool PRESSURE, typename FP, typename FU, typename FV>
-__device__ __forceinline__ void split_volume(const R* xm, int lane, const FP& P, const FU& U,
+__device__ __forceinline__ void split_volume(const SplitBufs& B, unsigned kb, unsigned wplane,
+                                             const R* xm, int lane, const FP& P, const FU& U,
                                              const FV& V, R (&ga)[4][NQ], const R (&gb)[4][NQ],
                                              R (&b0)[(N + 1) * (N + 1)],
-                                             R (&b1)[(N + 1) * (N + 1)]) {
+                                             R (&b1)[(N + 1) * (N + 1)], R (&w)[NQ * NQ]) {
   constexpr int NP = (N + 1) * (N + 1);
 #pragma unroll
   for (int n = 0; n < NP; ++n) b0[n] = b1[n] = R(0);
@@ -106,6 +110,8 @@ __device__ __forceinline__ void split_volume(const R* xm, int lane, const FP& P,
       for (int j = 0; j < NQ; ++j) ga[q][j] = xm[(((i - 1) * 4 + q) * NQ + j) * kWave + lane];
     column(i, ga);
   }
+  order();
+  split_weights<R, NQ>(B, wplane, kb, w);
   order();
   column(NQ - 1, gb);
 }
@@ -195,9 +201,10 @@ __global__ __launch_bounds__(4 * kWave) void split_kernel(const StageParams p) {
   __shared__ __attribute__((aligned(16))) R tq[tile];
   __shared__ __attribute__((aligned(16))) R xf[L::xf];
   __shared__ __attribute__((aligned(16))) R xm[L::xm];
-  R* const xv = xm;   // b_v, once the staged metric columns are dead
+  R* const xv = xm;                         // b_v, once the staged metric
+  R* const xr = xm + (size_t)L::NP * kWave;  // columns are dead; residuals 0, 1
 
-  const int w = xcd_remap(blockIdx.x, gridDim.x);
+  const int w = item_of(blockIdx.x, gridDim.x, p.reverse);
   const int Be = p.tile_groups, Bs = p.tile_slices, nEG = p.nEG;
   const int sb = w / (Bs * nEG);
   const int r = w - sb * Bs * nEG;
@@ -266,30 +273,30 @@ __global__ __launch_bounds__(4 * kWave) void split_kernel(const StageParams p) {
           split_metric_column<R, NQ>(B, NQ - 1, kb, gb);
         },
         [] {});
-    R b0[NP], b1[NP];
+    R b0[NP], b1[NP], w[NQ2];
     if (wave == 0)
-      split_volume<R, N, NQ, true>(xm, lane, P, U, V, ga, gb, b0, b1);
+      split_volume<R, N, NQ, true>(B, kb, 4 * NQ2, xm, lane, P, U, V, ga, gb, b0, b1, w);
     else
-      split_volume<R, N, NQ, false>(xm, lane, P, U, V, ga, gb, b0, b1);
+      split_volume<R, N, NQ, false>(B, kb, 5 * NQ2, xm, lane, P, U, V, ga, gb, b0, b1, w);
     __syncthreads();                                   // face terms ready
-    R w[NQ2], resv[NP], dq[NP];
+    R resv[NP], dq[NP];
     if (wave == 0) {
-      split_weights<R, NQ>(B, 4 * NQ2, kb, w);
-      load_res<R, NP, MODE>(k, B.res, 0, kb, resv);
       add_face_terms<R, N>(xf, 0, lane, b0);
-      __syncthreads();                                 // b_v handed over
+      __syncthreads();                                 // b_v, residuals handed over
+#pragma unroll
+      for (int n = 0; n < NP; ++n) resv[n] = xr[n * kWave + lane];
 #pragma unroll
       for (int q = 0; q < NQ2; ++q) w[q] *= k.c2s;
       wadg_inverse<R, N, NQ>(b0, w, dq);
       finish_field<R, NP, MODE>(k, B.qout, B.resw, P, 0, kb, active, resv, dq);
     } else {
-      split_weights<R, NQ>(B, 5 * NQ2, kb, w);
-      load_res<R, NP, MODE>(k, B.res, 1, kb, resv);
       add_face_terms<R, N>(xf, 1, lane, b0);
       add_face_terms<R, N>(xf, 2, lane, b1);
 #pragma unroll
       for (int n = 0; n < NP; ++n) xv[n * kWave + lane] = b1[n];
-      __syncthreads();                                 // b_v handed over
+      __syncthreads();                                 // b_v, residuals handed over
+#pragma unroll
+      for (int n = 0; n < NP; ++n) resv[n] = xr[(NP + n) * kWave + lane];
       wadg_inverse<R, N, NQ>(b0, w, dq);
       finish_field<R, NP, MODE>(k, B.qout, B.resw, P, 1, kb, active, resv, dq);
     }
@@ -305,19 +312,30 @@ __global__ __launch_bounds__(4 * kWave) void split_kernel(const StageParams p) {
       split_faces<R, N, NQ, 0, 2>(k, B, kb, lane, P, U, V, xf);
     else
       split_faces<R, N, NQ, 1, 3>(k, B, kb, lane, P, U, V, xf);
-    R w[NQ2], resv[NP];
     if (wave == 2) {
+      R w[NQ2], resv[NP];
       split_weights<R, NQ>(B, 5 * NQ2, kb, w);
       load_res<R, NP, MODE>(k, B.res, 2, kb, resv);
-    }
-    __syncthreads();                                   // face terms ready
-    __syncthreads();                                   // b_v handed over
-    if (wave == 2) {
+      __syncthreads();                                 // face terms ready
+      __syncthreads();                                 // b_v handed over
       R bv[NP], dq[NP];
 #pragma unroll
       for (int n = 0; n < NP; ++n) bv[n] = xv[n * kWave + lane];
       wadg_inverse<R, N, NQ>(bv, w, dq);
       finish_field<R, NP, MODE>(k, B.qout, B.resw, P, 2, kb, active, resv, dq);
+    } else {
+      // the residuals of fields 0 and 1, requested for the volume waves
+      // while they finish their volume terms
+      R r0[NP], r1[NP];
+      load_res<R, NP, MODE>(k, B.res, 0, kb, r0);
+      load_res<R, NP, MODE>(k, B.res, 1, kb, r1);
+      __syncthreads();                                 // face terms ready
+#pragma unroll
+      for (int n = 0; n < NP; ++n) {
+        xr[n * kWave + lane] = r0[n];
+        xr[(NP + n) * kWave + lane] = r1[n];
+      }
+      __syncthreads();                                 // residuals handed over
     }
   }
 }

@@ -1,7 +1,7 @@
-// Device building blocks shared by the two WADG stage kernels (the
-// streamed-geometry kernel and the LDS-resident-geometry kernel).
+// Device building blocks shared by the WADG stage kernels (streamed
+// geometry, LDS-resident geometry, split work, batched problems).
 //
-// Both kernels map one element to one lane and use the same arithmetic,
+// Every kernel maps one element to one lane and uses the same arithmetic,
 // written once here, so they produce bit-identical results:
 //
 //   * pressure / velocity volume term of one quadrature column (Section 4.1,
@@ -439,6 +439,16 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
   const int q8 = nb >> 3, r8 = nb & 7;
   const int xcd = bid & 7, jx = bid >> 3;
   return xcd * q8 + (xcd < r8 ? xcd : r8) + jx;
+}
+
+// Work item of workgroup bid: the XCD-aware order above, or the same order
+// run backwards (each XCD still takes one contiguous run of items).
+// Successive dependent launches alternate the direction, so that a launch
+// starts on the items whose inputs the previous launch wrote last -- the
+// ones most likely still held in the memory-side cache.
+__device__ __forceinline__ int item_of(int bid, int nb, int reverse) {
+  const int w = xcd_remap(bid, nb);
+  return reverse ? nb - 1 - w : w;
 }
 
 }  // namespace dev

@@ -207,7 +207,7 @@ __global__ __launch_bounds__(2 * kWave) void stage_kernel(const StageParams p) {
   constexpr unsigned KP = kWave * sizeof(R);
   __shared__ __attribute__((aligned(16))) R tq[tile];
 
-  const int w = xcd_remap(blockIdx.x, gridDim.x);
+  const int w = item_of(blockIdx.x, gridDim.x, p.reverse);
   // work item -> (slice, element group): tiles of Be element groups x Bs
   // slices, ordered (slice block, element block), slice-major inside a tile
   const int Be = p.tile_groups, Bs = p.tile_slices, nEG = p.nEG;

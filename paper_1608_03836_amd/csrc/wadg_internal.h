@@ -81,6 +81,7 @@ struct StageParams {
   double tau_p, tau_u;
   double rkA, rkB, dt;
   double c2_scale;       // c^2 multiplier (pressure mass weights)
+  int32_t reverse;       // nonzero: the work items in reverse order
 };
 
 // What a stage-kernel launch computes from the load vector b = A Qin:
