@@ -64,7 +64,7 @@ extern "C" {
 #define WADG_MAX_N 4            /* degrees 1..4 are compiled in            */
 
 /* Stage-kernel variants (wadg_set_kernel). */
-#define WADG_KERNEL_AUTO 0      /* resident where it fits, else streamed      */
+#define WADG_KERNEL_AUTO 0      /* the fastest measured per launch kind     */
 #define WADG_KERNEL_STREAMED 1  /* geometry read from global memory per item */
 #define WADG_KERNEL_RESIDENT 2  /* geometry held in LDS per element group    */
 #define WADG_KERNEL_SPLIT 3     /* one work item over four waves            */
@@ -291,8 +291,11 @@ int wadg_norms(wadg_ctx ctx, const double* A, const double* B, int32_t S, double
 /* Tuning: the order in which (slice, 64-element group) work items are
  * launched.  Items are grouped in tiles of groups_per_tile element groups x
  * slices_per_tile slices (0: all slices), slice-major inside a tile; each
- * XCD takes a contiguous range of tiles.  Results do not depend on it
- * (bitwise).  Defaults: 8, 0.  Returns WADG_E_INVALID for
+ * XCD takes a contiguous range of tiles.  Successive stage launches of a
+ * context walk this order in alternating directions, so that a launch
+ * starts on the items the previous one wrote last (memory-side cache
+ * reuse).  Results do not depend on the order (bitwise).  Defaults: 8, 0.
+ * Not thread-safe per context.  Returns WADG_E_INVALID for
  * groups_per_tile < 1 or slices_per_tile < 0. */
 int wadg_set_schedule(wadg_ctx ctx, int32_t groups_per_tile, int32_t slices_per_tile);
 
