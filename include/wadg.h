@@ -248,10 +248,12 @@ int wadg_adjoint(wadg_ctx ctx, const double* chk, const double* seed, double* gr
  * wadg_batch_integrate: every problem advanced by nsteps LSRK steps of its
  *   own dt[i] (host array, finite > 0), all slices at once.  Q (device):
  *   the batch state, in/out; work: device workspace.  Asynchronous.
- * wadg_batch_set_schedule: persistent workgroups per CU (1..64; 0 = one
- *   workgroup per work item) and work-list order (0 problem-major, 1
- *   round-robin over problems).  Results are bitwise independent of it.
- *   Defaults 2, 0.
+ * wadg_batch_set_schedule: workgroups and work-list order.  wg_per_cu 0:
+ *   one four-wave workgroup per work item (the split-work kernel, as
+ *   WADG_KERNEL_SPLIT); 1..64: that many persistent two-wave workgroups per
+ *   CU looping over the list (the streamed kernel).  order: 0 problem-major,
+ *   1 round-robin over problems.  Results are bitwise independent of it.
+ *   Defaults 0, 0 (the fastest measured on the 1000-problem workload).
  * wadg_batch_tune: the autotuner -- times one stage of every schedule
  *   candidate (1, 2, 4, 8 workgroups per CU or one per item, both orders)
  *   reps times on the device, keeps the fastest and returns it (host out:

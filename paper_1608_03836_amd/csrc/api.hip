@@ -696,7 +696,7 @@ struct wadg_batch_s {
   int32_t* d_nbr = nullptr;
   wadg::BatchProb* d_prob = nullptr;
   int32_t* d_items = nullptr;
-  int grid_mult = 2;                           // persistent workgroups per CU (0: one per item)
+  int grid_mult = 0;                           // persistent workgroups per CU (0: one per item)
   int order = 0;                               // 0 problem-major, 1 interleaved
   hipStream_t capture_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -784,7 +784,10 @@ int batch_stage(wadg_batch b, const double* qin, double* qout, double* res, int 
   p.tau_u = b->tau_u;
   p.rkA = kRkA[i];
   p.rkB = kRkB[i];
-  int e = wadg::launch_batch_stage(b->N, b->nq1, p, batch_grid(b), stream);
+  // one workgroup per item: the split-work kernel; persistent workgroups:
+  // the streamed kernel (wadg_batch_set_schedule)
+  int e = b->grid_mult == 0 ? wadg::launch_batch_split(b->N, b->nq1, p, stream)
+                            : wadg::launch_batch_stage(b->N, b->nq1, p, batch_grid(b), stream);
   if (e) return hip_fail((hipError_t)e, "batch stage kernel launch");
   return WADG_OK;
 }

@@ -191,48 +191,21 @@ __device__ __forceinline__ void add_face_terms(const R* xf, int c, int lane,
 
 }  // namespace
 
+// One work item -- a 64-element group of one slice -- over the four waves of
+// the workgroup.  B: the item's resources; k: the stage's scalars; active:
+// this lane holds an element; tq, xf, xm: the workgroup's LDS (Split<>).
 template <typename R, int N, int NQ, int MODE>
-__global__ __launch_bounds__(4 * kWave) void split_kernel(const StageParams p) {
-  static_assert(MODE == kStage || MODE == kRhs, "stage and right-hand-side modes only");
+__device__ __forceinline__ void split_item(const SplitBufs& B, const StageScalars<R>& k,
+                                           bool active, R* tq, R* xf, R* xm) {
   using L = Split<R, N, NQ>;
   constexpr int NP = L::NP, NQ2 = L::NQ2;
   constexpr unsigned tile = L::tile;
-  constexpr unsigned KP = kWave * sizeof(R);
-  __shared__ __attribute__((aligned(16))) R tq[tile];
-  __shared__ __attribute__((aligned(16))) R xf[L::xf];
-  __shared__ __attribute__((aligned(16))) R xm[L::xm];
   R* const xv = xm;                         // b_v, once the staged metric
   R* const xr = xm + (size_t)L::NP * kWave;  // columns are dead; residuals 0, 1
-
-  const int w = item_of(blockIdx.x, gridDim.x, p.reverse);
-  const int Be = p.tile_groups, Bs = p.tile_slices, nEG = p.nEG;
-  const int sb = w / (Bs * nEG);
-  const int r = w - sb * Bs * nEG;
-  const int bs = min(Bs, p.S - sb * Bs);
-  const int eb = r / (Be * bs);
-  const int r2 = r - eb * Be * bs;
-  const int be = min(Be, nEG - eb * Be);
-  const int s = sb * Bs + r2 / be;
-  const int eg = eb * Be + r2 % be;
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & (kWave - 1);
   const unsigned kb = (unsigned)lane * sizeof(R);
-
-  const R* Qin = static_cast<const R*>(p.Qin);
-  const size_t slice = (size_t)s * p.nEG * tile;
-  const size_t grp = slice + (size_t)eg * tile;
-  SplitBufs B;
-  B.qin = make_rsrc(Qin + grp, tile * sizeof(R));
-  B.qout = make_rsrc(static_cast<R*>(p.Qout) + grp, tile * sizeof(R));
-  B.res = make_rsrc(static_cast<R*>(MODE == kRhs ? p.Qout : p.res) + grp, tile * sizeof(R));
-  B.resw = make_rsrc(static_cast<R*>(p.res_out ? p.res_out : p.res) + grp,
-                     MODE == kStage ? tile * sizeof(R) : 0u);
-  B.qslice = make_rsrc(Qin + slice, (unsigned)p.nEG * tile * sizeof(R));
-  B.vol = make_rsrc(static_cast<const R*>(p.vol) + (size_t)eg * 6 * NQ2 * kWave, 6u * NQ2 * KP);
-  B.face = make_rsrc(static_cast<const R*>(p.face) + (size_t)eg * 12 * NQ * kWave,
-                     12u * NQ * KP);
-  B.nbr = make_rsrc(p.nbr + (size_t)eg * 8 * kWave, 8u * kWave * 4u);
 
   // The input tile into LDS, 16-byte chunks over all four waves, and with
   // it the volume phase's metric terms: columns 0 and NQ-1 into the volume
@@ -259,8 +232,6 @@ __global__ __launch_bounds__(4 * kWave) void split_kernel(const StageParams p) {
     __syncthreads();                                   // tile in LDS
   };
 
-  const StageScalars<R> k = stage_scalars<R>(p);
-  const bool active = eg * kWave + lane < p.K;
   auto P = [&](int n) { return tq[n * kWave + lane]; };
   auto U = [&](int n) { return tq[(NP + n) * kWave + lane]; };
   auto V = [&](int n) { return tq[(2 * NP + n) * kWave + lane]; };
@@ -340,6 +311,94 @@ __global__ __launch_bounds__(4 * kWave) void split_kernel(const StageParams p) {
   }
 }
 
+template <typename R, int N, int NQ, int MODE>
+__global__ __launch_bounds__(4 * kWave) void split_kernel(const StageParams p) {
+  static_assert(MODE == kStage || MODE == kRhs, "stage and right-hand-side modes only");
+  using L = Split<R, N, NQ>;
+  constexpr int NQ2 = L::NQ2;
+  constexpr unsigned tile = L::tile;
+  constexpr unsigned KP = kWave * sizeof(R);
+  __shared__ __attribute__((aligned(16))) R tq[tile];
+  __shared__ __attribute__((aligned(16))) R xf[L::xf];
+  __shared__ __attribute__((aligned(16))) R xm[L::xm];
+
+  const int w = item_of(blockIdx.x, gridDim.x, p.reverse);
+  const int Be = p.tile_groups, Bs = p.tile_slices, nEG = p.nEG;
+  const int sb = w / (Bs * nEG);
+  const int r = w - sb * Bs * nEG;
+  const int bs = min(Bs, p.S - sb * Bs);
+  const int eb = r / (Be * bs);
+  const int r2 = r - eb * Be * bs;
+  const int be = min(Be, nEG - eb * Be);
+  const int s = sb * Bs + r2 / be;
+  const int eg = eb * Be + r2 % be;
+  const int lane = threadIdx.x & (kWave - 1);
+
+  const R* Qin = static_cast<const R*>(p.Qin);
+  const size_t slice = (size_t)s * p.nEG * tile;
+  const size_t grp = slice + (size_t)eg * tile;
+  SplitBufs B;
+  B.qin = make_rsrc(Qin + grp, tile * sizeof(R));
+  B.qout = make_rsrc(static_cast<R*>(p.Qout) + grp, tile * sizeof(R));
+  B.res = make_rsrc(static_cast<R*>(MODE == kRhs ? p.Qout : p.res) + grp, tile * sizeof(R));
+  B.resw = make_rsrc(static_cast<R*>(p.res_out ? p.res_out : p.res) + grp,
+                     MODE == kStage ? tile * sizeof(R) : 0u);
+  B.qslice = make_rsrc(Qin + slice, (unsigned)p.nEG * tile * sizeof(R));
+  B.vol = make_rsrc(static_cast<const R*>(p.vol) + (size_t)eg * 6 * NQ2 * kWave, 6u * NQ2 * KP);
+  B.face = make_rsrc(static_cast<const R*>(p.face) + (size_t)eg * 12 * NQ * kWave,
+                     12u * NQ * KP);
+  B.nbr = make_rsrc(p.nbr + (size_t)eg * 8 * kWave, 8u * kWave * 4u);
+  split_item<R, N, NQ, MODE>(B, stage_scalars<R>(p), eg * kWave + lane < p.K, tq, xf, xm);
+}
+
+// Batched LSRK stage (FP64) over a work list of (problem, slice, element
+// group) items of many independent problems: the split-work item above, the
+// problem's state offset, geometry groups and dt taken from its descriptor.
+// One workgroup per item (grid = nitems), XCD-remapped.  Not persistent: a
+// loop over items keeps the kernel's operator constants live across
+// iterations and spills scalar registers; the persistent batch kernel is the
+// streamed one (stage_kernel.hip).
+template <int N, int NQ>
+__global__ __launch_bounds__(4 * kWave) void batch_split_kernel(const BatchParams bp) {
+  using R = double;
+  using L = Split<R, N, NQ>;
+  constexpr int NQ2 = L::NQ2;
+  constexpr unsigned tile = L::tile;
+  constexpr unsigned KP = kWave * sizeof(R);
+  __shared__ __attribute__((aligned(16))) R tq[tile];
+  __shared__ __attribute__((aligned(16))) R xf[L::xf];
+  __shared__ __attribute__((aligned(16))) R xm[L::xm];
+  const int lane = threadIdx.x & (kWave - 1);
+
+  {
+    const int it = xcd_remap(blockIdx.x, gridDim.x);
+    if (it >= bp.nitems) return;
+    const int pi = bp.items[2 * it], local = bp.items[2 * it + 1];
+    const BatchProb pr = bp.prob[pi];
+    const int s = local / pr.nEG, eg = local - s * pr.nEG;
+    const size_t slice = (size_t)pr.qoff + (size_t)s * pr.nEG * tile;
+    const size_t grp = slice + (size_t)eg * tile;
+    const size_t gg = (size_t)pr.g0 + eg;
+    SplitBufs B;
+    B.qin = make_rsrc(bp.Qin + grp, tile * sizeof(R));
+    B.qout = make_rsrc(bp.Qout + grp, tile * sizeof(R));
+    B.res = make_rsrc(bp.res + grp, tile * sizeof(R));
+    B.resw = B.res;
+    B.qslice = make_rsrc(bp.Qin + slice, (unsigned)pr.nEG * tile * sizeof(R));
+    B.vol = make_rsrc(bp.vol + gg * 6 * NQ2 * kWave, 6u * NQ2 * KP);
+    B.face = make_rsrc(bp.face + gg * 12 * NQ * kWave, 12u * NQ * KP);
+    B.nbr = make_rsrc(bp.nbr + gg * 8 * kWave, 8u * kWave * 4u);
+    StageScalars<R> k;
+    k.tau_p = bp.tau_p;
+    k.tau_u = bp.tau_u;
+    k.A = bp.rkA;
+    k.B = bp.rkB;
+    k.dt = pr.dt;
+    k.c2s = 1.0;
+    split_item<R, N, NQ, kStage>(B, k, eg * kWave + lane < pr.K, tq, xf, xm);
+  }
+}
+
 namespace {
 
 template <typename R, int N, int NQ>
@@ -376,7 +435,35 @@ int launch_r(int N, int nq, int mode, const StageParams& p, void* stream) {
   }
 }
 
+template <int N, int NQ>
+int launch_batch_nq(const BatchParams& p, void* stream) {
+  hipLaunchKernelGGL((batch_split_kernel<N, NQ>), dim3(p.nitems), dim3(4 * kWave), 0,
+                     static_cast<hipStream_t>(stream), p);
+  return (int)hipGetLastError();
+}
+
+template <int N>
+int launch_batch_n(int nq, const BatchParams& p, void* stream) {
+  switch (nq - N) {
+    case 1: return launch_batch_nq<N, N + 1>(p, stream);
+    case 2: return launch_batch_nq<N, N + 2>(p, stream);
+    case 3: return launch_batch_nq<N, N + 3>(p, stream);
+    default: return (int)hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
+
+int launch_batch_split(int N, int nq, const BatchParams& p, void* stream) {
+  if (p.nitems <= 0) return 0;
+  switch (N) {
+    case 1: return launch_batch_n<1>(nq, p, stream);
+    case 2: return launch_batch_n<2>(nq, p, stream);
+    case 3: return launch_batch_n<3>(nq, p, stream);
+    case 4: return launch_batch_n<4>(nq, p, stream);
+    default: return (int)hipErrorInvalidValue;
+  }
+}
 
 int launch_stage_split(int N, int nq, int mode, const StageParams& p, void* stream) {
   return launch_r<double>(N, nq, mode, p, stream);

@@ -146,9 +146,12 @@ struct BatchParams {
   const int32_t* nbr;    // [all groups][2][4][64]
   double tau_p, tau_u, rkA, rkB;
 };
-// grid = number of persistent workgroups (each loops over items with stride
-// grid), or nitems for one workgroup per item.
+// Streamed kernel, persistent two-wave workgroups: grid = number of
+// workgroups (each loops over items with stride grid), or nitems for one
+// workgroup per item.
 int launch_batch_stage(int N, int nq, const BatchParams& p, int grid, void* stream);
+// Split-work kernel, one four-wave workgroup per item.
+int launch_batch_split(int N, int nq, const BatchParams& p, void* stream);
 
 // Per-slice norms over the tiled layout (padding skipped): partial sums into
 // `partials` [S][nblk][4] then a fixed-order reduction into `out` [S][4].
