@@ -318,7 +318,9 @@ int wadg_set_schedule(wadg_ctx ctx, int32_t groups_per_tile, int32_t slices_per_
  *     kernel, right-hand-side launches the resident kernel where it fits,
  *     else the split kernel -- the fastest measured on MI355X.
  * All variants give bitwise-identical results.  The adjoint's operator
- * launches always use the streamed kernel.  Returns WADG_E_INVALID for an
+ * launches (apply-A) take the split kernel under AUTO and SPLIT, else the
+ * streamed kernel (the resident kernel has no apply-A mode).  Returns
+ * WADG_E_INVALID for an
  * unknown value and WADG_E_UNSUPPORTED when the resident kernel is
  * requested for an (N, nq1) whose FP64 geometry does not fit. */
 int wadg_set_kernel(wadg_ctx ctx, int32_t kernel);

@@ -144,7 +144,9 @@ int check_slices(wadg_ctx c, int32_t S) {
 // the adjoint exists in the streamed kernel only.)
 int kernel_path(wadg_ctx c, bool fp32, int mode) {
   const bool fits = wadg::resident_supported(c->N, c->nq1, fp32);
-  if (mode == wadg::kApplyA) return WADG_KERNEL_STREAMED;
+  if (mode == wadg::kApplyA)   // no resident apply-A mode
+    return c->kernel == WADG_KERNEL_AUTO || c->kernel == WADG_KERNEL_SPLIT ? WADG_KERNEL_SPLIT
+                                                                           : WADG_KERNEL_STREAMED;
   if (c->kernel == WADG_KERNEL_RESIDENT && fits) return WADG_KERNEL_RESIDENT;
   if (c->kernel != WADG_KERNEL_AUTO) return c->kernel == WADG_KERNEL_RESIDENT
                                                 ? WADG_KERNEL_STREAMED : c->kernel;

@@ -1,9 +1,10 @@
 // Fused WADG stage kernel for gfx950, split-work variant.
 //
-// The same stage (or right-hand side) and the same arithmetic as the other
-// stage kernels (stage_common.h), with one 64-element group of one slice
-// spread over four waves instead of two, so that each wave carries about
-// a quarter of the item and two workgroups share a CU (two waves per SIMD):
+// The same stage (or right-hand side, or the adjoint's apply-A product) and
+// the same arithmetic as the other stage kernels (stage_common.h), with one
+// 64-element group of one slice spread over four waves instead of two, so
+// that each wave carries about a quarter of the item and two workgroups
+// share a CU (two waves per SIMD):
 //
 //   wave 0  pressure volume term (Section 4.1), then the pressure mass
 //           inverse and update;
@@ -81,7 +82,8 @@ __device__ __forceinline__ void split_weights(const SplitBufs& B, unsigned wplan
 // LDS stage xm; ga is reused for them once column 0 is done.  The mass
 // weights of the wave's field (plane wplane) are requested before the last
 // column, when ga is free again.
-template <typename R, int N, int NQ, bool PRESSURE, typename FP, typename FU, typename FV>
+template <typename R, int N, int NQ, bool PRESSURE, bool WEIGHTS, typename FP, typename FU,
+          typename FV>
 __device__ __forceinline__ void split_volume(const SplitBufs& B, unsigned kb, unsigned wplane,
                                              const R* xm, int lane, const FP& P, const FU& U,
                                              const FV& V, R (&ga)[4][NQ], const R (&gb)[4][NQ],
@@ -111,7 +113,7 @@ __device__ __forceinline__ void split_volume(const SplitBufs& B, unsigned kb, un
     column(i, ga);
   }
   order();
-  split_weights<R, NQ>(B, wplane, kb, w);
+  if constexpr (WEIGHTS) split_weights<R, NQ>(B, wplane, kb, w);
   order();
   column(NQ - 1, gb);
 }
@@ -206,6 +208,17 @@ __device__ __forceinline__ void split_item(const SplitBufs& B, const StageScalar
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & (kWave - 1);
   const unsigned kb = (unsigned)lane * sizeof(R);
+  // Apply-A mode (the adjoint's outer factor) takes the load vector itself:
+  // no mass inverse and no mass weights.
+  constexpr bool kInv = MODE != kApplyA;
+  auto inverse = [](const R(&b)[NP], const R(&w)[NQ2], R(&dq)[NP]) {
+    if constexpr (kInv) {
+      wadg_inverse<R, N, NQ>(b, w, dq);
+    } else {
+#pragma unroll
+      for (int n = 0; n < NP; ++n) dq[n] = b[n];
+    }
+  };
 
   // The input tile into LDS, 16-byte chunks over all four waves, and with
   // it the volume phase's metric terms: columns 0 and NQ-1 into the volume
@@ -246,9 +259,9 @@ __device__ __forceinline__ void split_item(const SplitBufs& B, const StageScalar
         [] {});
     R b0[NP], b1[NP], w[NQ2];
     if (wave == 0)
-      split_volume<R, N, NQ, true>(B, kb, 4 * NQ2, xm, lane, P, U, V, ga, gb, b0, b1, w);
+      split_volume<R, N, NQ, true, kInv>(B, kb, 4 * NQ2, xm, lane, P, U, V, ga, gb, b0, b1, w);
     else
-      split_volume<R, N, NQ, false>(B, kb, 5 * NQ2, xm, lane, P, U, V, ga, gb, b0, b1, w);
+      split_volume<R, N, NQ, false, kInv>(B, kb, 5 * NQ2, xm, lane, P, U, V, ga, gb, b0, b1, w);
     __syncthreads();                                   // face terms ready
     R resv[NP], dq[NP];
     if (wave == 0) {
@@ -256,9 +269,11 @@ __device__ __forceinline__ void split_item(const SplitBufs& B, const StageScalar
       __syncthreads();                                 // b_v, residuals handed over
 #pragma unroll
       for (int n = 0; n < NP; ++n) resv[n] = xr[n * kWave + lane];
+      if constexpr (kInv) {
 #pragma unroll
-      for (int q = 0; q < NQ2; ++q) w[q] *= k.c2s;
-      wadg_inverse<R, N, NQ>(b0, w, dq);
+        for (int q = 0; q < NQ2; ++q) w[q] *= k.c2s;
+      }
+      inverse(b0, w, dq);
       finish_field<R, NP, MODE>(k, B.qout, B.resw, P, 0, kb, active, resv, dq);
     } else {
       add_face_terms<R, N>(xf, 1, lane, b0);
@@ -268,7 +283,7 @@ __device__ __forceinline__ void split_item(const SplitBufs& B, const StageScalar
       __syncthreads();                                 // b_v, residuals handed over
 #pragma unroll
       for (int n = 0; n < NP; ++n) resv[n] = xr[(NP + n) * kWave + lane];
-      wadg_inverse<R, N, NQ>(b0, w, dq);
+      inverse(b0, w, dq);
       finish_field<R, NP, MODE>(k, B.qout, B.resw, P, 1, kb, active, resv, dq);
     }
   } else {
@@ -285,14 +300,14 @@ __device__ __forceinline__ void split_item(const SplitBufs& B, const StageScalar
       split_faces<R, N, NQ, 1, 3>(k, B, kb, lane, P, U, V, xf);
     if (wave == 2) {
       R w[NQ2], resv[NP];
-      split_weights<R, NQ>(B, 5 * NQ2, kb, w);
+      if constexpr (kInv) split_weights<R, NQ>(B, 5 * NQ2, kb, w);
       load_res<R, NP, MODE>(k, B.res, 2, kb, resv);
       __syncthreads();                                 // face terms ready
       __syncthreads();                                 // b_v handed over
       R bv[NP], dq[NP];
 #pragma unroll
       for (int n = 0; n < NP; ++n) bv[n] = xv[n * kWave + lane];
-      wadg_inverse<R, N, NQ>(bv, w, dq);
+      inverse(bv, w, dq);
       finish_field<R, NP, MODE>(k, B.qout, B.resw, P, 2, kb, active, resv, dq);
     } else {
       // the residuals of fields 0 and 1, requested for the volume waves
@@ -313,7 +328,7 @@ __device__ __forceinline__ void split_item(const SplitBufs& B, const StageScalar
 
 template <typename R, int N, int NQ, int MODE>
 __global__ __launch_bounds__(4 * kWave) void split_kernel(const StageParams p) {
-  static_assert(MODE == kStage || MODE == kRhs, "stage and right-hand-side modes only");
+  static_assert(MODE != kApplyA || sizeof(R) == sizeof(double), "apply-A mode is FP64 only");
   using L = Split<R, N, NQ>;
   constexpr int NQ2 = L::NQ2;
   constexpr unsigned tile = L::tile;
@@ -405,12 +420,18 @@ template <typename R, int N, int NQ>
 int launch_nq(int mode, const StageParams& p, void* stream) {
   const dim3 grid(p.nEG * p.S), block(4 * kWave);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (mode == kStage)
+  if (mode == kStage) {
     hipLaunchKernelGGL((split_kernel<R, N, NQ, kStage>), grid, block, 0, st, p);
-  else if (mode == kRhs && sizeof(R) == sizeof(double))
-    hipLaunchKernelGGL((split_kernel<R, N, NQ, kRhs>), grid, block, 0, st, p);
-  else
+  } else if constexpr (sizeof(R) == sizeof(double)) {
+    if (mode == kRhs)
+      hipLaunchKernelGGL((split_kernel<R, N, NQ, kRhs>), grid, block, 0, st, p);
+    else if (mode == kApplyA)
+      hipLaunchKernelGGL((split_kernel<R, N, NQ, kApplyA>), grid, block, 0, st, p);
+    else
+      return (int)hipErrorInvalidValue;
+  } else {
     return (int)hipErrorInvalidValue;
+  }
   return (int)hipGetLastError();
 }
 

@@ -159,3 +159,25 @@ def test_full_size_adjoint_fd_and_transpose(W):
     rhs = torch.sum(x * PhiTw).item()
     print(f"adj128: <Phi x, w> = {lhs:.15e}, <x, Phi^T w> = {rhs:.15e}", flush=True)
     assert abs(lhs - rhs) <= 1e-10 * torch.linalg.norm(x).item() * torch.linalg.norm(w).item()
+
+
+def test_adjoint_kernel_variants_bitwise(W):
+    """The adjoint's apply-A launches run on the split kernel (default) or
+    the streamed kernel; forward checkpoints and the reverse sweep give the
+    same bits either way."""
+    _print_case(test="adjoint-kernels", workload="adj4-K1D8")
+    prob = make_sensitivity_problem("adj4", K1D=8)
+    outs = []
+    for kern in (W.WADG_KERNEL_AUTO, W.WADG_KERNEL_STREAMED):
+        sol = _solver(W, prob)
+        sol.set_kernel(kern)
+        y0 = sol.upload(prob.y0[None])
+        chk = sol.forward_checkpoints(y0, prob.S, prob.dt, prob.nsteps)
+        states = sol.download(chk, prob.S + 1)
+        seed = _seed(sol, states[-1], prob.p_target)
+        grad, dscale = sol.adjoint(chk, seed, prob.S, prob.dt, prob.nsteps)
+        outs.append((states, sol.download(grad, 1)[0], dscale))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.all(np.isfinite(outs[0][1]))
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert outs[0][2] == outs[1][2]

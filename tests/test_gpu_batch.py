@@ -138,3 +138,35 @@ def test_full_batch_sampled_problems(W):
         q = sol.upload(p.Q0)
         sol.integrate(q, p.S, p.dt, 1)
         assert np.array_equal(sol.download(q, p.S), g), i
+
+
+@pytest.mark.parametrize("N,nq1", [(1, 2), (2, 4), (4, 6)])
+def test_other_degrees_both_batch_kernels(W, N, nq1):
+    """Batches of other degrees and quadratures, mixing packed (4 and 9
+    elements) and multi-group (100 elements) meshes with c^2 varying: every
+    problem equals the single-problem path bitwise, with the split-work
+    kernel (one workgroup per item) and with persistent workgroups."""
+    from workloads import periodic_quad_mesh, c2_layered
+    _print_case(test="batch-degrees", N=N, nq1=nq1)
+    meshes = [periodic_quad_mesh(k, N, eps=0.05, warp="skew", rotate_seed=k) for k in (2, 3, 10)]
+    S = [5, 3, 2]
+    rng = np.random.default_rng(N)
+    Q0 = [rng.standard_normal((s, 3, m.Np, m.K)) for m, s in zip(meshes, S)]
+    dts = [0.1 / (m.K1D * (N + 1) ** 2) for m in meshes]
+    batch = W.Batch(meshes, S, nq1=nq1, c2=c2_layered)
+    assert max(batch.pack) > 1 and min(batch.pack) == 1
+    outs = []
+    for wg in (0, 2):
+        batch.set_schedule(wg, 0)
+        Q = batch.upload(Q0)
+        batch.integrate(Q, dts, 2)
+        outs.append(batch.download(Q))
+    batch.set_schedule(0, 0)
+    for i, (m, s) in enumerate(zip(meshes, S)):
+        sol = W.Solver(m, nq1=nq1, c2=c2_layered)
+        q = sol.upload(Q0[i])
+        sol.integrate(q, s, dts[i], 2)
+        want = sol.download(q, s)
+        assert np.all(np.isfinite(want))
+        assert np.array_equal(outs[0][i], want), (i, "split")
+        assert np.array_equal(outs[1][i], want), (i, "persistent")
