@@ -104,8 +104,8 @@ def cpu_baseline(prob, seconds):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
-              "the sweep shards by slices without communication, see the design notes",
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the sweep shards "
+              "over slices with no communication, so N GPUs would each advance S/N slices",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np
