@@ -184,6 +184,9 @@ def main():
                    "unknowns_per_slice": 3 * nodes, "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     # measured HBM bytes (the counters) at this run's launch time
+                     "traffic_frac": (None if traffic is None else
+                                      traffic / (stage_ms * 1e-3) / 1e9 / PEAK_HBM_GBS),
                      "kernel": kname,
                      "avg_launch_us": stage_ms * 1e3,
                      "algorithmic_bytes_per_launch": bytes_launch},
