@@ -9,6 +9,12 @@ the per-slice reductions (norms, finite check).  Default workload: wadg64
 
 Prints one JSON line.  ``value`` = grid-point-steps/s: slices x nodes per
 slice (one node carries p, u, v) x LSRK steps per slice / seconds per step.
+
+``--path`` selects another part of the library, each also one JSON line:
+fp32 (FP32-bulk sweep, with its error against the FP64 sweep), batch (the
+1000-problem batch, one 4-step sweep per step), adjoint (forward sweep with
+checkpoints plus the reverse sweep on the 128 x 128 sensitivity problem),
+parareal (the wadg64 trajectory by parareal, against the serial fine sweep).
 """
 
 import argparse
@@ -28,6 +34,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--path", choices=("fp64", "fp32", "batch", "adjoint", "parareal"),
+                    default="fp64", help="what to measure (default: the FP64 sweep)")
     ap.add_argument("--workload", default="wadg64")
     ap.add_argument("--tile-groups", type=int, default=None,
                     help="schedule: element groups per tile (default: library default)")
@@ -42,14 +50,15 @@ def parse():
     return ap.parse_args()
 
 
-def stage_bytes(K, S, N, nq1):
+def stage_bytes(K, S, N, nq1, word=8):
     """Algorithmic HBM bytes of one stage launch, averaged over the 5 stages:
     per element and slice, read Q_in and write Q_out and res (3 (N+1)^2
-    doubles each) and read res in 4 of the 5 stages; per element, read the
-    geometry once (6 nq1^2 volume + 12 nq1 face doubles, 8 int32 offsets)."""
+    values each) and read res in 4 of the 5 stages; per element, read the
+    geometry once (6 nq1^2 volume + 12 nq1 face values, 8 int32 offsets).
+    word: bytes per value (8 FP64, 4 FP32-bulk)."""
     Np = (N + 1) ** 2
-    per_elem_slice = 3 * Np * 8 * (3 + 4 / 5)
-    per_elem = (6 * nq1 * nq1 + 12 * nq1) * 8 + 8 * 4
+    per_elem_slice = 3 * Np * word * (3 + 4 / 5)
+    per_elem = (6 * nq1 * nq1 + 12 * nq1) * word + 8 * 4
     return K * (S * per_elem_slice + per_elem)
 
 
@@ -101,6 +110,239 @@ def cpu_baseline(prob, seconds):
                       f"({prob.K} elements, N={prob.N}), numpy FP64, 1 thread, {el:.1f} s"}
 
 
+def common(args, value, ms_per_step, dtype, config):
+    return {"metric": "grid-point-steps/sec", "value": value, "unit": "grid-point-steps/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": config}
+
+
+def roofline(kname, bytes_launch, stage_ms, traffic=None):
+    achieved = bytes_launch / (stage_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+            # measured HBM bytes (the counters) at this run's launch time
+            "traffic_frac": (None if traffic is None else
+                             traffic / (stage_ms * 1e-3) / 1e9 / PEAK_HBM_GBS),
+            "kernel": kname, "avg_launch_us": stage_ms * 1e3,
+            "algorithmic_bytes_per_launch": bytes_launch}
+
+
+def timed(args, torch, stream, body):
+    """warmup untimed calls of body(), then args.steps timed ones bracketed by
+    synchronisations; returns (wall seconds, [HIP-event ms of each call])."""
+    for _ in range(args.warmup):
+        body()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        body()
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, [a.elapsed_time(b) for a, b in ev]
+
+
+def run_fp32(args):
+    """FP32-bulk sweep (state, residual and geometry FP32 inside the sweep,
+    FP64 in and out) of the whole workload; error against the FP64 sweep of
+    the same start states."""
+    import numpy as np
+    import torch
+    import paper_1608_03836_amd as W
+    from workloads import make_problem
+    prob = make_problem(args.workload)
+    sol = W.Solver.from_problem(prob)
+    S, K, N = prob.S, prob.K, prob.N
+    stream = torch.cuda.current_stream()
+    Q64 = sol.upload(prob.Q0)
+    sol.integrate(Q64, S, prob.dt, prob.nsteps, stream=stream)
+    Q = sol.upload(prob.Q0)
+    work = sol.workspace_fp32(S)
+    sol.integrate_fp32(Q, S, prob.dt, prob.nsteps, work=work, stream=stream)
+    torch.cuda.synchronize()
+    d = (Q - Q64).reshape(S, -1)
+    rel = float(torch.max(torch.linalg.norm(d, dim=1) /
+                          torch.linalg.norm(Q64.reshape(S, -1), dim=1)).item())
+    del Q64
+    elapsed, ev = timed(args, torch, stream,
+                        lambda: sol.integrate_fp32(Q, S, prob.dt, prob.nsteps, work=work,
+                                                   stream=stream))
+    norms = sol.norms(Q, None, S)
+    assert np.all(norms[:, 3] == 1.0), "non-finite state"
+    nodes = K * (N + 1) ** 2
+    line = common(args, S * nodes * prob.nsteps / (elapsed / args.steps),
+                  1e3 * elapsed / args.steps, "f32",
+                  {"workload": prob.name, "path": "fp32-bulk", "elements": K, "degree": N,
+                   "nq1": prob.nq1, "slices": S, "lsrk_steps_per_slice": prob.nsteps,
+                   "parallelism": "single-gpu"})
+    k = {W.WADG_KERNEL_STREAMED: "stage_kernel", W.WADG_KERNEL_RESIDENT: "resident_kernel",
+         W.WADG_KERNEL_SPLIT: "split_kernel"}[sol.kernel_in_use(fp32=True)]
+    # the events bracket the whole call: 5 nsteps stage launches plus the two
+    # FP64<->FP32 conversions at the ends of the sweep
+    line["roofline"] = roofline(f"{k}<float,{N},{prob.nq1},false>",
+                                stage_bytes(K, S, N, prob.nq1, word=4),
+                                sum(ev) / (args.steps * 5 * prob.nsteps))
+    line["max_rel_err_vs_fp64_sweep"] = rel
+    if args.cpu_baseline_seconds > 0:
+        line["cpu_baseline"] = cpu_baseline(prob, args.cpu_baseline_seconds)
+    print(json.dumps(line), flush=True)
+
+
+def run_batch(args):
+    """The 1000-problem batch: one 4-step sweep of every problem per step."""
+    import numpy as np
+    import torch
+    import paper_1608_03836_amd as W
+    from threadpoolctl import threadpool_limits
+    from workloads import make_batch
+    from oracle import WADGOracle
+    probs = make_batch()
+    batch = W.Batch([p.mesh for p in probs], [p.S for p in probs])
+    dts = [p.dt for p in probs]
+    nsteps = probs[0].nsteps
+    stream = torch.cuda.current_stream()
+    Q = batch.upload([p.Q0 for p in probs])
+    work = batch.workspace()
+    elapsed, ev = timed(args, torch, stream,
+                        lambda: batch.integrate(Q, dts, nsteps, work=work, stream=stream))
+    N, nq1 = batch.N, batch.nq1
+    gps = sum(p.S * p.mesh.K * (N + 1) ** 2 for p in probs) * nsteps
+    line = common(args, gps / (elapsed / args.steps), 1e3 * elapsed / args.steps, "f64",
+                  {"workload": "batch1000", "problems": len(probs),
+                   "elements": int(sum(p.mesh.K for p in probs)),
+                   "slices": int(sum(p.S for p in probs)), "degree": N, "nq1": nq1,
+                   "lsrk_steps_per_slice": nsteps, "parallelism": "single-gpu"})
+    line["roofline"] = roofline(f"batch_split_kernel<{N},{nq1}>",
+                                sum(stage_bytes(p.mesh.K, p.S, N, nq1) for p in probs),
+                                sum(ev) / (args.steps * 5 * nsteps))
+    if args.cpu_baseline_seconds > 0:
+        # the oracle on the first problems of the list, whole problems, until
+        # about the requested time
+        with threadpool_limits(1):
+            done, el, npb = 0, 0.0, 0
+            for p in probs:
+                o = WADGOracle(p.mesh)
+                t0 = time.perf_counter()
+                for s in range(p.S):
+                    o.integrate(p.Q0[s], p.dt, p.nsteps)
+                el += time.perf_counter() - t0
+                done += p.S * p.mesh.K * (N + 1) ** 2 * p.nsteps
+                npb += 1
+                if el >= args.cpu_baseline_seconds:
+                    break
+        line["cpu_baseline"] = {"value": done / el, "unit": "grid-point-steps/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": f"the first {npb} problems of the batch, every slice, "
+                                          f"{nsteps} LSRK steps, numpy FP64, 1 thread, {el:.1f} s"}
+    print(json.dumps(line), flush=True)
+
+
+def run_adjoint(args):
+    """Forward sweep with checkpoints plus the reverse (adjoint) sweep: one
+    gradient of the terminal objective with respect to the start state and
+    the c^2 scale, on the 128 x 128 sensitivity problem."""
+    import numpy as np
+    import torch
+    import paper_1608_03836_amd as W
+    from workloads import make_sensitivity_problem
+    from paper_1608_03836_amd.autograd import pressure_mask
+    prob = make_sensitivity_problem("adj128")
+    sol = W.Solver(prob.mesh, nq1=prob.nq1, c2=prob.c0, tau_p=prob.tau_p, tau_u=prob.tau_u)
+    sol.set_c2_scale(prob.gamma)
+    stream = torch.cuda.current_stream()
+    y0 = sol.upload(prob.y0[None])
+    work = sol.adjoint_workspace(prob.nsteps)
+    target = np.zeros((1, 3) + prob.p_target.shape)
+    target[0, 0] = prob.p_target
+    target = sol.upload(target)
+    mask = pressure_mask(sol)
+    n1 = sol.slice_doubles
+    fw, rv = [], []
+
+    def body():
+        a, b, c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        a.record(stream)
+        chk = sol.forward_checkpoints(y0, prob.S, prob.dt, prob.nsteps, work=work, stream=stream)
+        b.record(stream)
+        seed = (2.0 * mask * (chk[prob.S * n1:] - target)).contiguous()
+        sol.adjoint(chk, seed, prob.S, prob.dt, prob.nsteps, work=work, stream=stream)
+        c.record(stream)
+        fw.append((a, b))
+        rv.append((b, c))
+
+    elapsed, _ = timed(args, torch, stream, body)
+    fwd = sum(a.elapsed_time(b) for a, b in fw[-args.steps:]) / args.steps
+    rev = sum(a.elapsed_time(b) for a, b in rv[-args.steps:]) / args.steps
+    nodes = prob.mesh.K * (prob.mesh.N + 1) ** 2
+    line = common(args, prob.S * prob.nsteps * nodes / (elapsed / args.steps),
+                  1e3 * elapsed / args.steps, "f64",
+                  {"workload": prob.name, "path": "forward + adjoint",
+                   "elements": prob.mesh.K, "degree": prob.mesh.N, "nq1": prob.nq1,
+                   "checkpointed_slices": prob.S, "lsrk_steps_per_slice": prob.nsteps,
+                   "parallelism": "single-gpu"})
+    line["forward_ms"] = fwd
+    line["adjoint_ms"] = rev
+    # one-slice launches (6.3 MB of state each) are cache-resident: no roofline point
+    line["roofline"] = None
+    if args.cpu_baseline_seconds > 0:
+        from workloads import make_problem
+        from types import SimpleNamespace
+        p = SimpleNamespace(mesh=prob.mesh, nq1=prob.nq1, c2=lambda x, y: prob.gamma * prob.c0(x, y),
+                            tau_p=prob.tau_p, tau_u=prob.tau_u, Q0=prob.y0[None], dt=prob.dt,
+                            nsteps=prob.nsteps, K=prob.mesh.K, N=prob.mesh.N, name=prob.name)
+        line["cpu_baseline"] = cpu_baseline(p, args.cpu_baseline_seconds)
+        line["cpu_baseline"]["sample"] += " (forward sweep only)"
+    print(json.dumps(line), flush=True)
+
+
+def run_parareal(args):
+    """The wadg64 trajectory (slice 0's start state, 64 slices of 32 steps)
+    by parareal with a 16-step coarse sweep, against the serial fine sweep."""
+    import numpy as np
+    import torch
+    import paper_1608_03836_amd as W
+    from workloads import make_problem
+    prob = make_problem("wadg64", slices=[0])
+    sol = W.Solver.from_problem(prob)
+    S, nf, nc = 64, prob.nsteps, 16
+    stream = torch.cuda.current_stream()
+    y0 = sol.upload(prob.Q0[:1])
+    work1 = sol.workspace(1)
+    q = y0.clone()
+    sol.integrate(q, 1, prob.dt, 1, work=work1, stream=stream)
+    torch.cuda.synchronize()
+    q = y0.clone()
+    t0 = time.perf_counter()
+    for _ in range(S):
+        sol.integrate(q, 1, prob.dt, nf, work=work1, stream=stream)
+    torch.cuda.synchronize()
+    serial = time.perf_counter() - t0
+    res = {}
+
+    def body():
+        res["out"] = sol.parareal(y0, S, prob.dt, nf, nc, max_iter=12, tol=1e-8, stream=stream)
+
+    elapsed, _ = timed(args, torch, stream, body)
+    U, it, ch = res["out"]
+    err = float(torch.linalg.norm(U[S * sol.slice_doubles:] - q) / torch.linalg.norm(q))
+    nodes = prob.K * (prob.N + 1) ** 2
+    line = common(args, S * nf * nodes / (elapsed / args.steps), 1e3 * elapsed / args.steps,
+                  "f64", {"workload": "wadg64-trajectory", "path": "parareal",
+                          "elements": prob.K, "degree": prob.N, "slices": S,
+                          "fine_steps_per_slice": nf, "coarse_steps_per_slice": nc,
+                          "parallelism": "single-gpu"})
+    line.update({"iterations": it, "last_change": ch, "rel_err_vs_serial_fine": err,
+                 "serial_fine_ms": serial * 1e3,
+                 "speedup_vs_serial_fine": serial / (elapsed / args.steps), "roofline": None})
+    if args.cpu_baseline_seconds > 0:
+        line["cpu_baseline"] = cpu_baseline(prob, args.cpu_baseline_seconds)
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -108,6 +350,10 @@ def main():
               "over slices with no communication, so N GPUs would each advance S/N slices",
               file=sys.stderr)
         sys.exit(2)
+    other = {"fp32": run_fp32, "batch": run_batch, "adjoint": run_adjoint,
+             "parareal": run_parareal}
+    if args.path in other:
+        return other[args.path](args)
     import numpy as np
     import torch
     import paper_1608_03836_amd as W
