@@ -128,6 +128,17 @@ def roofline(kname, bytes_launch, stage_ms, traffic=None):
             "algorithmic_bytes_per_launch": bytes_launch}
 
 
+def calibrate(args, torch):
+    """The known-size device copy that HBM byte counters are scaled by."""
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+
 def timed(args, torch, stream, body):
     """warmup untimed calls of body(), then args.steps timed ones bracketed by
     synchronisations; returns (wall seconds, [HIP-event ms of each call])."""
@@ -168,6 +179,7 @@ def run_fp32(args):
     rel = float(torch.max(torch.linalg.norm(d, dim=1) /
                           torch.linalg.norm(Q64.reshape(S, -1), dim=1)).item())
     del Q64
+    calibrate(args, torch)
     elapsed, ev = timed(args, torch, stream,
                         lambda: sol.integrate_fp32(Q, S, prob.dt, prob.nsteps, work=work,
                                                    stream=stream))
@@ -183,9 +195,10 @@ def run_fp32(args):
          W.WADG_KERNEL_SPLIT: "split_kernel"}[sol.kernel_in_use(fp32=True)]
     # the events bracket the whole call: 5 nsteps stage launches plus the two
     # FP64<->FP32 conversions at the ends of the sweep
-    line["roofline"] = roofline(f"{k}<float,{N},{prob.nq1},false>",
-                                stage_bytes(K, S, N, prob.nq1, word=4),
-                                sum(ev) / (args.steps * 5 * prob.nsteps))
+    kname = f"{k}<float,{N},{prob.nq1},false>"
+    line["roofline"] = roofline(kname, stage_bytes(K, S, N, prob.nq1, word=4),
+                                sum(ev) / (args.steps * 5 * prob.nsteps),
+                                measured_traffic(kname, prob.name))
     line["max_rel_err_vs_fp64_sweep"] = rel
     if args.cpu_baseline_seconds > 0:
         line["cpu_baseline"] = cpu_baseline(prob, args.cpu_baseline_seconds)
@@ -207,6 +220,7 @@ def run_batch(args):
     stream = torch.cuda.current_stream()
     Q = batch.upload([p.Q0 for p in probs])
     work = batch.workspace()
+    calibrate(args, torch)
     elapsed, ev = timed(args, torch, stream,
                         lambda: batch.integrate(Q, dts, nsteps, work=work, stream=stream))
     N, nq1 = batch.N, batch.nq1
@@ -216,9 +230,10 @@ def run_batch(args):
                    "elements": int(sum(p.mesh.K for p in probs)),
                    "slices": int(sum(p.S for p in probs)), "degree": N, "nq1": nq1,
                    "lsrk_steps_per_slice": nsteps, "parallelism": "single-gpu"})
-    line["roofline"] = roofline(f"batch_split_kernel<{N},{nq1}>",
-                                sum(stage_bytes(p.mesh.K, p.S, N, nq1) for p in probs),
-                                sum(ev) / (args.steps * 5 * nsteps))
+    kname = f"batch_split_kernel<{N},{nq1}>"
+    line["roofline"] = roofline(kname, sum(stage_bytes(p.mesh.K, p.S, N, nq1) for p in probs),
+                                sum(ev) / (args.steps * 5 * nsteps),
+                                measured_traffic(kname, "batch1000"))
     if args.cpu_baseline_seconds > 0:
         # the oracle on the first problems of the list, whole problems, until
         # about the requested time
@@ -378,13 +393,7 @@ def main():
         out = sol.norms(Q, None, S, stream=stream)
         return out
 
-    if args.copy_calibration_mib:
-        n = args.copy_calibration_mib * (1 << 20) // 8
-        src = torch.ones(n, dtype=torch.float64, device=sol.device)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    calibrate(args, torch)
 
     for _ in range(args.warmup):
         step()
