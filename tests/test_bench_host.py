@@ -1,0 +1,57 @@
+"""CPU: the host-side logic of bench.py -- the algorithmic byte count the
+roofline divides by, the traffic record lookup (reported only while the
+kernel sources hash as they did when the counters were taken), and the
+one-GPU refusal."""
+
+import hashlib
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_stage_bytes_by_hand():
+    # N = 3, nq1 = 5: per element and slice 3 fields x 16 nodes x 8 B x
+    # (read Q_in, write Q_out, write res, read res in 4 of 5 stages) = 1459.2 B;
+    # per element geometry (6 x 25 + 12 x 5) x 8 B + 8 int32 = 1712 B
+    assert bench.stage_bytes(1, 1, 3, 5) == pytest.approx(1459.2 + 1712)
+    assert bench.stage_bytes(4096, 64, 3, 5) == pytest.approx(4096 * (64 * 1459.2 + 1712))
+    # FP32-bulk: values are 4 bytes, the int32 offsets stay 32 B
+    assert bench.stage_bytes(1, 1, 3, 5, word=4) == pytest.approx(729.6 + 840 + 32)
+
+
+def test_traffic_record_follows_the_sources(tmp_path, monkeypatch):
+    src = tmp_path / "k.hip"
+    src.write_text("kernel v1\n")
+    (tmp_path / "profiles").mkdir()
+    rec = {"kernel": "k<double>", "workload": "w", "fetch_bytes_per_launch": 300,
+           "write_bytes_per_launch": 200, "sources": ["k.hip"],
+           "sources_sha1": hashlib.sha1(b"kernel v1\n").hexdigest()}
+    (tmp_path / "profiles" / "hbm_traffic.json").write_text(json.dumps({"records": [rec]}))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("k<double>", "w") == 500
+    assert bench.measured_traffic("k<double>", "other") is None
+    assert bench.measured_traffic("other", "w") is None
+    src.write_text("kernel v2\n")               # the kernel changed since the counters
+    assert bench.measured_traffic("k<double>", "w") is None
+
+
+def test_roofline_fields():
+    r = bench.roofline("k", 8e9, 1.0, traffic=4e9)
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
+    assert r["achieved"] == pytest.approx(8000.0) and r["frac"] == pytest.approx(1.0)
+    assert r["traffic_frac"] == pytest.approx(0.5)
+    assert bench.roofline("k", 8e9, 2.0)["traffic_frac"] is None
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr
