@@ -140,8 +140,9 @@ int check_slices(wadg_ctx c, int32_t S) {
 // Automatic choice, from measurement on MI355X (64x64 and 128x128
 // elements, N = 3, FP64 and FP32): LSRK stages take the split-work kernel;
 // right-hand-side launches take the resident-geometry kernel where the
-// geometry fits in LDS, else the split-work kernel.  (The apply-A mode of
-// the adjoint exists in the streamed kernel only.)
+// geometry fits in LDS, else the split-work kernel; the adjoint's apply-A
+// launches take the split-work kernel (the resident kernel has no apply-A
+// mode, so an explicit RESIDENT or STREAMED choice runs them streamed).
 int kernel_path(wadg_ctx c, bool fp32, int mode) {
   const bool fits = wadg::resident_supported(c->N, c->nq1, fp32);
   if (mode == wadg::kApplyA)   // no resident apply-A mode

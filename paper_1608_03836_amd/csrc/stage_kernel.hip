@@ -13,8 +13,10 @@
 //
 // This variant reads the geometry of its element group from global memory
 // (L2-resident, shared by all slices) for every work item.  It serves every
-// (N, nq) the library supports; where the group's geometry fits in LDS, the
-// resident-geometry kernel is used instead (resident_kernel.hip).
+// (N, nq) the library supports.  The split-work kernel (split_kernel.hip),
+// which computes the same item over four waves, is the default; this one
+// remains selectable, and the persistent batch kernel below uses its
+// per-wave code.
 //
 // The group's input tile (3 (N+1)^2 x 64 values) is first copied into LDS
 // with 16-byte coalesced loads; the waves then re-read their own nodal

@@ -88,7 +88,7 @@ struct StageParams {
 //   kStage   LSRK stage: res_out <- A res + dt M^-1 b; Qout <- Qin + B res_out
 //   kRhs     Qout <- M^-1 b
 //   kApplyA  adjoint stage part: Qout <- res + dt D b, D = diag(1, -1, -1)
-//            (no mass inverse; streamed kernel only)
+//            (no mass inverse; streamed and split kernels)
 enum StageMode { kStage = 0, kRhs = 1, kApplyA = 2 };
 
 // Launch one stage (rhs == false: LSRK stage update; rhs == true: write
