@@ -79,6 +79,42 @@ def test_rhs_matches_oracle(W, N, dq, K1D, warp, rot, c2, tau):
     _assert_close(sol.download(dQ, S), want)
 
 
+@pytest.mark.parametrize("N", [1, 3, 4])
+def test_affine_sweep_equals_exact_dg(W, N):
+    """Affine elements (eps = 0) and constant c^2: J and c^2/J are constant
+    per element, so the weight-adjusted inverse is the exact inverse of the
+    weighted mass matrix (Section 4) and the GPU's WADG sweep must equal the
+    oracle's exact-DG sweep (dense solves of the weighted mass matrices), not only its WADG
+    sweep."""
+    _print_case(test="affine-dg", N=N)
+    mesh = periodic_quad_mesh(6, N, eps=0.0, rotate_seed=N)
+    c2f = c2_constant(1.3)
+    S, dt, n = 2, 0.2 / (6 * (N + 1) ** 2), 3
+    Q0 = _random_states(mesh, S, seed=40 + N)
+    want = WADGOracle(mesh, c2=c2f).integrate(Q0, dt, n, mass="dg")
+    sol = W.Solver(mesh, c2=c2f)
+    Q = sol.upload(Q0)
+    sol.integrate(Q, S, dt, n)
+    _assert_close(sol.download(Q, S), want)
+
+
+@pytest.mark.parametrize("N", [2, 3])
+def test_collocated_quadrature_sweep_equals_quadrature_dg(W, N):
+    """Curved elements, varying c^2, and the (N+1)-point Gauss rule: then
+    P_q = V_q^{-1} and the weight-adjusted inverse equals the inverse of the
+    quadrature-weighted mass matrix, so the GPU's WADG sweep must equal the
+    oracle's DG sweep with that rule."""
+    _print_case(test="collocated-dg", N=N)
+    mesh = periodic_quad_mesh(5, N, eps=0.05, warp="skew", rotate_seed=N)
+    S, dt, n = 2, 0.2 / (5 * (N + 1) ** 2), 3
+    Q0 = _random_states(mesh, S, seed=50 + N)
+    want = WADGOracle(mesh, nq1=N + 1, c2=c2_layered).integrate(Q0, dt, n, mass="dg")
+    sol = W.Solver(mesh, nq1=N + 1, c2=c2_layered)
+    Q = sol.upload(Q0)
+    sol.integrate(Q, S, dt, n)
+    _assert_close(sol.download(Q, S), want)
+
+
 def test_integrate_small_workload(W):
     """wadg4: 16 slices, one step each, start states = exact solution at t_s."""
     _print_case(test="integrate", workload="wadg4")
