@@ -75,6 +75,29 @@ def test_adjoint_matches_oracle(W):
     assert abs(dscale / prob.gamma - dgamma) <= 1e-10 * abs(dgamma)
 
 
+@pytest.mark.parametrize("N", [1, 2, 4])
+def test_adjoint_other_degrees_match_oracle(W, N):
+    """The adjoint sweep of other degrees (the adjoint mass kernel and the
+    apply-A launches of degree N) against the oracle's terminal-objective
+    gradient, on 4 x 4 elements."""
+    _print_case(test="adjoint-degrees", N=N)
+    prob = make_sensitivity_problem("adj4", N=N)
+    sol = _solver(W, prob)
+    y0 = sol.upload(prob.y0[None])
+    chk = sol.forward_checkpoints(y0, prob.S, prob.dt, prob.nsteps)
+    states = sol.download(chk, prob.S + 1)
+    seed = _seed(sol, states[-1], prob.p_target)
+    grad, dscale = sol.adjoint(chk, seed, prob.S, prob.dt, prob.nsteps)
+    g_gpu = sol.download(grad, 1)[0]
+    obj = TerminalObjective(prob.mesh, c0=prob.c0)
+    J, g_orc, dgamma = obj.gradient(prob.y0, prob.p_target, prob.gamma, prob.dt,
+                                    prob.S * prob.nsteps)
+    rel = np.linalg.norm(g_gpu - g_orc) / np.linalg.norm(g_orc)
+    print(f"adj4 N={N}: |grad - oracle|/|oracle| = {rel:.3e}", flush=True)
+    assert rel <= 1e-10
+    assert abs(dscale / prob.gamma - dgamma) <= 1e-10 * abs(dgamma)
+
+
 def test_autograd_function_matches_finite_differences(W):
     import torch
     from paper_1608_03836_amd.autograd import sweep, pressure_mask

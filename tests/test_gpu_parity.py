@@ -284,6 +284,25 @@ def test_fp32_bulk_small(W):
     assert err > 1e-12          # it really ran in single precision
 
 
+@pytest.mark.parametrize("N,dq", [(1, 1), (2, 2), (4, 1), (4, 3)])
+def test_fp32_bulk_other_degrees(W, N, dq):
+    """FP32-bulk sweeps of other degrees and quadratures (curved elements,
+    varying c^2, ragged last group) against the FP64 oracle: relative error
+    per slice <= 1e-6."""
+    _print_case(test="fp32-bulk-degrees", N=N, nq1=N + dq)
+    mesh = periodic_quad_mesh(9, N, eps=0.05, warp="skew", rotate_seed=N)
+    S, dt, n = 3, 0.2 / (9 * (N + 1) ** 2), 3
+    Q0 = _random_states(mesh, S, seed=60 + N)
+    want = WADGOracle(mesh, nq1=N + dq, c2=c2_layered).integrate(Q0, dt, n)
+    sol = W.Solver(mesh, nq1=N + dq, c2=c2_layered)
+    Q = sol.upload(Q0)
+    sol.integrate_fp32(Q, S, dt, n)
+    err = _fp32_error(sol.download(Q, S), want)
+    print(f"FP32-bulk N={N} nq1={N + dq} relative error vs FP64 oracle: {err:.3e}")
+    assert err <= TOL_FP32
+    assert err > 1e-12
+
+
 def test_fp32_bulk_full_size_wadg128(W):
     """wadg128 (heterogeneous c^2, 256 slices x 10 steps) in FP32 bulk;
     slices 0, 17, 255 against the FP64 oracle."""
