@@ -540,12 +540,13 @@ int wadg_parareal(wadg_ctx ctx, const double* y0, double* U, void* work, int32_t
 }
 
 namespace {
-// Adjoint workspace: nsteps step-start states, 5 stage residuals, two
-// ping-pong states, ybar, rbar, z (one slice each), then the per-workgroup
-// sensitivity partials.
+// Adjoint workspace: the 5 stage residuals of every step of one slice, two
+// alternating stage states, ybar, rbar, z (one slice each), then the
+// per-workgroup sensitivity partials.  (wadg_forward_checkpoints uses the
+// first five slices of it.)
 size_t adjoint_bytes(wadg_ctx ctx, int32_t nsteps) {
   const size_t n1 = ctx->slice_doubles();
-  return ((size_t)nsteps + 10) * n1 * sizeof(double) + (size_t)ctx->groups() * sizeof(double);
+  return (5 * (size_t)nsteps + 5) * n1 * sizeof(double) + (size_t)ctx->groups() * sizeof(double);
 }
 
 // One LSRK step of one slice from `in` to `out` (distinct), through t0, t1.
@@ -618,11 +619,9 @@ int wadg_adjoint(wadg_ctx ctx, const double* chk, const double* seed, double* gr
   if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select the context's device");
   hipStream_t hs = static_cast<hipStream_t>(stream);
 
-  double* X = static_cast<double*>(work);       // step-start states of a slice
-  double* R = X + (size_t)nsteps * n1;           // stage residuals r_1..r_5
-  double* t0 = R + 5 * n1;
-  double* t1 = t0 + n1;
-  double* yb = t1 + n1;
+  double* R = static_cast<double*>(work);       // residuals r_{m,i} at R + (5 m + i) n1
+  double* T[2] = {R + 5 * (size_t)nsteps * n1, R + (5 * (size_t)nsteps + 1) * n1};
+  double* yb = T[1] + n1;
   double* rb = yb + n1;
   double* z = rb + n1;
   double* part = z + n1;
@@ -633,31 +632,31 @@ int wadg_adjoint(wadg_ctx ctx, const double* chk, const double* seed, double* gr
   wadg::StageParams p = base_params(ctx, 1);
   p.dt = dt;
   for (int s = S - 1; s >= 0; --s) {
-    // step-start states of slice s, recomputed from its checkpoint
-    WADG_HIP(hipMemcpyAsync(X, chk + s * n1, sb, hipMemcpyDeviceToDevice, hs));
-    for (int m = 1; m < nsteps; ++m) {
-      int st = one_step(ctx, X + (m - 1) * n1, X + m * n1, t0, t1, R, dt, stream);
-      if (st) return st;
-    }
-    for (int m = nsteps - 1; m >= 0; --m) {
-      // the five stages of step m again, each residual kept
-      const double* cur = X + m * n1;
+    // slice s recomputed once from its checkpoint, every stage residual
+    // kept; stage j = 5 m + i writes T[j % 2] and reads what stage j - 1
+    // wrote (the checkpoint for j = 0), never its own output buffer
+    const double* cur = chk + s * n1;
+    for (int m = 0; m < nsteps; ++m) {
       for (int i = 0; i < 5; ++i) {
+        double* out = T[(5 * m + i) % 2];
         p.Qin = cur;
-        p.Qout = i % 2 == 0 ? t0 : t1;
-        p.res = i == 0 ? R : R + (i - 1) * n1;
-        p.res_out = R + i * n1;
+        p.Qout = out;
+        p.res = R + (5 * (size_t)m + (i == 0 ? 0 : i - 1)) * n1;
+        p.res_out = R + (5 * (size_t)m + i) * n1;
         p.rkA = kRkA[i];
         p.rkB = kRkB[i];
         int e = launch_stage(ctx, wadg::kStage, false, p, stream);
         if (e) return hip_fail((hipError_t)e, "stage kernel launch");
-        cur = static_cast<const double*>(p.Qout);
+        cur = out;
       }
-      p.res_out = nullptr;
+    }
+    p.res_out = nullptr;
+    for (int m = nsteps - 1; m >= 0; --m) {
+      const double* Rm = R + 5 * (size_t)m * n1;
       // reverse stages: rbar += B_i ybar; ybar += dt L^T rbar; rbar *= A_i
       for (int i = 4; i >= 0; --i) {
-        int e = wadg::launch_adjoint_mass(ctx->N, ctx->nq1, p, rb, yb, z, R + i * n1,
-                                          i > 0 ? R + (i - 1) * n1 : nullptr,
+        int e = wadg::launch_adjoint_mass(ctx->N, ctx->nq1, p, rb, yb, z, Rm + i * n1,
+                                          i > 0 ? Rm + (i - 1) * n1 : nullptr,
                                           i == 4 ? 0.0 : kRkA[i + 1], kRkB[i], kRkA[i], part,
                                           stream);
         if (e) return hip_fail((hipError_t)e, "adjoint mass kernel launch");
@@ -1010,15 +1009,19 @@ int wadg_batch_tune(wadg_batch b, const double* Q, double* work, const double* d
   int st = batch_upload_dt(b, dt);
   if (st) return st;
   hipStream_t hs = static_cast<hipStream_t>(stream);
-  hipEvent_t e0, e1;
-  WADG_HIP(hipEventCreate(&e0));
-  WADG_HIP(hipEventCreate(&e1));
-  // candidates: persistent grids of 1, 2, 4, 8 workgroups per CU or one
-  // workgroup per item, in both item orders; each timed on a stage with a
-  // residual read (Q is only read, the workspace is scratch)
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hip_fail(hipErrorUnknown, "hipEventCreate");
+  }
+  // candidates: persistent grids of 1, 2, 4, 8 two-wave workgroups per CU
+  // (streamed kernel) or one four-wave workgroup per item (split kernel), in
+  // both item orders; each timed on a stage with a residual read (Q is only
+  // read, the workspace is scratch)
   const int mults[] = {1, 2, 4, 8, 0};
   double best = 1e300;
-  int bm = b->grid_mult, bo = b->order;
+  const int m0 = b->grid_mult, o0 = b->order;
+  int bm = m0, bo = o0;
   for (int o = 0; o < 2 && !st; ++o) {
     for (int m : mults) {
       if ((st = wadg_batch_set_schedule(b, m, o))) break;
@@ -1042,7 +1045,10 @@ int wadg_batch_tune(wadg_batch b, const double* Q, double* work, const double* d
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (st) return st;
+  if (st) {
+    (void)wadg_batch_set_schedule(b, m0, o0);   // leave the schedule as it was
+    return st;
+  }
   if ((st = wadg_batch_set_schedule(b, bm, bo))) return st;
   *wg_per_cu = bm;
   *order = bo;
