@@ -145,6 +145,7 @@ int check_slices(wadg_ctx c, int32_t S) {
 // mode, so an explicit RESIDENT or STREAMED choice runs them streamed).
 int kernel_path(wadg_ctx c, bool fp32, int mode) {
   const bool fits = wadg::resident_supported(c->N, c->nq1, fp32);
+  if (mode == wadg::kApplyAMass) return WADG_KERNEL_SPLIT;   // split kernel only
   if (mode == wadg::kApplyA)   // no resident apply-A mode
     return c->kernel == WADG_KERNEL_AUTO || c->kernel == WADG_KERNEL_SPLIT ? WADG_KERNEL_SPLIT
                                                                            : WADG_KERNEL_STREAMED;
@@ -541,12 +542,12 @@ int wadg_parareal(wadg_ctx ctx, const double* y0, double* U, void* work, int32_t
 
 namespace {
 // Adjoint workspace: the 5 stage residuals of every step of one slice, two
-// alternating stage states, ybar, rbar, z (one slice each), then the
-// per-workgroup sensitivity partials.  (wadg_forward_checkpoints uses the
-// first five slices of it.)
+// alternating stage states, ybar, rbar, two alternating z (one slice each),
+// then the per-workgroup sensitivity partials.  (wadg_forward_checkpoints
+// uses the first five slices of it.)
 size_t adjoint_bytes(wadg_ctx ctx, int32_t nsteps) {
   const size_t n1 = ctx->slice_doubles();
-  return (5 * (size_t)nsteps + 5) * n1 * sizeof(double) + (size_t)ctx->groups() * sizeof(double);
+  return (5 * (size_t)nsteps + 6) * n1 * sizeof(double) + (size_t)ctx->groups() * sizeof(double);
 }
 
 // One LSRK step of one slice from `in` to `out` (distinct), through t0, t1.
@@ -623,8 +624,15 @@ int wadg_adjoint(wadg_ctx ctx, const double* chk, const double* seed, double* gr
   double* T[2] = {R + 5 * (size_t)nsteps * n1, R + (5 * (size_t)nsteps + 1) * n1};
   double* yb = T[1] + n1;
   double* rb = yb + n1;
-  double* z = rb + n1;
-  double* part = z + n1;
+  double* zc = rb + n1;    // z read by the next apply-A launch
+  double* zn = zc + n1;    // z written by a fused apply-A + mass launch
+  double* part = zn + n1;
+  // With the split kernel, the mass step of reverse stage j-1 runs at the
+  // end of the apply-A launch of stage j (it needs only the item's own new
+  // ybar and rbar): one launch per stage instead of two, except at the
+  // first stage of each slice (its residuals are recomputed just before)
+  // and the last (no next stage in the slice).
+  const bool fused = kernel_path(ctx, false, wadg::kApplyA) == WADG_KERNEL_SPLIT;
   const int G = ctx->groups();
   WADG_HIP(hipMemsetAsync(part, 0, (size_t)G * sizeof(double), hs));
   WADG_HIP(hipMemcpyAsync(yb, seed, sb, hipMemcpyDeviceToDevice, hs));
@@ -655,16 +663,35 @@ int wadg_adjoint(wadg_ctx ctx, const double* chk, const double* seed, double* gr
       const double* Rm = R + 5 * (size_t)m * n1;
       // reverse stages: rbar += B_i ybar; ybar += dt L^T rbar; rbar *= A_i
       for (int i = 4; i >= 0; --i) {
-        int e = wadg::launch_adjoint_mass(ctx->N, ctx->nq1, p, rb, yb, z, Rm + i * n1,
-                                          i > 0 ? Rm + (i - 1) * n1 : nullptr,
-                                          i == 4 ? 0.0 : kRkA[i + 1], kRkB[i], kRkA[i], part,
-                                          stream);
-        if (e) return hip_fail((hipError_t)e, "adjoint mass kernel launch");
+        int e = 0;
+        if (!fused || (m == nsteps - 1 && i == 4)) {
+          e = wadg::launch_adjoint_mass(ctx->N, ctx->nq1, p, rb, yb, zc, Rm + i * n1,
+                                        i > 0 ? Rm + (i - 1) * n1 : nullptr,
+                                        i == 4 ? 0.0 : kRkA[i + 1], kRkB[i], kRkA[i], part,
+                                        stream);
+          if (e) return hip_fail((hipError_t)e, "adjoint mass kernel launch");
+        }
         wadg::StageParams q = p;
-        q.Qin = z;
+        q.Qin = zc;
         q.res = yb;
         q.Qout = yb;
-        e = launch_stage(ctx, wadg::kApplyA, false, q, stream);
+        if (fused && (m > 0 || i > 0)) {
+          // the mass step of the next reverse stage (m2, i2) of this slice
+          const int m2 = i > 0 ? m : m - 1, i2 = i > 0 ? i - 1 : 4;
+          const double* R2 = R + 5 * (size_t)m2 * n1;
+          q.adj.rbar = rb;
+          q.adj.z = zn;
+          q.adj.r = R2 + i2 * n1;
+          q.adj.r_prev = i2 > 0 ? R2 + (i2 - 1) * n1 : nullptr;
+          q.adj.part = part;
+          q.adj.a_next = i2 == 4 ? 0.0 : kRkA[i2 + 1];
+          q.adj.b = kRkB[i2];
+          q.adj.a = kRkA[i2];
+          e = launch_stage(ctx, wadg::kApplyAMass, false, q, stream);
+          std::swap(zc, zn);
+        } else {
+          e = launch_stage(ctx, wadg::kApplyA, false, q, stream);
+        }
         if (e) return hip_fail((hipError_t)e, "stage kernel launch (apply A)");
       }
     }

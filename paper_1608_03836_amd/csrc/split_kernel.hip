@@ -53,9 +53,12 @@ struct Split {
       (unsigned)(NM * 4 * NQ > 3 * NP ? NM * 4 * NQ : 3 * NP) * kWave;
 };
 
-// Global geometry and state resources of one work item.
+// Global geometry and state resources of one work item; the last five
+// only in the fused apply-A + mass mode (rbar read and written, z, r_i,
+// r_{i-1}).
 struct SplitBufs {
   rsrc_t qin, qout, res, resw, qslice, vol, face, nbr;
+  rsrc_t rbr, rbw, zo, ri, rp;
 };
 
 template <typename R, int NQ>
@@ -191,14 +194,63 @@ __device__ __forceinline__ void add_face_terms(const R* xf, int c, int lane,
     for (int m = 0; m < NP1; ++m) b[fnode<N>(f, m)] += xf[((f * 3 + c) * NP1 + m) * kWave + lane];
 }
 
+// Fused apply-A + mass mode, field c: the apply-A update of ybar (as
+// finish_field), then the next reverse stage's mass step on the new ybar,
+// in the adjoint mass kernel's order of operations.  w: the field's mass
+// weights (c2_scale c^2/J for p, 1/J for u, v).  Returns the pressure
+// sensitivity partial of this lane (0 for u, v).
+template <int N, int NQ>
+__device__ __forceinline__ double apply_a_mass_field(const StageScalars<double>& k,
+                                                     const SplitBufs& B, const AdjMassParams& am,
+                                                     int c, unsigned kb, bool active,
+                                                     const double (&resv)[(N + 1) * (N + 1)],
+                                                     const double (&b)[(N + 1) * (N + 1)],
+                                                     const double (&w)[NQ * NQ]) {
+  constexpr int NP = (N + 1) * (N + 1);
+  constexpr unsigned KP = kWave * sizeof(double);
+  const double sdt = c == 0 ? k.dt : -k.dt;
+  double y[NP], r[NP], dq[NP];
+#pragma unroll
+  for (int n = 0; n < NP; ++n) y[n] = mad(sdt, b[n], resv[n]);
+  if (active) {
+#pragma unroll
+    for (int n = 0; n < NP; ++n) st(B.qout, kb, (c * NP + n) * KP, y[n]);
+  }
+#pragma unroll
+  for (int n = 0; n < NP; ++n)
+    r[n] = mad(am.a_next, ldr<double>(B.rbr, kb, (c * NP + n) * KP), am.b * y[n]);
+  double dot = 0.0;
+  if (c == 0) {
+#pragma unroll
+    for (int n = 0; n < NP; ++n)
+      dot = mad(r[n], mad(-am.a, ldr<double>(B.rp, kb, n * KP), ldr<double>(B.ri, kb, n * KP)),
+                dot);
+  }
+  wadg_inverse<double, N, NQ>(r, w, dq);
+  if (active) {
+    const double sg = c == 0 ? 1.0 : -1.0;
+#pragma unroll
+    for (int n = 0; n < NP; ++n) {
+      const unsigned so = (c * NP + n) * KP;
+      st(B.rbw, kb, so, r[n]);
+      st(B.zo, kb, so, sg * dq[n]);
+    }
+  }
+  return dot;
+}
+
 }  // namespace
 
 // One work item -- a 64-element group of one slice -- over the four waves of
 // the workgroup.  B: the item's resources; k: the stage's scalars; active:
-// this lane holds an element; tq, xf, xm: the workgroup's LDS (Split<>).
+// this lane holds an element; tq, xf, xm: the workgroup's LDS (Split<>);
+// am, part: the fused apply-A + mass mode's scalars and this item's slot in
+// am.part.
 template <typename R, int N, int NQ, int MODE>
 __device__ __forceinline__ void split_item(const SplitBufs& B, const StageScalars<R>& k,
-                                           bool active, R* tq, R* xf, R* xm) {
+                                           bool active, R* tq, R* xf, R* xm,
+                                           const AdjMassParams& am = AdjMassParams{},
+                                           int part = 0) {
   using L = Split<R, N, NQ>;
   constexpr int NP = L::NP, NQ2 = L::NQ2;
   constexpr unsigned tile = L::tile;
@@ -208,9 +260,10 @@ __device__ __forceinline__ void split_item(const SplitBufs& B, const StageScalar
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & (kWave - 1);
   const unsigned kb = (unsigned)lane * sizeof(R);
-  // Apply-A mode (the adjoint's outer factor) takes the load vector itself:
-  // no mass inverse and no mass weights.
-  constexpr bool kInv = MODE != kApplyA;
+  // Apply-A modes (the adjoint's outer factor) take the load vector itself:
+  // no mass inverse; the fused apply-A + mass mode still needs the weights.
+  constexpr bool kInv = MODE != kApplyA && MODE != kApplyAMass;
+  constexpr bool kW = MODE != kApplyA;
   auto inverse = [](const R(&b)[NP], const R(&w)[NQ2], R(&dq)[NP]) {
     if constexpr (kInv) {
       wadg_inverse<R, N, NQ>(b, w, dq);
@@ -259,9 +312,9 @@ __device__ __forceinline__ void split_item(const SplitBufs& B, const StageScalar
         [] {});
     R b0[NP], b1[NP], w[NQ2];
     if (wave == 0)
-      split_volume<R, N, NQ, true, kInv>(B, kb, 4 * NQ2, xm, lane, P, U, V, ga, gb, b0, b1, w);
+      split_volume<R, N, NQ, true, kW>(B, kb, 4 * NQ2, xm, lane, P, U, V, ga, gb, b0, b1, w);
     else
-      split_volume<R, N, NQ, false, kInv>(B, kb, 5 * NQ2, xm, lane, P, U, V, ga, gb, b0, b1, w);
+      split_volume<R, N, NQ, false, kW>(B, kb, 5 * NQ2, xm, lane, P, U, V, ga, gb, b0, b1, w);
     __syncthreads();                                   // face terms ready
     R resv[NP], dq[NP];
     if (wave == 0) {
@@ -269,12 +322,20 @@ __device__ __forceinline__ void split_item(const SplitBufs& B, const StageScalar
       __syncthreads();                                 // b_v, residuals handed over
 #pragma unroll
       for (int n = 0; n < NP; ++n) resv[n] = xr[n * kWave + lane];
-      if constexpr (kInv) {
+      if constexpr (kW) {
 #pragma unroll
         for (int q = 0; q < NQ2; ++q) w[q] *= k.c2s;
       }
       inverse(b0, w, dq);
-      finish_field<R, NP, MODE>(k, B.qout, B.resw, P, 0, kb, active, resv, dq);
+      if constexpr (MODE == kApplyAMass) {
+        double dot = apply_a_mass_field<N, NQ>(k, B, am, 0, kb, active, resv, dq, w);
+        if (!active) dot = 0.0;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) dot += __shfl_xor(dot, off, 64);
+        if (lane == 0) am.part[part] += dot;
+      } else {
+        finish_field<R, NP, MODE>(k, B.qout, B.resw, P, 0, kb, active, resv, dq);
+      }
     } else {
       add_face_terms<R, N>(xf, 1, lane, b0);
       add_face_terms<R, N>(xf, 2, lane, b1);
@@ -284,7 +345,10 @@ __device__ __forceinline__ void split_item(const SplitBufs& B, const StageScalar
 #pragma unroll
       for (int n = 0; n < NP; ++n) resv[n] = xr[(NP + n) * kWave + lane];
       inverse(b0, w, dq);
-      finish_field<R, NP, MODE>(k, B.qout, B.resw, P, 1, kb, active, resv, dq);
+      if constexpr (MODE == kApplyAMass)
+        (void)apply_a_mass_field<N, NQ>(k, B, am, 1, kb, active, resv, dq, w);
+      else
+        finish_field<R, NP, MODE>(k, B.qout, B.resw, P, 1, kb, active, resv, dq);
     }
   } else {
     if (wave == 2) {
@@ -300,7 +364,7 @@ __device__ __forceinline__ void split_item(const SplitBufs& B, const StageScalar
       split_faces<R, N, NQ, 1, 3>(k, B, kb, lane, P, U, V, xf);
     if (wave == 2) {
       R w[NQ2], resv[NP];
-      if constexpr (kInv) split_weights<R, NQ>(B, 5 * NQ2, kb, w);
+      if constexpr (kW) split_weights<R, NQ>(B, 5 * NQ2, kb, w);
       load_res<R, NP, MODE>(k, B.res, 2, kb, resv);
       __syncthreads();                                 // face terms ready
       __syncthreads();                                 // b_v handed over
@@ -308,7 +372,10 @@ __device__ __forceinline__ void split_item(const SplitBufs& B, const StageScalar
 #pragma unroll
       for (int n = 0; n < NP; ++n) bv[n] = xv[n * kWave + lane];
       inverse(bv, w, dq);
-      finish_field<R, NP, MODE>(k, B.qout, B.resw, P, 2, kb, active, resv, dq);
+      if constexpr (MODE == kApplyAMass)
+        (void)apply_a_mass_field<N, NQ>(k, B, am, 2, kb, active, resv, dq, w);
+      else
+        finish_field<R, NP, MODE>(k, B.qout, B.resw, P, 2, kb, active, resv, dq);
     } else {
       // the residuals of fields 0 and 1, requested for the volume waves
       // while they finish their volume terms
@@ -328,7 +395,8 @@ __device__ __forceinline__ void split_item(const SplitBufs& B, const StageScalar
 
 template <typename R, int N, int NQ, int MODE>
 __global__ __launch_bounds__(4 * kWave) void split_kernel(const StageParams p) {
-  static_assert(MODE != kApplyA || sizeof(R) == sizeof(double), "apply-A mode is FP64 only");
+  static_assert((MODE != kApplyA && MODE != kApplyAMass) || sizeof(R) == sizeof(double),
+                "apply-A modes are FP64 only");
   using L = Split<R, N, NQ>;
   constexpr int NQ2 = L::NQ2;
   constexpr unsigned tile = L::tile;
@@ -363,7 +431,18 @@ __global__ __launch_bounds__(4 * kWave) void split_kernel(const StageParams p) {
   B.face = make_rsrc(static_cast<const R*>(p.face) + (size_t)eg * 12 * NQ * kWave,
                      12u * NQ * KP);
   B.nbr = make_rsrc(p.nbr + (size_t)eg * 8 * kWave, 8u * kWave * 4u);
-  split_item<R, N, NQ, MODE>(B, stage_scalars<R>(p), eg * kWave + lane < p.K, tq, xf, xm);
+  if constexpr (MODE == kApplyAMass) {
+    const AdjMassParams& am = p.adj;
+    const unsigned tb = tile * sizeof(R);
+    B.rbr = make_rsrc(am.rbar + grp, am.a_next != 0.0 ? tb : 0u);
+    B.rbw = make_rsrc(am.rbar + grp, tb);
+    B.zo = make_rsrc(am.z + grp, tb);
+    B.ri = make_rsrc(am.r + grp, tb);
+    B.rp = make_rsrc(am.r_prev ? am.r_prev + grp : am.r + grp,
+                     (am.a != 0.0 && am.r_prev) ? tb : 0u);
+  }
+  split_item<R, N, NQ, MODE>(B, stage_scalars<R>(p), eg * kWave + lane < p.K, tq, xf, xm, p.adj,
+                             s * nEG + eg);
 }
 
 // Batched LSRK stage (FP64) over a work list of (problem, slice, element
@@ -427,6 +506,8 @@ int launch_nq(int mode, const StageParams& p, void* stream) {
       hipLaunchKernelGGL((split_kernel<R, N, NQ, kRhs>), grid, block, 0, st, p);
     else if (mode == kApplyA)
       hipLaunchKernelGGL((split_kernel<R, N, NQ, kApplyA>), grid, block, 0, st, p);
+    else if (mode == kApplyAMass)
+      hipLaunchKernelGGL((split_kernel<R, N, NQ, kApplyAMass>), grid, block, 0, st, p);
     else
       return (int)hipErrorInvalidValue;
   } else {

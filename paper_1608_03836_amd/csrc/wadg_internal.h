@@ -65,6 +65,19 @@ std::vector<T> tile_planes(const std::vector<T>& a, int planes, int K) {
 // Physical coordinates of the volume quadrature points, [K][nq*nq].
 void quadrature_points(const MeshIn& m, const RefOps& ops, double* xq, double* yq);
 
+// The adjoint mass step of the next reverse stage, fused into an apply-A
+// launch (mode kApplyAMass; split kernel, FP64).  With y the new ybar:
+//   rbar <- a_next rbar + b y;   z <- D Mtilde^{-1} rbar;
+//   part[group] += sum over pressure values of rbar (r - a r_prev).
+struct AdjMassParams {
+  double* rbar;           // one slice, read (unless a_next = 0) and written
+  double* z;              // one slice, written; not the launch's Qin
+  const double* r;        // stage residual r_i of the mass stage
+  const double* r_prev;   // r_{i-1}; NULL when a = 0
+  double* part;           // [groups] sensitivity partials
+  double a_next, b, a;
+};
+
 // Arrays are of the kernel's arithmetic type (double, or float for the
 // FP32-bulk propagator) except the int32 neighbour offsets.
 struct StageParams {
@@ -82,6 +95,7 @@ struct StageParams {
   double rkA, rkB, dt;
   double c2_scale;       // c^2 multiplier (pressure mass weights)
   int32_t reverse;       // nonzero: the work items in reverse order
+  AdjMassParams adj;     // kApplyAMass only
 };
 
 // What a stage-kernel launch computes from the load vector b = A Qin:
@@ -89,7 +103,9 @@ struct StageParams {
 //   kRhs     Qout <- M^-1 b
 //   kApplyA  adjoint stage part: Qout <- res + dt D b, D = diag(1, -1, -1)
 //            (no mass inverse; streamed and split kernels)
-enum StageMode { kStage = 0, kRhs = 1, kApplyA = 2 };
+//   kApplyAMass  kApplyA, then the next reverse stage's mass step on the
+//            new Qout (AdjMassParams; split kernel, FP64)
+enum StageMode { kStage = 0, kRhs = 1, kApplyA = 2, kApplyAMass = 3 };
 
 // Launch one stage (rhs == false: LSRK stage update; rhs == true: write
 // dQ/dt to Qout).  Returns a hipError_t as int.
