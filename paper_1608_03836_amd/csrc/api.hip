@@ -98,6 +98,10 @@ struct wadg_ctx_s {
   double* d_partials = nullptr;  // norms scratch, grown on demand
   double* d_out = nullptr;
   int32_t norms_cap = 0;
+  // adjoint: a second stream (default priority) for the forward recompute
+  // that overlaps the reverse sweep, and the events that order the two
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_in = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_rev[2] = {nullptr, nullptr};
   int groups() const { return (K + wadg::kWave - 1) / wadg::kWave; }
   size_t tile() const { return (size_t)3 * (N + 1) * (N + 1) * wadg::kWave; }
   size_t slice_doubles() const { return (size_t)groups() * tile(); }
@@ -115,6 +119,9 @@ void free_ctx(wadg_ctx c) {
   if (c->d_nbr) (void)hipFree(c->d_nbr);
   if (c->d_partials) (void)hipFree(c->d_partials);
   if (c->d_out) (void)hipFree(c->d_out);
+  for (hipEvent_t e : {c->ev_in, c->ev_rec[0], c->ev_rec[1], c->ev_rev[0], c->ev_rev[1]})
+    if (e) (void)hipEventDestroy(e);
+  if (c->aux) (void)hipStreamDestroy(c->aux);
   delete c;
 }
 
@@ -541,13 +548,40 @@ int wadg_parareal(wadg_ctx ctx, const double* y0, double* U, void* work, int32_t
 }
 
 namespace {
-// Adjoint workspace: the 5 stage residuals of every step of one slice, two
-// alternating stage states, ybar, rbar, two alternating z (one slice each),
-// then the per-workgroup sensitivity partials.  (wadg_forward_checkpoints
-// uses the first five slices of it.)
+// Adjoint workspace: two sets of the 5 stage residuals of every step of one
+// slice (one being recomputed while the other is read), two alternating
+// stage states, ybar, rbar, two alternating z (one slice each), then the
+// per-workgroup sensitivity partials.  (wadg_forward_checkpoints uses the
+// first five slices of it.)
 size_t adjoint_bytes(wadg_ctx ctx, int32_t nsteps) {
   const size_t n1 = ctx->slice_doubles();
-  return (5 * (size_t)nsteps + 6) * n1 * sizeof(double) + (size_t)ctx->groups() * sizeof(double);
+  return (10 * (size_t)nsteps + 6) * n1 * sizeof(double) + (size_t)ctx->groups() * sizeof(double);
+}
+
+// One slice recomputed from its start state chk_s, keeping every stage
+// residual r_{m,i} at R + (5 m + i) n1; stage j = 5 m + i writes T[j % 2]
+// and reads what stage j - 1 wrote (chk_s for j = 0), never its own output.
+int adjoint_recompute(wadg_ctx ctx, const double* chk_s, double* R, double* const (&T)[2],
+                      double dt, int32_t nsteps, void* stream) {
+  const size_t n1 = ctx->slice_doubles();
+  wadg::StageParams p = base_params(ctx, 1);
+  p.dt = dt;
+  const double* cur = chk_s;
+  for (int m = 0; m < nsteps; ++m) {
+    for (int i = 0; i < 5; ++i) {
+      double* out = T[(5 * m + i) % 2];
+      p.Qin = cur;
+      p.Qout = out;
+      p.res = R + (5 * (size_t)m + (i == 0 ? 0 : i - 1)) * n1;
+      p.res_out = R + (5 * (size_t)m + i) * n1;
+      p.rkA = kRkA[i];
+      p.rkB = kRkB[i];
+      int e = launch_stage(ctx, wadg::kStage, false, p, stream);
+      if (e) return hip_fail((hipError_t)e, "stage kernel launch");
+      cur = out;
+    }
+  }
+  return WADG_OK;
 }
 
 // One LSRK step of one slice from `in` to `out` (distinct), through t0, t1.
@@ -620,8 +654,8 @@ int wadg_adjoint(wadg_ctx ctx, const double* chk, const double* seed, double* gr
   if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select the context's device");
   hipStream_t hs = static_cast<hipStream_t>(stream);
 
-  double* R = static_cast<double*>(work);       // residuals r_{m,i} at R + (5 m + i) n1
-  double* T[2] = {R + 5 * (size_t)nsteps * n1, R + (5 * (size_t)nsteps + 1) * n1};
+  double* R = static_cast<double*>(work);       // two residual sets of 5 nsteps slices
+  double* const T[2] = {R + 10 * (size_t)nsteps * n1, R + (10 * (size_t)nsteps + 1) * n1};
   double* yb = T[1] + n1;
   double* rb = yb + n1;
   double* zc = rb + n1;    // z read by the next apply-A launch
@@ -639,28 +673,36 @@ int wadg_adjoint(wadg_ctx ctx, const double* chk, const double* seed, double* gr
 
   wadg::StageParams p = base_params(ctx, 1);
   p.dt = dt;
+  // The forward recompute of slice s-1 (on the context's second stream)
+  // runs while the reverse sweep of slice s (on `stream`) reads the other
+  // residual set: ev_rec[b] = residual set b is ready, ev_rev[b] = the
+  // reverse sweep that read set b is done.
+  if (!ctx->aux) {
+    WADG_HIP(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+    for (hipEvent_t* e : {&ctx->ev_in, &ctx->ev_rec[0], &ctx->ev_rec[1], &ctx->ev_rev[0],
+                          &ctx->ev_rev[1]})
+      WADG_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+  }
+  hipStream_t aux = ctx->aux;
+  WADG_HIP(hipEventRecord(ctx->ev_in, hs));          // chk and seed are written
+  WADG_HIP(hipStreamWaitEvent(aux, ctx->ev_in, 0));
+  double* const Rs[2] = {R, R + 5 * (size_t)nsteps * n1};
+  auto recompute = [&](int s) -> int {
+    const int b = s % 2;
+    if (s + 2 <= S - 1) WADG_HIP(hipStreamWaitEvent(aux, ctx->ev_rev[b], 0));
+    int st = adjoint_recompute(ctx, chk + s * n1, Rs[b], T, dt, nsteps, aux);
+    if (st) return st;
+    WADG_HIP(hipEventRecord(ctx->ev_rec[b], aux));
+    return WADG_OK;
+  };
+  int st = recompute(S - 1);
+  if (st) return st;
   for (int s = S - 1; s >= 0; --s) {
-    // slice s recomputed once from its checkpoint, every stage residual
-    // kept; stage j = 5 m + i writes T[j % 2] and reads what stage j - 1
-    // wrote (the checkpoint for j = 0), never its own output buffer
-    const double* cur = chk + s * n1;
-    for (int m = 0; m < nsteps; ++m) {
-      for (int i = 0; i < 5; ++i) {
-        double* out = T[(5 * m + i) % 2];
-        p.Qin = cur;
-        p.Qout = out;
-        p.res = R + (5 * (size_t)m + (i == 0 ? 0 : i - 1)) * n1;
-        p.res_out = R + (5 * (size_t)m + i) * n1;
-        p.rkA = kRkA[i];
-        p.rkB = kRkB[i];
-        int e = launch_stage(ctx, wadg::kStage, false, p, stream);
-        if (e) return hip_fail((hipError_t)e, "stage kernel launch");
-        cur = out;
-      }
-    }
-    p.res_out = nullptr;
+    if (s >= 1 && (st = recompute(s - 1))) return st;
+    const double* Rs_ = Rs[s % 2];
+    WADG_HIP(hipStreamWaitEvent(hs, ctx->ev_rec[s % 2], 0));
     for (int m = nsteps - 1; m >= 0; --m) {
-      const double* Rm = R + 5 * (size_t)m * n1;
+      const double* Rm = Rs_ + 5 * (size_t)m * n1;
       // reverse stages: rbar += B_i ybar; ybar += dt L^T rbar; rbar *= A_i
       for (int i = 4; i >= 0; --i) {
         int e = 0;
@@ -678,7 +720,7 @@ int wadg_adjoint(wadg_ctx ctx, const double* chk, const double* seed, double* gr
         if (fused && (m > 0 || i > 0)) {
           // the mass step of the next reverse stage (m2, i2) of this slice
           const int m2 = i > 0 ? m : m - 1, i2 = i > 0 ? i - 1 : 4;
-          const double* R2 = R + 5 * (size_t)m2 * n1;
+          const double* R2 = Rs_ + 5 * (size_t)m2 * n1;
           q.adj.rbar = rb;
           q.adj.z = zn;
           q.adj.r = R2 + i2 * n1;
@@ -695,6 +737,7 @@ int wadg_adjoint(wadg_ctx ctx, const double* chk, const double* seed, double* gr
         if (e) return hip_fail((hipError_t)e, "stage kernel launch (apply A)");
       }
     }
+    WADG_HIP(hipEventRecord(ctx->ev_rev[s % 2], hs));
   }
   if (grad != yb) WADG_HIP(hipMemcpyAsync(grad, yb, sb, hipMemcpyDeviceToDevice, hs));
   std::vector<double> h(G);

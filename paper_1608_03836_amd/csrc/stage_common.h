@@ -394,7 +394,7 @@ __device__ __forceinline__ void load_res(const StageScalars<R>& k, rsrc_t res, i
                                          unsigned kb, R (&resv)[NP]) {
   constexpr unsigned KP = kWave * sizeof(R);
   if constexpr (MODE != kRhs) {
-    if (MODE == kApplyA || k.A != R(0)) {
+    if (MODE == kApplyA || MODE == kApplyAMass || k.A != R(0)) {
 #pragma unroll
       for (int n = 0; n < NP; ++n) resv[n] = ldr<R>(res, kb, (c * NP + n) * KP);
       return;
