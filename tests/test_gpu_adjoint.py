@@ -204,3 +204,28 @@ def test_adjoint_kernel_variants_bitwise(W):
     assert np.all(np.isfinite(outs[0][1]))
     assert np.array_equal(outs[0][1], outs[1][1])
     assert outs[0][2] == outs[1][2]
+
+
+def test_adjoint_on_a_caller_stream_is_bitwise_the_same(W):
+    """The reverse sweep orders its recompute stream against the caller's
+    stream with events; run on a non-default torch stream (the binding
+    passes torch's current stream), the gradient and the c^2 sensitivity
+    equal the default-stream run bit for bit."""
+    import contextlib
+    import torch
+    _print_case(test="adjoint-stream", workload="adj4-K1D8")
+    prob = make_sensitivity_problem("adj4", K1D=8, S=5)
+    outs = []
+    for side in (None, torch.cuda.Stream()):
+        sol = _solver(W, prob)
+        with (torch.cuda.stream(side) if side is not None else contextlib.nullcontext()):
+            y0 = sol.upload(prob.y0[None])
+            chk = sol.forward_checkpoints(y0, prob.S, prob.dt, prob.nsteps)
+            seed = (2.0 * chk[prob.S * sol.slice_doubles:]).contiguous()
+            grad, dscale = sol.adjoint(chk, seed, prob.S, prob.dt, prob.nsteps)
+            g = sol.download(grad, 1)[0]
+        torch.cuda.synchronize()
+        outs.append((g, dscale))
+    assert np.all(np.isfinite(outs[0][0]))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert outs[0][1] == outs[1][1]
