@@ -421,7 +421,7 @@ def tile_state(Qn):
 
 
 def untile_state(Qt, K):
-    """Tiled [..., G, 3, Np, 64] (or flat per slice) -> natural [..., 3, Np, K]."""
+    """Tiled [..., G, 3, Np, 64] -> natural [..., 3, Np, K]."""
     Qt = np.asarray(Qt)
     *lead, G, F, Np, L = Qt.shape
     n = np.moveaxis(Qt, -4, -2).reshape(tuple(lead) + (F, Np, G * L))

@@ -13,6 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libwadg.so")
+DEMO = os.path.join(PKG, "abi_demo")
 
 SOURCES = ["reference.cpp", "stage_kernel.hip", "resident_kernel.hip", "split_kernel.hip",
            "adjoint_kernel.hip",
@@ -56,6 +57,15 @@ def build(verbose=False, extra_flags=(), jobs=None):
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    # the plain-C consumer of the library (csrc/abi_demo.c), linked against
+    # it with the library's directory as run path
+    cmd = ["gcc", "-std=c99", "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I", INCLUDE,
+           "-I", "/opt/rocm/include", os.path.join(CSRC, "abi_demo.c"), "-o", DEMO,
+           "-L", PKG, "-lwadg", "-L", "/opt/rocm/lib", "-lamdhip64",
+           "-Wl,-rpath,$ORIGIN", "-Wl,-rpath,/opt/rocm/lib"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
     return LIB
 
 

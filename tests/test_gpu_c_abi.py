@@ -1,0 +1,60 @@
+"""GPU: the library through its C ABI alone.  A plain C program
+(paper_1608_03836_amd/csrc/abi_demo.c, linked against libwadg.so by the
+build) reads a mesh and tiled start states, creates a context, integrates
+every slice and takes the norms -- no Python and no torch in that process.
+Its result equals the Python binding's bit for bit (same kernels, same
+launches) and the oracle's to the FP64 bar, for the automatic kernel choice
+and for the streamed kernel."""
+
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from workloads import periodic_quad_mesh
+from oracle import WADGOracle
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+DEMO = os.path.join(ROOT, "paper_1608_03836_amd", "abi_demo")
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_c_consumer_matches_python_binding_and_oracle(tmp_path, kernel):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    import paper_1608_03836_amd as W
+    from paper_1608_03836_amd import binding as B
+    assert os.path.exists(DEMO), "abi_demo is built with the library (build.py)"
+    print(f"CASE test=c-abi kernel={kernel}", flush=True)
+    N, K1D, S, nsteps = 3, 9, 3, 2
+    mesh = periodic_quad_mesh(K1D, N, eps=0.05, warp="skew", rotate_seed=4)
+    dt = 0.1 / (K1D * (N + 1) ** 2)
+    Q0 = np.random.default_rng(31).standard_normal((S, 3, mesh.Np, mesh.K))
+    inp, out = tmp_path / "in.bin", tmp_path / "out.bin"
+    with open(inp, "wb") as f:
+        f.write(np.array([N, N + 2, mesh.K, S, nsteps, kernel], dtype="<i4").tobytes())
+        f.write(np.array([dt, 1.0, 1.0], dtype="<f8").tobytes())
+        for a, t in ((mesh.x, "<f8"), (mesh.y, "<f8"), (mesh.etoe, "<i4"), (mesh.etof, "<i4")):
+            f.write(np.ascontiguousarray(a, dtype=t).tobytes())
+        f.write(B.tile_state(Q0).astype("<f8").tobytes())
+    p = subprocess.run([DEMO, str(inp), str(out)], capture_output=True, text=True, timeout=120)
+    assert p.returncode == 0, p.stderr
+    raw = np.fromfile(out, dtype="<f8")
+    sol = W.Solver(mesh)
+    sol.set_kernel(kernel)
+    n = S * sol.slice_doubles
+    got = sol.download(torch.from_numpy(raw[:n]), S)
+    norms = raw[n:].reshape(S, 4)
+    Q = sol.upload(Q0)
+    sol.integrate(Q, S, dt, nsteps)
+    want_py = sol.download(Q, S)
+    assert np.array_equal(got, want_py)
+    assert np.array_equal(norms, sol.norms(Q, None, S))
+    want = WADGOracle(mesh).integrate(Q0, dt, nsteps)
+    for s in range(S):
+        rel = np.linalg.norm(got[s] - want[s]) / np.linalg.norm(want[s])
+        assert rel <= 1e-12, (s, rel)
