@@ -1,0 +1,439 @@
+// C ABI, batches of independent problems (declared in include/wadg.h).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "api_internal.h"
+
+using namespace wadg::host;
+
+// ---------------------------------------------------------------------------
+// Batches of independent problems.
+
+struct wadg_batch_s {
+  int device = 0, N = 0, nq1 = 0, cus = 256, nprob = 0;
+  double tau_p = 1.0, tau_u = 1.0;
+  std::vector<int32_t> pack, K, S;            // per problem: copies per lane group, elements, slices
+  std::vector<int32_t> Kv, Sv, nEG, g0;       // packed (virtual) mesh and its slices
+  std::vector<int64_t> offset;                 // [nprob + 1] state offsets in doubles
+  std::vector<double> dt;                      // per problem (last uploaded)
+  int64_t groups = 0, items = 0;
+  double* d_vol = nullptr;
+  double* d_face = nullptr;
+  int32_t* d_nbr = nullptr;
+  wadg::BatchProb* d_prob = nullptr;
+  int32_t* d_items = nullptr;
+  int grid_mult = 0;                           // persistent workgroups per CU (0: one per item)
+  int order = 0;                               // 0 problem-major, 1 interleaved
+  hipStream_t capture_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void free_batch(wadg_batch b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+  for (void* ptr : {(void*)b->d_vol, (void*)b->d_face, (void*)b->d_nbr, (void*)b->d_prob,
+                    (void*)b->d_items})
+    if (ptr) (void)hipFree(ptr);
+  delete b;
+}
+
+// Work list in the current order: problem-major (all items of problem 0,
+// then problem 1, ...) or interleaved (round-robin over problems, one slice
+// of each at a time).
+std::vector<int32_t> batch_items(const wadg_batch b) {
+  std::vector<int32_t> it;
+  it.reserve(2 * b->items);
+  if (b->order == 0) {
+    for (int i = 0; i < b->nprob; ++i)
+      for (int l = 0; l < b->Sv[i] * b->nEG[i]; ++l) {
+        it.push_back(i);
+        it.push_back(l);
+      }
+  } else {
+    int smax = 0;
+    for (int i = 0; i < b->nprob; ++i) smax = std::max(smax, b->Sv[i]);
+    for (int s = 0; s < smax; ++s)
+      for (int i = 0; i < b->nprob; ++i)
+        if (s < b->Sv[i])
+          for (int g = 0; g < b->nEG[i]; ++g) {
+            it.push_back(i);
+            it.push_back(s * b->nEG[i] + g);
+          }
+  }
+  return it;
+}
+
+int batch_upload_items(wadg_batch b) {
+  std::vector<int32_t> it = batch_items(b);
+  WADG_HIP(hipMemcpy(b->d_items, it.data(), it.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  return WADG_OK;
+}
+
+int batch_upload_dt(wadg_batch b, const double* dt) {
+  bool same = !b->dt.empty();
+  for (int i = 0; same && i < b->nprob; ++i) same = b->dt[i] == dt[i];
+  if (same) return WADG_OK;
+  std::vector<wadg::BatchProb> pr(b->nprob);
+  for (int i = 0; i < b->nprob; ++i) {
+    if (!(dt[i] > 0.0) || !std::isfinite(dt[i]))
+      return fail(WADG_E_INVALID, "dt[" + std::to_string(i) + "] must be finite and > 0");
+    pr[i] = wadg::BatchProb{b->offset[i], b->nEG[i], b->Sv[i], b->Kv[i], b->g0[i], dt[i]};
+  }
+  WADG_HIP(hipMemcpy(b->d_prob, pr.data(), pr.size() * sizeof(wadg::BatchProb),
+                     hipMemcpyHostToDevice));
+  b->dt.assign(dt, dt + b->nprob);
+  return WADG_OK;
+}
+
+int batch_grid(const wadg_batch b) {
+  if (b->grid_mult == 0 || (int64_t)b->grid_mult * b->cus >= b->items) return (int)b->items;
+  return b->grid_mult * b->cus;
+}
+
+int batch_stage(wadg_batch b, const double* qin, double* qout, double* res, int i, void* stream) {
+  wadg::BatchParams p{};
+  p.prob = b->d_prob;
+  p.items = b->d_items;
+  p.nitems = (int32_t)b->items;
+  p.Qin = qin;
+  p.Qout = qout;
+  p.res = res;
+  p.vol = b->d_vol;
+  p.face = b->d_face;
+  p.nbr = b->d_nbr;
+  p.tau_p = b->tau_p;
+  p.tau_u = b->tau_u;
+  p.rkA = kRkA[i];
+  p.rkB = kRkB[i];
+  // one workgroup per item: the split-work kernel; persistent workgroups:
+  // the streamed kernel (wadg_batch_set_schedule)
+  int e = b->grid_mult == 0 ? wadg::launch_batch_split(b->N, b->nq1, p, stream)
+                            : wadg::launch_batch_stage(b->N, b->nq1, p, batch_grid(b), stream);
+  if (e) return hip_fail((hipError_t)e, "batch stage kernel launch");
+  return WADG_OK;
+}
+
+int batch_sweep(wadg_batch b, double* Q, double* work, int32_t nsteps, void* stream) {
+  const size_t n = (size_t)b->offset[b->nprob];
+  double* res = work;
+  double* other = work + n;
+  double* cur = Q;
+  for (int stp = 0; stp < nsteps; ++stp)
+    for (int i = 0; i < 5; ++i) {
+      double* out = cur == Q ? other : Q;
+      int st = batch_stage(b, cur, out, res, i, stream);
+      if (st) return st;
+      cur = out;
+    }
+  if (cur != Q) {   // a kernel, not a runtime copy: the sweep is captured into graphs
+    int e = wadg::launch_copy(cur, Q, n, stream);
+    if (e) return hip_fail((hipError_t)e, "copy kernel launch");
+  }
+  return WADG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int wadg_batch_create(const wadg_mesh* meshes, int32_t nprob, const int32_t* S, int32_t device,
+                      wadg_batch* out) {
+  if (!out) return fail(WADG_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!meshes || !S || nprob < 1) return fail(WADG_E_INVALID, "meshes, S and nprob >= 1 required");
+  const int N = meshes[0].N, nq = meshes[0].nq1;
+  if (!wadg::stage_supported(N, nq))
+    return fail(WADG_E_UNSUPPORTED, "degree / quadrature not compiled in");
+  wadg::RefOps ops;
+  std::string err;
+  if (!wadg::build_ref_ops(N, nq, &ops, &err)) return fail(WADG_E_UNSUPPORTED, err);
+  wadg_batch b = new wadg_batch_s();
+  b->N = N;
+  b->nq1 = nq;
+  b->nprob = nprob;
+  b->tau_p = meshes[0].tau_p;
+  b->tau_u = meshes[0].tau_u;
+  const int Np = (N + 1) * (N + 1);
+  const size_t tile = (size_t)3 * Np * wadg::kWave;
+  std::vector<double> vol, face;
+  std::vector<int32_t> nbr;
+  b->offset.push_back(0);
+  for (int i = 0; i < nprob; ++i) {
+    const wadg_mesh& m = meshes[i];
+    int st = check_mesh(&m);
+    if (st) {
+      free_batch(b);
+      return fail(st, "problem " + std::to_string(i) + ": " + g_last_error);
+    }
+    if (m.N != N || m.nq1 != nq || m.tau_p != b->tau_p || m.tau_u != b->tau_u) {
+      free_batch(b);
+      return fail(WADG_E_INVALID, "all problems of a batch share N, nq1, tau_p and tau_u");
+    }
+    if (S[i] < 1) {
+      free_batch(b);
+      return fail(WADG_E_INVALID, "S[" + std::to_string(i) + "] must be >= 1");
+    }
+    // meshes of at most half a lane group carry several slices side by side
+    const int P = m.K <= wadg::kWave / 2 ? wadg::kWave / m.K : 1;
+    const int Kv = P * m.K;
+    std::vector<double> x((size_t)Kv * Np), y((size_t)Kv * Np), c2;
+    std::vector<int32_t> etoe((size_t)Kv * 4), etof((size_t)Kv * 4);
+    const int nqq = nq * nq;
+    if (m.c2q) c2.resize((size_t)Kv * nqq);
+    for (int j = 0; j < P; ++j) {
+      std::memcpy(&x[(size_t)j * m.K * Np], m.x, sizeof(double) * m.K * Np);
+      std::memcpy(&y[(size_t)j * m.K * Np], m.y, sizeof(double) * m.K * Np);
+      for (int k = 0; k < m.K * 4; ++k) {
+        etoe[(size_t)j * m.K * 4 + k] = m.etoe[k] + j * m.K;
+        etof[(size_t)j * m.K * 4 + k] = m.etof[k];
+      }
+      if (m.c2q) std::memcpy(&c2[(size_t)j * m.K * nqq], m.c2q, sizeof(double) * m.K * nqq);
+    }
+    wadg::MeshIn mi{N, nq, Kv, x.data(), y.data(), etoe.data(), etof.data(),
+                    m.c2q ? c2.data() : nullptr};
+    std::vector<double> v0, f0;
+    std::vector<int32_t> n0;
+    int g = wadg::build_geometry(mi, ops, &v0, &f0, &n0, &err);
+    if (g) {
+      free_batch(b);
+      return fail(g == -1 ? WADG_E_INVALID : WADG_E_GEOMETRY,
+                  "problem " + std::to_string(i) + ": " + err);
+    }
+    std::vector<double> vt = wadg::tile_planes(v0, 6 * nqq, Kv);
+    std::vector<double> ft = wadg::tile_planes(f0, 12 * nq, Kv);
+    std::vector<int32_t> nt = wadg::tile_planes(n0, 8, Kv);
+    vol.insert(vol.end(), vt.begin(), vt.end());
+    face.insert(face.end(), ft.begin(), ft.end());
+    nbr.insert(nbr.end(), nt.begin(), nt.end());
+    const int nEG = (Kv + wadg::kWave - 1) / wadg::kWave;
+    const int Sv = (S[i] + P - 1) / P;
+    b->pack.push_back(P);
+    b->K.push_back(m.K);
+    b->S.push_back(S[i]);
+    b->Kv.push_back(Kv);
+    b->Sv.push_back(Sv);
+    b->nEG.push_back(nEG);
+    b->g0.push_back((int32_t)b->groups);
+    b->groups += nEG;
+    b->items += (int64_t)Sv * nEG;
+    b->offset.push_back(b->offset.back() + (int64_t)Sv * nEG * (int64_t)tile);
+  }
+  if (b->items >= (1LL << 31) || b->groups >= (1LL << 31)) {
+    free_batch(b);
+    return fail(WADG_E_INVALID, "batch too large");
+  }
+  int dev = device;
+  if (dev < 0 && hipGetDevice(&dev) != hipSuccess) {
+    free_batch(b);
+    return fail(WADG_E_DEVICE, "no current HIP device");
+  }
+  DeviceGuard guard(dev);
+  if (!guard.ok) {
+    free_batch(b);
+    return fail(WADG_E_DEVICE, "cannot select HIP device " + std::to_string(dev));
+  }
+  b->device = dev;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      cus > 0)
+    b->cus = cus;
+  hipError_t e;
+  if ((e = hipMalloc(&b->d_vol, vol.size() * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc(&b->d_face, face.size() * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc(&b->d_nbr, nbr.size() * sizeof(int32_t))) != hipSuccess ||
+      (e = hipMalloc(&b->d_prob, (size_t)nprob * sizeof(wadg::BatchProb))) != hipSuccess ||
+      (e = hipMalloc(&b->d_items, (size_t)b->items * 2 * sizeof(int32_t))) != hipSuccess ||
+      (e = hipMemcpy(b->d_vol, vol.data(), vol.size() * sizeof(double),
+                     hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(b->d_face, face.data(), face.size() * sizeof(double),
+                     hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(b->d_nbr, nbr.data(), nbr.size() * sizeof(int32_t),
+                     hipMemcpyHostToDevice)) != hipSuccess) {
+    free_batch(b);
+    return hip_fail(e, "wadg_batch_create device setup");
+  }
+  int st = batch_upload_items(b);
+  if (st) {
+    free_batch(b);
+    return st;
+  }
+  *out = b;
+  return WADG_OK;
+}
+
+void wadg_batch_destroy(wadg_batch b) {
+  if (!b) return;
+  DeviceGuard guard(b->device);
+  free_batch(b);
+}
+
+int wadg_batch_layout(wadg_batch b, int64_t* offset, int32_t* pack) {
+  if (!b) return fail(WADG_E_INVALID, "batch is NULL");
+  if (offset) std::memcpy(offset, b->offset.data(), (b->nprob + 1) * sizeof(int64_t));
+  if (pack) std::memcpy(pack, b->pack.data(), b->nprob * sizeof(int32_t));
+  return WADG_OK;
+}
+
+int wadg_batch_workspace_bytes(wadg_batch b, size_t* bytes) {
+  if (!b) return fail(WADG_E_INVALID, "batch is NULL");
+  if (!bytes) return fail(WADG_E_INVALID, "bytes is NULL");
+  *bytes = 2 * (size_t)b->offset[b->nprob] * sizeof(double);
+  return WADG_OK;
+}
+
+int wadg_batch_integrate(wadg_batch b, double* Q, double* work, const double* dt, int32_t nsteps,
+                         void* stream) {
+  if (!b) return fail(WADG_E_INVALID, "batch is NULL");
+  if (!Q || !work || !dt) return fail(WADG_E_INVALID, "Q, work and dt must not be NULL");
+  if (nsteps < 0) return fail(WADG_E_INVALID, "nsteps must be >= 0");
+  const size_t n = (size_t)b->offset[b->nprob];
+  if (overlaps(Q, n * sizeof(double), work, 2 * n * sizeof(double)))
+    return fail(WADG_E_INVALID, "work must not alias Q");
+  if (nsteps == 0) return WADG_OK;
+  DeviceGuard guard(b->device);
+  if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select the batch's device");
+  int st = batch_upload_dt(b, dt);
+  if (st) return st;
+  return batch_sweep(b, Q, work, nsteps, stream);
+}
+
+int wadg_batch_set_schedule(wadg_batch b, int32_t wg_per_cu, int32_t order) {
+  if (!b) return fail(WADG_E_INVALID, "batch is NULL");
+  if (wg_per_cu < 0 || wg_per_cu > 64 || (order != 0 && order != 1))
+    return fail(WADG_E_INVALID, "wg_per_cu in [0, 64] and order in {0, 1} required");
+  if (b->exec) return fail(WADG_E_INVALID, "release the captured graph first");
+  DeviceGuard guard(b->device);
+  if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select the batch's device");
+  b->grid_mult = wg_per_cu;
+  if (order != b->order) {
+    b->order = order;
+    int st = batch_upload_items(b);
+    if (st) return st;
+  }
+  return WADG_OK;
+}
+
+int wadg_batch_tune(wadg_batch b, const double* Q, double* work, const double* dt, int32_t reps,
+                    int32_t* wg_per_cu, int32_t* order, double* best_us, void* stream) {
+  if (!b) return fail(WADG_E_INVALID, "batch is NULL");
+  if (!Q || !work || !dt || !wg_per_cu || !order || !best_us)
+    return fail(WADG_E_INVALID, "Q, work, dt and the outputs must not be NULL");
+  if (reps < 1) return fail(WADG_E_INVALID, "reps must be >= 1");
+  if (b->exec) return fail(WADG_E_INVALID, "release the captured graph first");
+  const size_t n = (size_t)b->offset[b->nprob];
+  if (overlaps(Q, n * sizeof(double), work, 2 * n * sizeof(double)))
+    return fail(WADG_E_INVALID, "work must not alias Q");
+  DeviceGuard guard(b->device);
+  if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select the batch's device");
+  int st = batch_upload_dt(b, dt);
+  if (st) return st;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hip_fail(hipErrorUnknown, "hipEventCreate");
+  }
+  // candidates: persistent grids of 1, 2, 4, 8 two-wave workgroups per CU
+  // (streamed kernel) or one four-wave workgroup per item (split kernel), in
+  // both item orders; each timed on a stage with a residual read (Q is only
+  // read, the workspace is scratch)
+  const int mults[] = {1, 2, 4, 8, 0};
+  double best = 1e300;
+  const int m0 = b->grid_mult, o0 = b->order;
+  int bm = m0, bo = o0;
+  for (int o = 0; o < 2 && !st; ++o) {
+    for (int m : mults) {
+      if ((st = wadg_batch_set_schedule(b, m, o))) break;
+      if ((st = batch_stage(b, Q, work, work + n, 1, stream))) break;
+      if (hipEventRecord(e0, hs) != hipSuccess) { st = hip_fail(hipErrorUnknown, "event"); break; }
+      for (int r = 0; r < reps && !st; ++r) st = batch_stage(b, Q, work, work + n, 1, stream);
+      if (st) break;
+      float ms = 0.f;
+      if (hipEventRecord(e1, hs) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        st = hip_fail(hipErrorUnknown, "event timing");
+        break;
+      }
+      const double us = 1e3 * ms / reps;
+      if (us < best) {
+        best = us;
+        bm = m;
+        bo = o;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) {
+    (void)wadg_batch_set_schedule(b, m0, o0);   // leave the schedule as it was
+    return st;
+  }
+  if ((st = wadg_batch_set_schedule(b, bm, bo))) return st;
+  *wg_per_cu = bm;
+  *order = bo;
+  *best_us = best;
+  return WADG_OK;
+}
+
+int wadg_batch_capture(wadg_batch b, double* Q, double* work, const double* dt, int32_t nsteps) {
+  if (!b) return fail(WADG_E_INVALID, "batch is NULL");
+  if (!Q || !work || !dt || nsteps < 1)
+    return fail(WADG_E_INVALID, "Q, work, dt and nsteps >= 1 required");
+  const size_t n = (size_t)b->offset[b->nprob];
+  if (overlaps(Q, n * sizeof(double), work, 2 * n * sizeof(double)))
+    return fail(WADG_E_INVALID, "work must not alias Q");
+  DeviceGuard guard(b->device);
+  if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select the batch's device");
+  int st = batch_upload_dt(b, dt);
+  if (st) return st;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  if (!b->capture_stream)
+    WADG_HIP(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
+  WADG_HIP(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
+  st = batch_sweep(b, Q, work, nsteps, b->capture_stream);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(b->capture_stream, &g);
+  if (st) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  b->graph = g;
+  WADG_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  return WADG_OK;
+}
+
+int wadg_batch_replay(wadg_batch b, void* stream) {
+  if (!b) return fail(WADG_E_INVALID, "batch is NULL");
+  if (!b->exec) return fail(WADG_E_INVALID, "no captured sweep (wadg_batch_capture)");
+  DeviceGuard guard(b->device);
+  if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select the batch's device");
+  WADG_HIP(hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)));
+  return WADG_OK;
+}
+
+int wadg_batch_release_graph(wadg_batch b) {
+  if (!b) return fail(WADG_E_INVALID, "batch is NULL");
+  DeviceGuard guard(b->device);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  return WADG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+// Host-side internals shared by the sources of the C ABI: the context,
+// error reporting, device selection, argument checks and the stage-launch
+// policy (launch.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "wadg.h"
+#include "wadg_internal.h"
+
+struct wadg_ctx_s {
+  int device = 0;
+  int N = 0, nq1 = 0, K = 0;
+  double tau_p = 1.0, tau_u = 1.0;
+  int tile_groups = 8;   // schedule: element groups per tile
+  int tile_slices = 0;   // slices per tile (0: all)
+  int kernel = WADG_KERNEL_AUTO;
+  int cus = 256;         // compute units of the device
+  double c2_scale = 1.0; // multiplies c^2 (wadg_set_c2_scale)
+  unsigned order_flip = 0;  // item order of the next stage launch (launch_stage)
+  double* d_vol = nullptr;
+  double* d_face = nullptr;
+  float* d_vol32 = nullptr;      // geometry rounded to FP32 (FP32-bulk path)
+  float* d_face32 = nullptr;
+  int32_t* d_nbr = nullptr;
+  double* d_partials = nullptr;  // norms scratch, grown on demand
+  double* d_out = nullptr;
+  int32_t norms_cap = 0;
+  // adjoint: a second stream (default priority) for the forward recompute
+  // that overlaps the reverse sweep, and the events that order the two
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_in = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_rev[2] = {nullptr, nullptr};
+  int groups() const { return (K + wadg::kWave - 1) / wadg::kWave; }
+  size_t tile() const { return (size_t)3 * (N + 1) * (N + 1) * wadg::kWave; }
+  size_t slice_doubles() const { return (size_t)groups() * tile(); }
+  size_t state_doubles(int32_t S) const { return (size_t)S * slice_doubles(); }
+};
+
+namespace wadg {
+namespace host {
+
+// The last failure's detail, per thread (wadg_last_error).
+extern thread_local std::string g_last_error;
+
+// Records msg as the thread's last error and returns code.
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define WADG_HIP(call)                                  \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);   \
+  } while (0)
+
+// LSRK(5,4) 2N-storage coefficients (launch.hip).
+extern const double kRkA[5];
+extern const double kRkB[5];
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) return;
+    ok = (dev == prev) || hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+int check_mesh(const wadg_mesh* m);
+int check_slices(wadg_ctx c, int32_t S);
+
+inline wadg::MeshIn mesh_in(const wadg_mesh* m) {
+  return wadg::MeshIn{m->N, m->nq1, m->K, m->x, m->y, m->etoe, m->etof, m->c2q};
+}
+
+inline bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = static_cast<const char*>(a);
+  const char* pb = static_cast<const char*>(b);
+  return pa < pb + nb && pb < pa + na;
+}
+
+// The stage kernel that runs for this context, precision and launch mode.
+int kernel_path(wadg_ctx c, bool fp32, int mode);
+// Launch one stage of `mode` with the context's kernel choice and the
+// alternating work-item order.
+int launch_stage(wadg_ctx c, int mode, bool fp32, const wadg::StageParams& p0, void* stream);
+// Stage parameters of the context for S slices (geometry, schedule, penalties).
+wadg::StageParams base_params(wadg_ctx c, int32_t S);
+
+}  // namespace host
+}  // namespace wadg
