@@ -217,10 +217,14 @@ int wadg_set_c2_scale(wadg_ctx ctx, double scale);
  *   D = diag(1,-1,-1) (the strong-weak DG operator A of Section 4.1 has
  *   skew p-u coupling and symmetric penalty blocks; Mtilde^{-1} is the
  *   symmetric WADG inverse of Section 4), recomputing each slice's forward
- *   states from its checkpoint.  Padding entries of seed must be zero; grad
- *   padding is unspecified.  Synchronises `stream` once at the end.
- *   Returns WADG_E_NONFINITE if dJ_dscale is not finite.  work must not
- *   overlap chk, seed or grad. */
+ *   stage residuals from its checkpoint (held for one slice at a time,
+ *   double-buffered: the workspace is about 10 nsteps + 6 slices).  The
+ *   recompute runs on a second stream owned by the context, ordered against
+ *   `stream` with events; the context must not be used from two threads at
+ *   once.  Padding entries of seed must be zero; grad padding is
+ *   unspecified.  Synchronises `stream` once at the end.  Returns
+ *   WADG_E_NONFINITE if dJ_dscale is not finite.  work must not overlap
+ *   chk, seed or grad. */
 int wadg_adjoint_workspace_bytes(wadg_ctx ctx, int32_t nsteps, size_t* bytes);
 int wadg_forward_checkpoints(wadg_ctx ctx, double* chk, void* work, int32_t S, double dt,
                              int32_t nsteps, void* stream);
