@@ -376,3 +376,38 @@ def test_parareal_fp32_fine_converges(W):
           f"error vs FP64 serial sweep {err:.2e}")
     assert ch <= 1e-6 and it <= S
     assert err <= 1e-6
+
+
+def test_random_configurations_match_oracle(W):
+    """24 seeded random small configurations -- degree, quadrature, mesh
+    size, warp, frame rotation, wave speed, penalties, slices, steps and the
+    stage kernel -- each checked against the oracle (RHS and sweep) to the
+    FP64 bar."""
+    rng = np.random.default_rng(2024)
+    kernels = (W.WADG_KERNEL_AUTO, W.WADG_KERNEL_STREAMED, W.WADG_KERNEL_RESIDENT,
+               W.WADG_KERNEL_SPLIT)
+    for case in range(24):
+        N = int(rng.integers(1, 5))
+        nq1 = N + int(rng.integers(1, 4))
+        K1D = int(rng.integers(2, 10))
+        warp = ("diag", "skew")[int(rng.integers(0, 2))]
+        rot = None if rng.random() < 0.3 else int(rng.integers(0, 100))
+        eps = float(rng.choice([0.0, 0.03, 0.05]))
+        tau = float(rng.choice([0.0, 0.5, 1.0]))
+        c2f = c2_layered if rng.random() < 0.5 else c2_constant(float(rng.uniform(0.5, 2.0)))
+        S, n = int(rng.integers(1, 5)), int(rng.integers(1, 4))
+        kern = int(rng.choice(kernels))
+        if kern == W.WADG_KERNEL_RESIDENT and not (N <= 2 or (N == 3 and nq1 <= 5)):
+            kern = W.WADG_KERNEL_AUTO     # its FP64 geometry does not fit in LDS
+        _print_case(test="random", case=case, N=N, nq1=nq1, K1D=K1D, warp=warp, rot=rot,
+                    eps=eps, tau=tau, S=S, n=n, kernel=kern)
+        mesh = periodic_quad_mesh(K1D, N, eps=eps, warp=warp, rotate_seed=rot)
+        Q0 = rng.standard_normal((S, 3, mesh.Np, mesh.K))
+        dt = 0.2 / (K1D * (N + 1) ** 2)
+        o = WADGOracle(mesh, nq1=nq1, c2=c2f, tau_p=tau, tau_u=tau)
+        sol = W.Solver(mesh, nq1=nq1, c2=c2f, tau_p=tau, tau_u=tau)
+        sol.set_kernel(kern)
+        _assert_close(sol.download(sol.rhs(sol.upload(Q0), S), S), o.rhs(Q0))
+        Q = sol.upload(Q0)
+        sol.integrate(Q, S, dt, n)
+        _assert_close(sol.download(Q, S), o.integrate(Q0, dt, n))
