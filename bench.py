@@ -446,6 +446,14 @@ def main():
                      "avg_launch_us": stage_ms * 1e3,
                      "algorithmic_bytes_per_launch": bytes_launch},
     }
+    # the paper's own stage rate, quoted with its hardware (context only: a
+    # different device, precision, element type and mesh); this run in the
+    # same unit, scalar unknowns x RK stages per second
+    line["paper_context"] = {
+        "value": 9.15e8, "unit": "dof-stages/s",
+        "what": "strong-weak WADG stage rate at N=3, Section 5.6 runtime per degree of freedom",
+        "hardware": "one NVIDIA GTX 980, FP32 (inferred), 3D curvilinear tetrahedra",
+        "this_run": 3 * nodes * S * 5 * prob.nsteps / (elapsed / args.steps)}
     if args.cpu_baseline_seconds > 0:
         line["cpu_baseline"] = cpu_baseline(prob, args.cpu_baseline_seconds)
     print(json.dumps(line), flush=True)
