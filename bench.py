@@ -451,7 +451,7 @@ def main():
     # same unit, scalar unknowns x RK stages per second
     line["paper_context"] = {
         "value": 9.15e8, "unit": "dof-stages/s",
-        "what": "strong-weak WADG stage rate at N=3, Section 5.6 runtime per degree of freedom",
+        "what": "strong-weak WADG stage rate at N=3 (Section 5.6, time per unknown and stage)",
         "hardware": "one NVIDIA GTX 980, FP32 (inferred), 3D curvilinear tetrahedra",
         "this_run": 3 * nodes * S * 5 * prob.nsteps / (elapsed / args.steps)}
     if args.cpu_baseline_seconds > 0:
