@@ -120,7 +120,8 @@ int wadg_quadrature_points(const wadg_mesh* mesh, double* xq, double* yq);
  *   face [3][4][nq1][K]: outward unit normal n_x, n_y and w sJ (face
  *        quadrature weight times surface Jacobian).
  * Either pointer may be NULL.  Returns WADG_E_GEOMETRY if J <= 0 anywhere,
- * a value is non-finite or the faces do not conform.  No GPU needed. */
+ * a value is non-finite or the faces do not conform (the arrays' contents
+ * are then unspecified).  No GPU needed; runs on the host's threads. */
 int wadg_geometry(const wadg_mesh* mesh, double* vol, double* face);
 
 /* Build a context on HIP device `device` (-1: the current device): validates

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -100,11 +101,8 @@ int wadg_geometry(const wadg_mesh* mesh, double* vol, double* face) {
   wadg::RefOps ops;
   std::string err;
   if (!wadg::build_ref_ops(mesh->N, mesh->nq1, &ops, &err)) return fail(WADG_E_UNSUPPORTED, err);
-  std::vector<double> v, f;
-  int g = wadg::build_geometry(mesh_in(mesh), ops, &v, &f, nullptr, &err);
+  int g = wadg::build_geometry(mesh_in(mesh), ops, vol, face, nullptr, false, &err);
   if (g) return fail(g == -1 ? WADG_E_INVALID : WADG_E_GEOMETRY, err);
-  if (vol) std::memcpy(vol, v.data(), v.size() * sizeof(double));
-  if (face) std::memcpy(face, f.data(), f.size() * sizeof(double));
   return WADG_OK;
 }
 
@@ -118,15 +116,16 @@ int wadg_create(const wadg_mesh* mesh, int32_t device, wadg_ctx* out) {
   wadg::RefOps ops;
   std::string err;
   if (!wadg::build_ref_ops(mesh->N, mesh->nq1, &ops, &err)) return fail(WADG_E_UNSUPPORTED, err);
-  std::vector<double> vol0, face0;
-  std::vector<int32_t> nbr0;
-  int g = wadg::build_geometry(mesh_in(mesh), ops, &vol0, &face0, &nbr0, &err);
-  if (g) return fail(g == -1 ? WADG_E_INVALID : WADG_E_GEOMETRY, err);
+  // geometry straight into the tiled device layout (no untiled copy); its
+  // FP32 copy for the FP32-bulk path is rounded on the device
   const int nq = mesh->nq1;
-  std::vector<double> vol = wadg::tile_planes(vol0, 6 * nq * nq, mesh->K);
-  std::vector<double> face = wadg::tile_planes(face0, 12 * nq, mesh->K);
-  std::vector<int32_t> nbr = wadg::tile_planes(nbr0, 8, mesh->K);
-  std::vector<float> vol32(vol.begin(), vol.end()), face32(face.begin(), face.end());
+  const size_t G = ((size_t)mesh->K + wadg::kWave - 1) / wadg::kWave;
+  const size_t nv = G * 6 * nq * nq * wadg::kWave, nf = G * 12 * nq * wadg::kWave,
+               nn = G * 8 * wadg::kWave;
+  std::unique_ptr<double[]> vol(new double[nv]), face(new double[nf]);
+  std::unique_ptr<int32_t[]> nbr(new int32_t[nn]);
+  int g = wadg::build_geometry(mesh_in(mesh), ops, vol.get(), face.get(), nbr.get(), true, &err);
+  if (g) return fail(g == -1 ? WADG_E_INVALID : WADG_E_GEOMETRY, err);
 
   int dev = device;
   if (dev < 0) WADG_HIP(hipGetDevice(&dev));
@@ -145,21 +144,21 @@ int wadg_create(const wadg_mesh* mesh, int32_t device, wadg_ctx* out) {
   c->tau_p = mesh->tau_p;
   c->tau_u = mesh->tau_u;
   hipError_t e;
-  if ((e = hipMalloc(&c->d_vol, vol.size() * sizeof(double))) != hipSuccess ||
-      (e = hipMalloc(&c->d_face, face.size() * sizeof(double))) != hipSuccess ||
-      (e = hipMalloc(&c->d_nbr, nbr.size() * sizeof(int32_t))) != hipSuccess ||
-      (e = hipMemcpy(c->d_vol, vol.data(), vol.size() * sizeof(double),
-                     hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(c->d_face, face.data(), face.size() * sizeof(double),
-                     hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(c->d_nbr, nbr.data(), nbr.size() * sizeof(int32_t),
-                     hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMalloc(&c->d_vol32, vol32.size() * sizeof(float))) != hipSuccess ||
-      (e = hipMalloc(&c->d_face32, face32.size() * sizeof(float))) != hipSuccess ||
-      (e = hipMemcpy(c->d_vol32, vol32.data(), vol32.size() * sizeof(float),
-                     hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(c->d_face32, face32.data(), face32.size() * sizeof(float),
-                     hipMemcpyHostToDevice)) != hipSuccess) {
+  if ((e = hipMalloc(&c->d_vol, nv * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc(&c->d_face, nf * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc(&c->d_nbr, nn * sizeof(int32_t))) != hipSuccess ||
+      (e = hipMemcpy(c->d_vol, vol.get(), nv * sizeof(double), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy(c->d_face, face.get(), nf * sizeof(double), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy(c->d_nbr, nbr.get(), nn * sizeof(int32_t), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMalloc(&c->d_vol32, nv * sizeof(float))) != hipSuccess ||
+      (e = hipMalloc(&c->d_face32, nf * sizeof(float))) != hipSuccess ||
+      (e = (hipError_t)wadg::launch_to_fp32(c->d_vol, c->d_vol32, nv, nullptr)) != hipSuccess ||
+      (e = (hipError_t)wadg::launch_to_fp32(c->d_face, c->d_face32, nf, nullptr)) !=
+          hipSuccess ||
+      (e = hipDeviceSynchronize()) != hipSuccess) {
     free_ctx(c);
     return hip_fail(e, "wadg_create device setup");
   }

@@ -202,17 +202,15 @@ int wadg_batch_create(const wadg_mesh* meshes, int32_t nprob, const int32_t* S, 
     }
     wadg::MeshIn mi{N, nq, Kv, x.data(), y.data(), etoe.data(), etof.data(),
                     m.c2q ? c2.data() : nullptr};
-    std::vector<double> v0, f0;
-    std::vector<int32_t> n0;
-    int g = wadg::build_geometry(mi, ops, &v0, &f0, &n0, &err);
+    const size_t Gv = ((size_t)Kv + wadg::kWave - 1) / wadg::kWave;
+    std::vector<double> vt(Gv * 6 * nqq * wadg::kWave), ft(Gv * 12 * nq * wadg::kWave);
+    std::vector<int32_t> nt(Gv * 8 * wadg::kWave);
+    int g = wadg::build_geometry(mi, ops, vt.data(), ft.data(), nt.data(), true, &err);
     if (g) {
       free_batch(b);
       return fail(g == -1 ? WADG_E_INVALID : WADG_E_GEOMETRY,
                   "problem " + std::to_string(i) + ": " + err);
     }
-    std::vector<double> vt = wadg::tile_planes(v0, 6 * nqq, Kv);
-    std::vector<double> ft = wadg::tile_planes(f0, 12 * nq, Kv);
-    std::vector<int32_t> nt = wadg::tile_planes(n0, 8, Kv);
     vol.insert(vol.end(), vt.begin(), vt.end());
     face.insert(face.end(), ft.begin(), ft.end());
     nbr.insert(nbr.end(), nt.begin(), nt.end());

@@ -41,26 +41,18 @@ struct MeshIn {
   const double* c2q;
 };
 
-// Host geometry arrays, untiled (element index fastest):
-//   vol  [6][nq*nq][K]   W ys, -W xs, -W yr, W xr, c2/J, 1/J
-//   face [3][4][nq][K]   nx, ny, w sJ
-//   nbr  [2][4][K]       offset (in values), within one slice of the tiled
-//                        state layout, of the neighbour's value at my face
-//                        node 0 (field 0), and the step along my face parameter
-int build_geometry(const MeshIn& m, const RefOps& ops, std::vector<double>* vol,
-                   std::vector<double>* face, std::vector<int32_t>* nbr, std::string* err);
-
-// Re-layout an untiled [P][K] array into the tiled [G][P][64] device layout
-// (padding zero-filled).
-template <typename T>
-std::vector<T> tile_planes(const std::vector<T>& a, int planes, int K) {
-  const int G = (K + kWave - 1) / kWave;
-  std::vector<T> t((size_t)G * planes * kWave, T(0));
-  for (int p = 0; p < planes; ++p)
-    for (int k = 0; k < K; ++k)
-      t[((size_t)(k / kWave) * planes + p) * kWave + (k % kWave)] = a[(size_t)p * K + k];
-  return t;
-}
+// Host geometry arrays, P planes of K values each:
+//   vol  P = 6 nq^2   W ys, -W xs, -W yr, W xr, c2/J, 1/J at each point
+//   face P = 12 nq    nx, ny, w sJ for each face and point
+//   nbr  P = 8        offset (in values), within one slice of the tiled
+//                     state layout, of the neighbour's value at my face
+//                     node 0 (field 0), and the step along my face parameter
+// written into caller-owned arrays (any may be NULL) either untiled,
+// [P][K] (element index fastest), or tiled, [G][P][64] with G = ceil(K/64)
+// and the padding lanes of the last group zero (the device layout).  On
+// failure the contents are unspecified.  Runs on the host's threads.
+int build_geometry(const MeshIn& m, const RefOps& ops, double* vol, double* face,
+                   int32_t* nbr, bool tiled, std::string* err);
 
 // Physical coordinates of the volume quadrature points, [K][nq*nq].
 void quadrature_points(const MeshIn& m, const RefOps& ops, double* xq, double* yq);
