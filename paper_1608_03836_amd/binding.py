@@ -151,6 +151,17 @@ class MeshDesc:
         self.c2q = None if c2q is None else np.ascontiguousarray(c2q, dtype=np.float64)
         self.N, self.nq1, self.K = int(N), int(nq1), int(self.x.shape[0])
         self.tau_p, self.tau_u = float(tau_p), float(tau_u)
+        # the library reads K rows of each array; it rejects an unsupported
+        # degree or quadrature before reading any of them
+        if 1 <= self.N <= WADG_MAX_N and self.N + 1 <= self.nq1 <= self.N + 3:
+            K, np1 = self.K, (self.N + 1) ** 2
+            want = {"x": (K, np1), "y": (K, np1), "etoe": (K, 4), "etof": (K, 4)}
+            if self.c2q is not None:
+                want["c2q"] = (K, self.nq1 ** 2)
+            for name, shape in want.items():
+                got = getattr(self, name).shape
+                if got != shape:
+                    raise ValueError(f"MeshDesc: {name} has shape {got}, expected {shape}")
 
     def struct(self):
         return wadg_mesh(

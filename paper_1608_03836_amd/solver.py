@@ -12,16 +12,21 @@ class Solver:
 
     ``mesh`` is any object with ``N, x, y, etoe, etof`` (GLL node coordinates
     [K][(N+1)^2], connectivity [K][4]); ``c2`` an optional callable
-    ``c2(x, y)`` evaluated at the volume quadrature points.
+    ``c2(x, y)`` evaluated at the volume quadrature points, or ``c2q`` the
+    values there, [K][nq1^2] (at most one of the two).
     """
 
-    def __init__(self, mesh, nq1=None, c2=None, tau_p=1.0, tau_u=1.0, device=0):
+    def __init__(self, mesh, nq1=None, c2=None, tau_p=1.0, tau_u=1.0, device=0, c2q=None):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", device)
         N = int(mesh.N)
         nq1 = N + 2 if nq1 is None else int(nq1)
-        desc = B.MeshDesc(N, nq1, mesh.x, mesh.y, mesh.etoe, mesh.etof, None, tau_p, tau_u)
+        if c2 is not None and c2q is not None:
+            raise ValueError("give c2 or c2q, not both")
+        desc = B.MeshDesc(N, nq1, mesh.x, mesh.y, mesh.etoe, mesh.etof,
+                          None if c2q is None else np.asarray(c2q, dtype=np.float64),
+                          tau_p, tau_u)
         if c2 is not None:
             xq, yq = B.wadg_quadrature_points(desc)
             desc = B.MeshDesc(N, nq1, mesh.x, mesh.y, mesh.etoe, mesh.etof,

@@ -156,3 +156,31 @@ def test_single_hip_runtime_in_process():
     maps = open("/proc/self/maps").read()
     libs = {line.split()[-1] for line in maps.splitlines() if "libamdhip64" in line}
     assert len(libs) == 1, libs
+
+
+def test_geometry_of_periodic_cover_repeats_base_geometry():
+    """Host geometry depends only on an element's own coordinates and c^2, so
+    on a periodic cover (copies of the base mesh with unchanged coordinates)
+    every copy's geometry equals its base element's, bitwise; the cover's
+    wrap-around faces match modulo the period."""
+    from workloads import periodic_cover
+    m, d = _mesh(K1D=5, N=2, rot=8, nq1=4)
+    cov, idx = periodic_cover(m, 3)
+    dc = W.MeshDesc(2, 4, cov.x, cov.y, cov.etoe, cov.etof)
+    xq, yq = W.wadg_quadrature_points(d)
+    c2 = c2_layered(xq, yq)
+    vb, fb = W.wadg_geometry(W.MeshDesc(2, 4, m.x, m.y, m.etoe, m.etof, c2))
+    vc, fc = W.wadg_geometry(W.MeshDesc(2, 4, cov.x, cov.y, cov.etoe, cov.etof, c2[idx]))
+    assert np.array_equal(vc, vb[..., idx]) and np.array_equal(fc, fb[..., idx])
+    assert np.array_equal(W.wadg_quadrature_points(dc)[0], xq[idx])
+
+
+def test_mesh_arrays_of_the_wrong_shape_are_refused():
+    """The binding checks array shapes before the library reads them."""
+    m, d = _mesh(N=2, nq1=4)
+    with pytest.raises(ValueError, match="c2q"):
+        W.MeshDesc(2, 4, m.x, m.y, m.etoe, m.etof, np.ones((m.K, 9)))
+    with pytest.raises(ValueError, match="etof"):
+        W.MeshDesc(2, 4, m.x, m.y, m.etoe, m.etof[:, :3])
+    with pytest.raises(ValueError, match="y"):
+        W.MeshDesc(2, 4, m.x, m.y[:-1], m.etoe, m.etof)

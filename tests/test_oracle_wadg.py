@@ -258,3 +258,34 @@ def test_nonconforming_connectivity_is_rejected():
     mesh.etoe[0, 1] = 5
     with pytest.raises(ValueError):
         WADGOracle(mesh)
+
+
+def test_periodic_cover_evolves_copy_by_copy():
+    """Translation invariance of the discretisation (Section 4's scheme is
+    element-local plus face coupling): on the m x m periodic cover of a mesh,
+    a state that repeats the base state on every copy has the base RHS and
+    the base LSRK solution on every copy.  Pins the cover generator that the
+    maximum-size GPU test relies on; a wrong neighbour displacement or face
+    map in the cover breaks it."""
+    from workloads import periodic_cover
+    base = periodic_quad_mesh(4, 2, eps=0.05, warp="skew", rotate_seed=6)
+    cover, idx = periodic_cover(base, 2)
+    assert cover.K == 4 * base.K and cover.K1D == 8
+    ob = WADGOracle(base, c2=c2_layered)
+    oc = WADGOracle(cover, c2=c2_layered)      # also checks conformity mod 1
+    Q0 = np.random.default_rng(4).standard_normal((2, 3, base.Np, base.K))
+    Qc = Q0[..., idx]
+    np.testing.assert_allclose(oc.rhs(Qc), ob.rhs(Q0)[..., idx], rtol=0,
+                               atol=1e-12 * np.max(np.abs(ob.rhs(Q0))))
+    want = ob.integrate(Q0, 0.01, 3)[..., idx]
+    np.testing.assert_allclose(oc.integrate(Qc, 0.01, 3), want, rtol=0,
+                               atol=1e-12 * np.max(np.abs(want)))
+    # the copies are distinct elements: perturbing one copy of base element 0
+    # (cover element 0) changes its RHS but not that of another copy of it
+    # (cover element 4 = (4, 0), not adjacent to (0, 0) on the 8 x 8 torus)
+    assert idx[0] == idx[4] == 0
+    Qx = Qc.copy()
+    Qx[..., 0] *= 2.0
+    rx, rb = oc.rhs(Qx), ob.rhs(Q0)
+    assert not np.allclose(rx[..., 0], rb[..., 0])
+    np.testing.assert_allclose(rx[..., 4], rb[..., 0], rtol=0, atol=1e-12 * np.max(np.abs(rb)))

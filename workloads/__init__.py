@@ -13,7 +13,7 @@ field ``f`` in (p, u, v), local node ``n = a + (N+1) b`` (``a`` along the
 reference r direction, ``b`` along s), element ``k`` fastest.
 """
 
-from .mesh import gll_points, periodic_quad_mesh, QuadMesh  # noqa: F401
+from .mesh import gll_points, periodic_quad_mesh, periodic_cover, QuadMesh  # noqa: F401
 from .fields import (  # noqa: F401
     wave_modes, PlaneWaveSolution, smooth_pressure, uniform_pressure,
     c2_constant, c2_layered, pack_state, unpack_state, heat_initial,

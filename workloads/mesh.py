@@ -165,3 +165,33 @@ def periodic_quad_mesh(K1D, N, eps=0.05, rotate_seed=None, warp="diag"):
                 etoe[k, f] = kn
                 etof[k, f] = fn | (int(fwd != fwd_n) << 2)
     return QuadMesh(N=N, K1D=K1D, eps=eps, x=x, y=y, etoe=etoe, etof=etof, rot=rot)
+
+
+def periodic_cover(mesh, m):
+    """The ``m x m`` periodic cover of a periodic mesh: ``m^2`` copies of
+    ``mesh`` side by side, joined into one torus of ``(m K1D)^2`` elements.
+
+    Every copy keeps the base mesh's node coordinates unchanged (faces match
+    modulo the unit period, as on the base torus's own wrap-around faces),
+    its local frames and face flips.  Element ``k = I + (m K1D) J`` is a copy
+    of base element ``base[k] = (I mod K1D) + K1D (J mod K1D)``; its neighbour
+    across face f is the element displaced from (I, J) as the base neighbour
+    is displaced from the base element.  A state that repeats the base state
+    on every copy therefore evolves as the base state does, copy by copy.
+    Returns ``(cover, base)``.  Needs ``mesh.K1D >= 3`` (so that neighbour
+    displacements are unambiguous)."""
+    K1D = int(mesh.K1D)
+    m = int(m)
+    if K1D < 3 or m < 1:
+        raise ValueError("periodic_cover needs K1D >= 3 and m >= 1")
+    C1D = m * K1D
+    k = np.arange(C1D * C1D, dtype=np.int64)
+    I, J = k % C1D, k // C1D
+    base = (I % K1D) + K1D * (J % K1D)
+    kb_n = mesh.etoe.astype(np.int64)                   # [Kb][4]
+    di = (kb_n % K1D - (np.arange(mesh.K) % K1D)[:, None] + 1) % K1D - 1
+    dj = (kb_n // K1D - (np.arange(mesh.K) // K1D)[:, None] + 1) % K1D - 1
+    etoe = ((I[:, None] + di[base]) % C1D + C1D * ((J[:, None] + dj[base]) % C1D))
+    cover = QuadMesh(N=mesh.N, K1D=C1D, eps=mesh.eps, x=mesh.x[base], y=mesh.y[base],
+                     etoe=etoe.astype(np.int32), etof=mesh.etof[base], rot=mesh.rot[base])
+    return cover, base
