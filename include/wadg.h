@@ -291,7 +291,8 @@ int wadg_batch_release_graph(wadg_batch b);
  *   out[s][1] = 0).
  *   A, B  device, S slices in the tiled state layout;  out: host [S][4].
  * Synchronises `stream`.  Deterministic: fixed reduction order.  Returns
- * WADG_E_NONFINITE (after filling out) if some A entry is not finite. */
+ * WADG_E_NONFINITE (after filling out) if some A entry is not finite, and
+ * WADG_E_INVALID for S >= 2^25 (64 partial sums per slice in one launch). */
 int wadg_norms(wadg_ctx ctx, const double* A, const double* B, int32_t S, double* out,
                void* stream);
 

@@ -432,6 +432,8 @@ int wadg_norms(wadg_ctx ctx, const double* A, const double* B, int32_t S, double
   int st = check_slices(ctx, S);
   if (st) return st;
   if (!A || !out) return fail(WADG_E_INVALID, "A and out must not be NULL");
+  if ((int64_t)S * kNormBlocks > INT32_MAX)
+    return fail(WADG_E_INVALID, "too many slices for one reduction (S * 64 must stay below 2^31)");
   DeviceGuard guard(ctx->device);
   if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select the context's device");
   hipStream_t hs = static_cast<hipStream_t>(stream);

@@ -25,7 +25,9 @@ __device__ inline void wave_reduce(double& sdd, double& sbb, double& mx, double&
 __global__ __launch_bounds__(kNormThreads) void norms_partial_kernel(
     const double* __restrict__ A, const double* __restrict__ B, int64_t n, int tile, int K,
     int nblk, double* __restrict__ partials) {
-  const int s = blockIdx.y, blk = blockIdx.x, tid = threadIdx.x;
+  // one block per (slice, partial): slice-major, so the grid's one
+  // dimension holds any slice count up to 2^31 / nblk
+  const int s = blockIdx.x / nblk, blk = blockIdx.x - s * nblk, tid = threadIdx.x;
   const double* a = A + (size_t)s * n;
   const double* b = B ? B + (size_t)s * n : nullptr;
   double sdd = 0.0, sbb = 0.0, mx = 0.0, bad = 0.0;
@@ -79,7 +81,8 @@ int launch_norms_final(const double* partials, int nblk, int32_t S, double* out,
 int launch_norms(const double* A, const double* B, int32_t S, int64_t n_per_slice, int32_t tile,
                  int32_t K, double* partials, int nblk, double* out, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
-  hipLaunchKernelGGL(norms_partial_kernel, dim3(nblk, S), dim3(kNormThreads), 0, st, A, B,
+  if (nblk < 1 || S < 1 || (int64_t)nblk * S > INT32_MAX) return (int)hipErrorInvalidValue;
+  hipLaunchKernelGGL(norms_partial_kernel, dim3(nblk * S), dim3(kNormThreads), 0, st, A, B,
                      n_per_slice, tile, K, nblk, partials);
   int e = (int)hipGetLastError();
   if (e) return e;

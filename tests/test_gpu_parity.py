@@ -234,6 +234,25 @@ def test_norms_and_nonfinite_detection(W):
     assert out[5, 3] == 0.0 and np.all(out[np.arange(prob.S) != 5, 3] == 1.0)
 
 
+
+def test_norms_over_more_slices_than_a_grid_row(W):
+    """70,000 slices of a 16-element mesh (more than the 65,535 blocks of
+    one grid row in y or z) against NumPy; S >= 2^25 is refused up front."""
+    _print_case(test="norms-many-slices", S=70000)
+    mesh = periodic_quad_mesh(4, 1, eps=0.05)
+    sol = W.Solver(mesh)
+    S = 70000
+    Q = np.random.default_rng(9).standard_normal((S, 3, mesh.Np, mesh.K))
+    A = sol.upload(Q)
+    out = sol.norms(A, None, S)
+    flat = Q.reshape(S, -1)
+    np.testing.assert_allclose(out[:, 0], np.linalg.norm(flat, axis=1), rtol=1e-13, atol=0)
+    assert np.all(out[:, 2] == np.abs(flat).max(axis=1)) and np.all(out[:, 3] == 1.0)
+    with pytest.raises(W.WadgError) as e:
+        sol.norms(A, None, 2 ** 25)
+    assert e.value.status == W.binding.WADG_E_INVALID
+
+
 def _sampled_full_size(W, name, sample):
     prob = make_problem(name)
     sol = W.Solver.from_problem(prob)
