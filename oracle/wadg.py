@@ -221,6 +221,23 @@ class WADGOracle:
             tot += np.sum(ref.W[None] * J * d * d)
         return np.sqrt(tot)
 
+    def l2_norm(self, Q, nq=None):
+        """L2 norm over the mesh of a discrete state [3][Np][K] (p, u, v
+        together): the square root of the integral of p^2 + u^2 + v^2 over
+        every element, with the element map's Jacobian, by an nq-point tensor
+        Gauss rule (default: the volume rule nq1).  The norm of the L2 errors
+        of Section 4.2, applied to a difference of two discrete states."""
+        ref = self.ref if nq is None or nq == self.nq1 else ReferenceQuad(self.N, nq)
+        Qm = self.to_modal(np.asarray(Q, dtype=np.float64))
+        xr, xs = self.cx @ ref.Vr.T, self.cx @ ref.Vs.T
+        yr, ys = self.cy @ ref.Vr.T, self.cy @ ref.Vs.T
+        J = xr * ys - xs * yr
+        tot = 0.0
+        for f in range(3):
+            d = Qm[f] @ ref.V.T
+            tot += np.sum(ref.W[None] * J * d * d)
+        return np.sqrt(tot)
+
     def assemble(self, mass="wadg"):
         """Dense matrix of Q -> dQ/dt in nodal coordinates (small meshes only)."""
         n = 3 * self.Np * self.K

@@ -289,3 +289,45 @@ def test_periodic_cover_evolves_copy_by_copy():
     rx, rb = oc.rhs(Qx), ob.rhs(Q0)
     assert not np.allclose(rx[..., 0], rb[..., 0])
     np.testing.assert_allclose(rx[..., 4], rb[..., 0], rtol=0, atol=1e-12 * np.max(np.abs(rb)))
+
+
+# -- Section 4.2: the L2 norm with the element maps' Jacobians ---------------
+
+def test_l2_norm_of_constant_fields_is_the_area():
+    """A constant field c on one component: ||Q||^2 = c^2 x area of the unit
+    torus, whatever the curved element maps (the rule integrates J exactly)."""
+    for N, warp, rot in ((2, "skew", 2), (3, "diag", None), (4, "skew", 5)):
+        mesh = periodic_quad_mesh(5, N, eps=0.05, warp=warp, rotate_seed=rot)
+        o = WADGOracle(mesh)
+        for f, c in ((0, 1.0), (2, -3.0)):
+            Q = np.zeros((3, mesh.Np, mesh.K))
+            Q[f] = c
+            assert abs(o.l2_norm(Q) - abs(c)) < 1e-13
+            assert abs(o.l2_norm(Q, nq=N + 4) - abs(c)) < 1e-13
+
+
+def test_l2_norm_of_smooth_field_converges_to_the_integral():
+    """p = sin(2 pi x) at the nodes: ||p||^2 -> 1/2 (its integral over the
+    unit torus) at the interpolation order as the curved mesh is refined."""
+    errs = []
+    for K1D in (8, 16):
+        mesh = periodic_quad_mesh(K1D, 3, eps=0.05, warp="skew")
+        o = WADGOracle(mesh)
+        Q = np.zeros((3, mesh.Np, mesh.K))
+        Q[0] = np.sin(2 * np.pi * mesh.x).T
+        errs.append(abs(o.l2_norm(Q) ** 2 - 0.5))
+    assert errs[1] < 1e-6 and errs[0] / errs[1] > 16
+
+
+def test_l2_norm_is_the_curvilinear_mass_norm():
+    """With the volume rule, ||Q||^2 = sum_f q_f^T M_J q_f (the exact
+    curvilinear DG mass matrix, modal coefficients), and with an nq-point
+    rule it is l2_error against the zero solution."""
+    mesh = periodic_quad_mesh(4, 3, eps=0.05, warp="skew", rotate_seed=4)
+    o = WADGOracle(mesh, c2=c2_layered)
+    Q = _random_state(mesh, 12)
+    Qm = o.to_modal(Q)
+    want = sum(np.einsum("ki,kij,kj->", Qm[f], o.M_J, Qm[f]) for f in range(3))
+    assert abs(o.l2_norm(Q) ** 2 - want) <= 1e-13 * want
+    zero = lambda x, y, t: np.zeros((3,) + x.shape)
+    assert abs(o.l2_norm(Q, nq=7) - o.l2_error(Q, zero, 0.0, nq_err=7)) <= 1e-14 * o.l2_norm(Q)
