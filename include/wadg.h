@@ -296,6 +296,21 @@ int wadg_batch_release_graph(wadg_batch b);
 int wadg_norms(wadg_ctx ctx, const double* A, const double* B, int32_t S, double* out,
                void* stream);
 
+/* L2 norms with the element maps' Jacobians (the norm of Section 4.2's L2
+ * errors), per slice:
+ *   out[s][0] = ||A_s - B_s||_{L2},  out[s][1] = ||B_s||_{L2},
+ * the square root of the integral over the mesh of p^2 + u^2 + v^2 of the
+ * difference (of B), by the context's volume rule (nq1 x nq1 Gauss points
+ * per element, each field interpolated there from its nodes, weighted by
+ * w_q J_q).  B may be NULL (treated as zero: out[s][1] = 0).
+ *   A, B  device, S slices in the tiled state layout;  out: host [S][2].
+ * Synchronises `stream`.  Deterministic: fixed reduction order.  The context
+ * keeps 16 (S ceil(K/64) + S) bytes of device scratch, grown on demand
+ * (draining `stream` first).  Returns WADG_E_NONFINITE (after filling out)
+ * if a norm is not finite. */
+int wadg_l2_norms(wadg_ctx ctx, const double* A, const double* B, int32_t S, double* out,
+                  void* stream);
+
 /* Tuning: the order in which (slice, 64-element group) work items are
  * launched.  Items are grouped in tiles of groups_per_tile element groups x
  * slices_per_tile slices (0: all slices), slice-major inside a tile; each

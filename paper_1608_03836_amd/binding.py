@@ -83,6 +83,7 @@ def _load():
                                          ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_double), vp]),
         "wadg_norms": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, _c_double_p, vp]),
+        "wadg_l2_norms": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, _c_double_p, vp]),
         "wadg_set_schedule": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32]),
         "wadg_set_kernel": (ctypes.c_int, [vp, ctypes.c_int32]),
         "wadg_set_c2_scale": (ctypes.c_int, [vp, ctypes.c_double]),
@@ -120,7 +121,7 @@ EXPORTED = ("wadg_quadrature_points", "wadg_geometry", "wadg_create", "wadg_dest
             "wadg_state_doubles", "wadg_workspace_bytes", "wadg_rhs", "wadg_integrate",
             "wadg_workspace_bytes_fp32", "wadg_integrate_fp32",
             "wadg_parareal_workspace_bytes", "wadg_parareal",
-            "wadg_norms", "wadg_set_schedule", "wadg_set_kernel", "wadg_kernel_in_use",
+            "wadg_norms", "wadg_l2_norms", "wadg_set_schedule", "wadg_set_kernel", "wadg_kernel_in_use",
             "wadg_set_c2_scale", "wadg_adjoint_workspace_bytes", "wadg_forward_checkpoints",
             "wadg_adjoint", "wadg_batch_create", "wadg_batch_destroy", "wadg_batch_layout",
             "wadg_batch_workspace_bytes", "wadg_batch_integrate", "wadg_batch_set_schedule",
@@ -282,6 +283,16 @@ def wadg_norms(ctx, A, B, S, stream=None, check_finite=True):
     out = np.empty((int(S), 4))
     st = LIB.wadg_norms(ctx, _ptr(A), _ptr(B), int(S), out.ctypes.data_as(_c_double_p),
                         _stream(stream))
+    if st == WADG_E_NONFINITE and not check_finite:
+        return out
+    _check(st)
+    return out
+
+
+def wadg_l2_norms(ctx, A, B, S, stream=None, check_finite=True):
+    out = np.empty((int(S), 2))
+    st = LIB.wadg_l2_norms(ctx, _ptr(A), _ptr(B), int(S), out.ctypes.data_as(_c_double_p),
+                           _stream(stream))
     if st == WADG_E_NONFINITE and not check_finite:
         return out
     _check(st)

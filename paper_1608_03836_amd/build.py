@@ -17,7 +17,7 @@ DEMO = os.path.join(PKG, "abi_demo")
 
 SOURCES = ["reference.cpp", "stage_kernel.hip", "resident_kernel.hip", "split_kernel.hip",
            "adjoint_kernel.hip",
-           "norms_kernel.hip", "convert_kernel.hip", "parareal_kernel.hip", "launch.hip",
+           "norms_kernel.hip", "l2_kernel.hip", "convert_kernel.hip", "parareal_kernel.hip", "launch.hip",
            "api.hip", "api_adjoint.hip", "api_batch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -74,6 +74,7 @@ void free_ctx(wadg_ctx c) {
   if (c->d_nbr) (void)hipFree(c->d_nbr);
   if (c->d_partials) (void)hipFree(c->d_partials);
   if (c->d_out) (void)hipFree(c->d_out);
+  if (c->d_l2) (void)hipFree(c->d_l2);
   for (hipEvent_t e : {c->ev_in, c->ev_rec[0], c->ev_rec[1], c->ev_rev[0], c->ev_rev[1]})
     if (e) (void)hipEventDestroy(e);
   if (c->aux) (void)hipStreamDestroy(c->aux);
@@ -465,6 +466,40 @@ int wadg_norms(wadg_ctx ctx, const double* A, const double* B, int32_t S, double
     out[4 * s + 3] = out[4 * s + 3] != 0.0 ? 0.0 : 1.0;
   }
   if (!all_finite) return fail(WADG_E_NONFINITE, "non-finite entries in A");
+  return WADG_OK;
+}
+
+int wadg_l2_norms(wadg_ctx ctx, const double* A, const double* B, int32_t S, double* out,
+                  void* stream) {
+  int st = check_slices(ctx, S);
+  if (st) return st;
+  if (!A || !out) return fail(WADG_E_INVALID, "A and out must not be NULL");
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select the context's device");
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  const int32_t nEG = ctx->groups();
+  const size_t need = ((size_t)S * nEG + S) * 2;
+  if (need > ctx->l2_cap) {
+    // grown like the norms scratch: the stream is drained first
+    WADG_HIP(hipStreamSynchronize(hs));
+    if (ctx->d_l2) (void)hipFree(ctx->d_l2);
+    ctx->d_l2 = nullptr;
+    ctx->l2_cap = 0;
+    WADG_HIP(hipMalloc(&ctx->d_l2, need * sizeof(double)));
+    ctx->l2_cap = need;
+  }
+  double* dout = ctx->d_l2 + (size_t)S * nEG * 2;
+  int e = wadg::launch_l2_norms(ctx->N, ctx->nq1, A, B, ctx->d_vol, S, nEG, ctx->K, ctx->d_l2,
+                                dout, stream);
+  if (e) return hip_fail((hipError_t)e, "L2 norms kernel launch");
+  WADG_HIP(hipMemcpyAsync(out, dout, (size_t)S * 2 * sizeof(double), hipMemcpyDeviceToHost, hs));
+  WADG_HIP(hipStreamSynchronize(hs));
+  bool finite = true;
+  for (int s = 0; s < 2 * S; ++s) {
+    out[s] = std::sqrt(out[s]);
+    if (!std::isfinite(out[s])) finite = false;
+  }
+  if (!finite) return fail(WADG_E_NONFINITE, "an L2 norm is not finite");
   return WADG_OK;
 }
 

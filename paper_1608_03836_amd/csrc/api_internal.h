@@ -28,6 +28,8 @@ struct wadg_ctx_s {
   double* d_partials = nullptr;  // norms scratch, grown on demand
   double* d_out = nullptr;
   int32_t norms_cap = 0;
+  double* d_l2 = nullptr;        // L2-norm scratch (partials and sums), grown on demand
+  size_t l2_cap = 0;             // its size in doubles
   // adjoint: a second stream (default priority) for the forward recompute
   // that overlaps the reverse sweep, and the events that order the two
   hipStream_t aux = nullptr;

@@ -166,6 +166,13 @@ int launch_batch_split(int N, int nq, const BatchParams& p, void* stream);
 int launch_norms(const double* A, const double* B, int32_t S, int64_t n_per_slice, int32_t tile,
                  int32_t K, double* partials, int nblk, double* out, void* stream);
 
+// Per-slice L2 norms with the Jacobian (l2_kernel.hip): item partials into
+// `partials` [S * nEG][2], then per slice out[s] = (||A_s - B_s||^2,
+// ||B_s||^2) [S][2] (squares); B may be NULL.
+int launch_l2_norms(int N, int nq, const double* A, const double* B, const double* vol,
+                    int32_t S, int32_t nEG, int32_t K, double* partials, double* out,
+                    void* stream);
+
 // Second pass of a per-slice reduction: partials [S][nblk][4] -> out [S][4].
 int launch_norms_final(const double* partials, int nblk, int32_t S, double* out, void* stream);
 

@@ -110,6 +110,10 @@ class Solver:
     def norms(self, A, Bt=None, S=1, stream=None, check_finite=True):
         return B.wadg_norms(self.ctx, A, Bt, S, stream, check_finite=check_finite)
 
+    def l2_norms(self, A, Bt=None, S=1, stream=None, check_finite=True):
+        """Per slice (||A - Bt||_L2, ||Bt||_L2) with the element Jacobians."""
+        return B.wadg_l2_norms(self.ctx, A, Bt, S, stream, check_finite=check_finite)
+
     def set_schedule(self, groups_per_tile, slices_per_tile=0):
         B.wadg_set_schedule(self.ctx, groups_per_tile, slices_per_tile)
 

@@ -73,6 +73,7 @@ def M():
     o = WADGOracle(base, nq1=NQ1, c2=c2_layered)
     m.or_rhs = o.rhs(m.Q0)
     m.or_int = o.integrate(m.Q0, DT, NSTEPS)
+    m.oracle = o
     m.dev = dev
     yield m
     m.big.close()
@@ -161,6 +162,13 @@ def test_max_size_sweep_and_norms(M):
     assert np.all(nd[:, 0] <= TOL * nd[:, 1]), nd[:, 0] / nd[:, 1]
     np.testing.assert_allclose(nd[:, 1], COPIES * np.linalg.norm(M.or_int.reshape(S, -1), axis=1),
                                rtol=TOL, atol=0)
+    _say("L2 norms")
+    nl = M.big.l2_norms(Qb, want, S)
+    o_l2 = np.array([M.oracle.l2_norm(M.or_int[s]) for s in range(S)])
+    np.testing.assert_allclose(nl[:, 1], COPIES * o_l2, rtol=TOL, atol=0)
+    assert np.all(nl[:, 0] <= TOL * nl[:, 1]), nl[:, 0] / nl[:, 1]
+    np.testing.assert_allclose(M.big.l2_norms(Qb, None, S)[:, 0],
+                               COPIES * M.small.l2_norms(qs, None, S)[:, 0], rtol=TOL, atol=0)
     del Qb, want
 
 

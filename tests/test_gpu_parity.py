@@ -253,6 +253,35 @@ def test_norms_over_more_slices_than_a_grid_row(W):
     assert e.value.status == W.binding.WADG_E_INVALID
 
 
+
+@pytest.mark.parametrize("N,dq,K1D,rot", [(1, 1, 9, 3), (2, 2, 9, None), (3, 2, 9, 5),
+                                          (3, 1, 5, 2), (4, 3, 5, 4)])
+def test_l2_norms_match_oracle(W, N, dq, K1D, rot):
+    """Per-slice L2 norms with the element Jacobians (Section 4.2's L2
+    errors) against the oracle's quadrature norm, with and without B; NaN in
+    the padding lanes of the last element group is ignored."""
+    _print_case(test="l2-norms", N=N, dq=dq, K1D=K1D)
+    mesh = periodic_quad_mesh(K1D, N, eps=0.05, warp="skew", rotate_seed=rot)
+    nq1 = N + dq
+    sol = W.Solver(mesh, nq1=nq1, c2=c2_layered)
+    o = WADGOracle(mesh, nq1=nq1, c2=c2_layered)
+    S = 3
+    A, Bs = _random_states(mesh, S, 31), _random_states(mesh, S, 32)
+    tA, tB = sol.upload(A), sol.upload(Bs)
+    G = (mesh.K + 63) // 64
+    pad = G * 64 - mesh.K
+    assert pad > 0
+    for t in (tA, tB):
+        t.view(S, G, 3, mesh.Np, 64)[:, G - 1, :, :, 64 - pad:] = float("nan")
+    out = sol.l2_norms(tA, tB, S)
+    out0 = sol.l2_norms(tA, None, S)
+    assert np.all(out0[:, 1] == 0.0)
+    for s in range(S):
+        for got, want in ((out[s, 0], o.l2_norm(A[s] - Bs[s])), (out[s, 1], o.l2_norm(Bs[s])),
+                          (out0[s, 0], o.l2_norm(A[s]))):
+            assert abs(got - want) <= TOL * want, (s, got, want)
+
+
 def _sampled_full_size(W, name, sample):
     prob = make_problem(name)
     sol = W.Solver.from_problem(prob)
