@@ -238,9 +238,13 @@ int wadg_adjoint(wadg_ctx ctx, const double* chk, const double* seed, double* gr
  * batching of elements per workgroup, taken across problems.
  *
  * wadg_batch_create: meshes[nprob] (host; all with the same N, nq1, tau_p,
- *   tau_u; validated like wadg_create), S[nprob] slices per problem.  A mesh
- *   of K <= 32 elements is stored as P = floor(64 / K) disjoint copies in
- *   one 64-lane group, so that P slices share one work item.  Returns
+ *   tau_u; validated like wadg_create), S[nprob] slices per problem.  A
+ *   problem's slices are stored P at a time side by side, as P disjoint
+ *   copies of its mesh (a virtual mesh of P K elements), so that small or
+ *   ragged meshes fill the 64 lanes of their element groups.  P in
+ *   [1, min(S, 64)] is chosen per problem to move the fewest bytes per stage
+ *   (state tiles per work item plus geometry per virtual element group;
+ *   ties: the smaller P), with a virtual slice under 2 GiB.  Returns
  *   WADG_E_GEOMETRY / WADG_E_INVALID naming the offending problem.
  * wadg_batch_layout: offset[nprob + 1] (host out, int64) -- problem i
  *   occupies doubles [offset[i], offset[i+1]) of the batch state;

@@ -147,6 +147,38 @@ int batch_sweep(wadg_batch b, double* Q, double* work, int32_t nsteps, void* str
 
 extern "C" {
 
+namespace {
+
+// Copies of a K-element mesh per virtual slice (its S slices side by side in
+// a virtual mesh of P K elements, ceil(S / P) virtual slices): the P in
+// [1, min(S, 64)] that moves the fewest bytes per stage, counting each work
+// item's state tiles (Q and the residual, read and written) and each
+// virtual element group's geometry once (a problem's items share it through
+// the cache); the smallest such P.  At P = 64 the copies fill whole groups,
+// so a larger P gains nothing; nor may a virtual slice outgrow the 2 GiB a
+// slice may take.
+int pack_copies(int K, int S, int Np, int nq) {
+  const double state_item = 4.0 * 3 * Np * wadg::kWave * sizeof(double);
+  const double geo_group = ((6.0 * nq * nq + 12.0 * nq) * sizeof(double) + 8 * sizeof(int32_t)) *
+                           wadg::kWave;
+  int best = 1;
+  double best_bytes = -1.0;
+  for (int P = 1; P <= std::min(S, wadg::kWave); ++P) {
+    const int64_t g = ((int64_t)P * K + wadg::kWave - 1) / wadg::kWave;
+    if (P > 1 && g * 3 * Np * wadg::kWave * (int64_t)sizeof(double) >= (1LL << 31)) break;
+    const double groups = (double)g;
+    const double items = (double)((S + P - 1) / P) * groups;
+    const double bytes = items * state_item + groups * geo_group;
+    if (best_bytes < 0.0 || bytes < best_bytes) {
+      best_bytes = bytes;
+      best = P;
+    }
+  }
+  return best;
+}
+
+}  // namespace
+
 int wadg_batch_create(const wadg_mesh* meshes, int32_t nprob, const int32_t* S, int32_t device,
                       wadg_batch* out) {
   if (!out) return fail(WADG_E_INVALID, "out is NULL");
@@ -184,8 +216,7 @@ int wadg_batch_create(const wadg_mesh* meshes, int32_t nprob, const int32_t* S, 
       free_batch(b);
       return fail(WADG_E_INVALID, "S[" + std::to_string(i) + "] must be >= 1");
     }
-    // meshes of at most half a lane group carry several slices side by side
-    const int P = m.K <= wadg::kWave / 2 ? wadg::kWave / m.K : 1;
+    const int P = pack_copies(m.K, S[i], Np, nq);
     const int Kv = P * m.K;
     std::vector<double> x((size_t)Kv * Np), y((size_t)Kv * Np), c2;
     std::vector<int32_t> etoe((size_t)Kv * 4), etof((size_t)Kv * 4);

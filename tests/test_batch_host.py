@@ -12,7 +12,7 @@ W = pytest.importorskip("paper_1608_03836_amd.binding",
 
 
 @pytest.mark.parametrize("S,K,P", [(1, 4, 16), (7, 9, 7), (34, 4, 16), (5, 36, 1), (3, 81, 1),
-                                   (16, 16, 4)])
+                                   (16, 16, 4), (109, 36, 7), (114, 225, 3), (40, 81, 13)])
 def test_pack_round_trip(S, K, P):
     rng = np.random.default_rng(S * 100 + K)
     Q = rng.standard_normal((S, 3, 16, K))

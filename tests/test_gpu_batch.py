@@ -15,8 +15,10 @@ from oracle import WADGOracle
 
 pytestmark = pytest.mark.gpu
 
-# packed meshes (4, 16, 25 elements), one group (36, 49) and several (121,
-# 144, 169, 196, 225) -- indices into the 1000-problem batch
+# indices into the 1000-problem batch: meshes of 4, 16 and 25 elements packed
+# into one lane group per virtual slice, of 36, 49, 144, 169, 196 and 225
+# packed over several groups, and one of 121 elements unpacked (several
+# groups, one slice each)
 MEMBERS = [3, 5, 2, 0, 1, 4, 6, 8, 10, 11, 12]
 
 
@@ -45,6 +47,10 @@ def test_members_cover_packed_and_multi_group(small):
     Ks = sorted(p.mesh.K for p in probs)
     assert Ks[0] <= 16 and Ks[-1] > 128
     assert max(batch.pack) > 1 and min(batch.pack) == 1
+    Ps = [(p.mesh.K, P) for p, P in zip(probs, batch.pack)]
+    assert any(P > 1 and P * K <= 64 for K, P in Ps)
+    assert any(P > 1 and P * K > 64 for K, P in Ps)
+    assert any(P == 1 and K > 64 for K, P in Ps)
 
 
 def test_batch_equals_single_problem_path(W, small):
