@@ -125,9 +125,11 @@ int wadg_quadrature_points(const wadg_mesh* mesh, double* xq, double* yq);
 int wadg_geometry(const wadg_mesh* mesh, double* vol, double* face);
 
 /* Build a context on HIP device `device` (-1: the current device): validates
- * the mesh, builds reference operators and geometry on the host and copies
- * them to library-owned device memory.  On success *out holds the context;
- * on failure *out is NULL. */
+ * the mesh, builds reference operators and geometry on the host (on up to
+ * 16 threads, directly in the tiled device layout) and copies them to
+ * library-owned device memory, where an FP32 copy of the geometry is rounded
+ * for the FP32-bulk path (on the null stream, awaited before returning).
+ * On success *out holds the context; on failure *out is NULL. */
 int wadg_create(const wadg_mesh* mesh, int32_t device, wadg_ctx* out);
 
 /* Release the context and its device memory.  NULL is accepted. */

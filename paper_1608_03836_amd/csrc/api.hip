@@ -159,7 +159,7 @@ int wadg_create(const wadg_mesh* mesh, int32_t device, wadg_ctx* out) {
       (e = (hipError_t)wadg::launch_to_fp32(c->d_vol, c->d_vol32, nv, nullptr)) != hipSuccess ||
       (e = (hipError_t)wadg::launch_to_fp32(c->d_face, c->d_face32, nf, nullptr)) !=
           hipSuccess ||
-      (e = hipDeviceSynchronize()) != hipSuccess) {
+      (e = hipStreamSynchronize(nullptr)) != hipSuccess) {
     free_ctx(c);
     return hip_fail(e, "wadg_create device setup");
   }
