@@ -221,9 +221,11 @@ int wadg_set_c2_scale(wadg_ctx ctx, double scale);
  *   skew p-u coupling and symmetric penalty blocks; Mtilde^{-1} is the
  *   symmetric WADG inverse of Section 4), recomputing each slice's forward
  *   stage residuals from its checkpoint (held for one slice at a time,
- *   double-buffered: the workspace is about 10 nsteps + 6 slices).  The
- *   recompute runs on a second stream owned by the context, ordered against
- *   `stream` with events; the context must not be used from two threads at
+ *   double-buffered: the workspace is about 10 nsteps + 6 slices).  With
+ *   the split kernel (WADG_KERNEL_AUTO or _SPLIT) the recompute of the next
+ *   slice shares each reverse-stage launch on `stream`; with the streamed
+ *   kernel it runs on a second stream owned by the context, ordered against
+ *   `stream` with events.  The context must not be used from two threads at
  *   once.  Padding entries of seed must be zero; grad padding is
  *   unspecified.  Synchronises `stream` once at the end.  Returns
  *   WADG_E_NONFINITE if dJ_dscale is not finite.  work must not overlap

@@ -139,20 +139,28 @@ int wadg_adjoint(wadg_ctx ctx, const double* chk, const double* seed, double* gr
 
   wadg::StageParams p = base_params(ctx, 1);
   p.dt = dt;
-  // The forward recompute of slice s-1 (on the context's second stream)
-  // runs while the reverse sweep of slice s (on `stream`) reads the other
-  // residual set: ev_rec[b] = residual set b is ready, ev_rev[b] = the
-  // reverse sweep that read set b is done.
-  if (!ctx->aux) {
-    WADG_HIP(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
-    for (hipEvent_t* e : {&ctx->ev_in, &ctx->ev_rec[0], &ctx->ev_rec[1], &ctx->ev_rev[0],
-                          &ctx->ev_rev[1]})
-      WADG_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
-  }
-  hipStream_t aux = ctx->aux;
-  WADG_HIP(hipEventRecord(ctx->ev_in, hs));          // chk and seed are written
-  WADG_HIP(hipStreamWaitEvent(aux, ctx->ev_in, 0));
   double* const Rs[2] = {R, R + 5 * (size_t)nsteps * n1};
+  // Each slice's residuals are recomputed from its checkpoint (into the
+  // residual set of its parity) before its reverse stages read them.  With
+  // the split kernel for both, the recompute of slice s-1 rides along in the
+  // launches of slice s's reverse stages, one stage each (launch_stage_pair:
+  // the two one-slice launches share the CUs), on `stream` alone.  Otherwise
+  // it runs on the context's second stream while the reverse sweep of slice
+  // s runs on `stream`: ev_rec[b] = residual set b is ready, ev_rev[b] = the
+  // reverse sweep that read set b is done.
+  const bool paired = fused && kernel_path(ctx, false, wadg::kStage) == WADG_KERNEL_SPLIT;
+  hipStream_t aux = nullptr;
+  if (!paired) {
+    if (!ctx->aux) {
+      WADG_HIP(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+      for (hipEvent_t* e : {&ctx->ev_in, &ctx->ev_rec[0], &ctx->ev_rec[1], &ctx->ev_rev[0],
+                            &ctx->ev_rev[1]})
+        WADG_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+    }
+    aux = ctx->aux;
+    WADG_HIP(hipEventRecord(ctx->ev_in, hs));          // chk and seed are written
+    WADG_HIP(hipStreamWaitEvent(aux, ctx->ev_in, 0));
+  }
   auto recompute = [&](int s) -> int {
     const int b = s % 2;
     if (s + 2 <= S - 1) WADG_HIP(hipStreamWaitEvent(aux, ctx->ev_rev[b], 0));
@@ -161,12 +169,17 @@ int wadg_adjoint(wadg_ctx ctx, const double* chk, const double* seed, double* gr
     WADG_HIP(hipEventRecord(ctx->ev_rec[b], aux));
     return WADG_OK;
   };
-  int st = recompute(S - 1);
+  int st = paired ? adjoint_recompute(ctx, chk + (S - 1) * n1, Rs[(S - 1) % 2], T, dt, nsteps, hs)
+                  : recompute(S - 1);
   if (st) return st;
   for (int s = S - 1; s >= 0; --s) {
-    if (s >= 1 && (st = recompute(s - 1))) return st;
+    if (!paired && s >= 1 && (st = recompute(s - 1))) return st;
     const double* Rs_ = Rs[s % 2];
-    WADG_HIP(hipStreamWaitEvent(hs, ctx->ev_rec[s % 2], 0));
+    if (!paired) WADG_HIP(hipStreamWaitEvent(hs, ctx->ev_rec[s % 2], 0));
+    // paired: the recompute of slice s-1 (stage t of it with reverse stage t
+    // of slice s), as adjoint_recompute does it
+    double* const Rn = Rs[(s + 1) % 2];
+    const double* cur = s >= 1 ? chk + (s - 1) * n1 : nullptr;
     for (int m = nsteps - 1; m >= 0; --m) {
       const double* Rm = Rs_ + 5 * (size_t)m * n1;
       // reverse stages: rbar += B_i ybar; ybar += dt L^T rbar; rbar *= A_i
@@ -183,6 +196,7 @@ int wadg_adjoint(wadg_ctx ctx, const double* chk, const double* seed, double* gr
         q.Qin = zc;
         q.res = yb;
         q.Qout = yb;
+        int mode = wadg::kApplyA;
         if (fused && (m > 0 || i > 0)) {
           // the mass step of the next reverse stage (m2, i2) of this slice
           const int m2 = i > 0 ? m : m - 1, i2 = i > 0 ? i - 1 : 4;
@@ -195,15 +209,27 @@ int wadg_adjoint(wadg_ctx ctx, const double* chk, const double* seed, double* gr
           q.adj.a_next = i2 == 4 ? 0.0 : kRkA[i2 + 1];
           q.adj.b = kRkB[i2];
           q.adj.a = kRkA[i2];
-          e = launch_stage(ctx, wadg::kApplyAMass, false, q, stream);
-          std::swap(zc, zn);
-        } else {
-          e = launch_stage(ctx, wadg::kApplyA, false, q, stream);
+          mode = wadg::kApplyAMass;
         }
+        if (paired && s >= 1) {
+          const int t = 5 * (nsteps - 1 - m) + (4 - i), m1 = t / 5, i1 = t % 5;
+          wadg::StageParams r = p;
+          r.Qin = cur;
+          r.Qout = T[t % 2];
+          r.res = Rn + (5 * (size_t)m1 + (i1 == 0 ? 0 : i1 - 1)) * n1;
+          r.res_out = Rn + (5 * (size_t)m1 + i1) * n1;
+          r.rkA = kRkA[i1];
+          r.rkB = kRkB[i1];
+          e = launch_stage_pair(ctx, mode, q, r, stream);
+          cur = T[t % 2];
+        } else {
+          e = launch_stage(ctx, mode, false, q, stream);
+        }
+        if (mode == wadg::kApplyAMass) std::swap(zc, zn);
         if (e) return hip_fail((hipError_t)e, "stage kernel launch (apply A)");
       }
     }
-    WADG_HIP(hipEventRecord(ctx->ev_rev[s % 2], hs));
+    if (!paired) WADG_HIP(hipEventRecord(ctx->ev_rev[s % 2], hs));
   }
   if (grad != yb) WADG_HIP(hipMemcpyAsync(grad, yb, sb, hipMemcpyDeviceToDevice, hs));
   std::vector<double> h(G);

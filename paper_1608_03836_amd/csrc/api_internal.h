@@ -91,6 +91,10 @@ int kernel_path(wadg_ctx c, bool fp32, int mode);
 // Launch one stage of `mode` with the context's kernel choice and the
 // alternating work-item order.
 int launch_stage(wadg_ctx c, int mode, bool fp32, const wadg::StageParams& p0, void* stream);
+// Launch an apply-A stage (mode_a) and an independent LSRK stage in one grid
+// of the split kernel (launch_stage_pair), with the alternating item order.
+int launch_stage_pair(wadg_ctx c, int mode_a, const wadg::StageParams& a0,
+                      const wadg::StageParams& b0, void* stream);
 // Stage parameters of the context for S slices (geometry, schedule, penalties).
 wadg::StageParams base_params(wadg_ctx c, int32_t S);
 

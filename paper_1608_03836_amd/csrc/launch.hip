@@ -58,6 +58,14 @@ int launch_stage(wadg_ctx c, int mode, bool fp32, const wadg::StageParams& p0, v
               : wadg::launch_stage_streamed(c->N, c->nq1, mode, p, stream);
 }
 
+int launch_stage_pair(wadg_ctx c, int mode_a, const wadg::StageParams& a0,
+                      const wadg::StageParams& b0, void* stream) {
+  wadg::StageParams a = a0, b = b0;
+  c->order_flip ^= 1;
+  a.reverse = b.reverse = (int32_t)c->order_flip;
+  return wadg::launch_stage_pair(c->N, c->nq1, mode_a, a, b, stream);
+}
+
 wadg::StageParams base_params(wadg_ctx c, int32_t S) {
   wadg::StageParams p{};
   p.vol = c->d_vol;

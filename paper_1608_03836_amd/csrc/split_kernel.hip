@@ -393,19 +393,20 @@ __device__ __forceinline__ void split_item(const SplitBufs& B, const StageScalar
   }
 }
 
+// Workgroup bid of a launch of nb workgroups: its work item of launch p
+// (slice, element group) in the launch's order, run over the workgroup's
+// LDS arrays (Split<>).
 template <typename R, int N, int NQ, int MODE>
-__global__ __launch_bounds__(4 * kWave) void split_kernel(const StageParams p) {
+__device__ __forceinline__ void split_run(const StageParams& p, int bid, int nb, R* tq, R* xf,
+                                          R* xm) {
   static_assert((MODE != kApplyA && MODE != kApplyAMass) || sizeof(R) == sizeof(double),
                 "apply-A modes are FP64 only");
   using L = Split<R, N, NQ>;
   constexpr int NQ2 = L::NQ2;
   constexpr unsigned tile = L::tile;
   constexpr unsigned KP = kWave * sizeof(R);
-  __shared__ __attribute__((aligned(16))) R tq[tile];
-  __shared__ __attribute__((aligned(16))) R xf[L::xf];
-  __shared__ __attribute__((aligned(16))) R xm[L::xm];
 
-  const int w = item_of(blockIdx.x, gridDim.x, p.reverse);
+  const int w = item_of(bid, nb, p.reverse);
   const int Be = p.tile_groups, Bs = p.tile_slices, nEG = p.nEG;
   const int sb = w / (Bs * nEG);
   const int r = w - sb * Bs * nEG;
@@ -443,6 +444,35 @@ __global__ __launch_bounds__(4 * kWave) void split_kernel(const StageParams p) {
   }
   split_item<R, N, NQ, MODE>(B, stage_scalars<R>(p), eg * kWave + lane < p.K, tq, xf, xm, p.adj,
                              s * nEG + eg);
+}
+
+template <typename R, int N, int NQ, int MODE>
+__global__ __launch_bounds__(4 * kWave) void split_kernel(const StageParams p) {
+  using L = Split<R, N, NQ>;
+  __shared__ __attribute__((aligned(16))) R tq[L::tile];
+  __shared__ __attribute__((aligned(16))) R xf[L::xf];
+  __shared__ __attribute__((aligned(16))) R xm[L::xm];
+  split_run<R, N, NQ, MODE>(p, blockIdx.x, gridDim.x, tq, xf, xm);
+}
+
+// Two independent launches in one grid (FP64): the first na workgroups run
+// the items of launch a in mode MA (an apply-A mode), the others the LSRK
+// stage items of launch b.  The adjoint's reverse sweep pairs each
+// transposed stage of one slice with a recompute stage of the slice before
+// it, so that the two one-slice launches share the CUs (two workgroups per
+// CU) instead of following each other.  Each item computes exactly what it
+// computes in its own launch.
+template <int N, int NQ, int MA>
+__global__ __launch_bounds__(4 * kWave) void split_pair_kernel(const StageParams a,
+                                                               const StageParams b, int na) {
+  using L = Split<double, N, NQ>;
+  __shared__ __attribute__((aligned(16))) double tq[L::tile];
+  __shared__ __attribute__((aligned(16))) double xf[L::xf];
+  __shared__ __attribute__((aligned(16))) double xm[L::xm];
+  if ((int)blockIdx.x < na)
+    split_run<double, N, NQ, MA>(a, blockIdx.x, na, tq, xf, xm);
+  else
+    split_run<double, N, NQ, kStage>(b, blockIdx.x - na, gridDim.x - na, tq, xf, xm);
 }
 
 // Batched LSRK stage (FP64) over a work list of (problem, slice, element
@@ -538,6 +568,31 @@ int launch_r(int N, int nq, int mode, const StageParams& p, void* stream) {
 }
 
 template <int N, int NQ>
+int launch_pair_nq(int mode_a, const StageParams& a, const StageParams& b, void* stream) {
+  const int na = a.nEG * a.S, nb = b.nEG * b.S;
+  const dim3 grid(na + nb), block(4 * kWave);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (mode_a == kApplyAMass)
+    hipLaunchKernelGGL((split_pair_kernel<N, NQ, kApplyAMass>), grid, block, 0, st, a, b, na);
+  else if (mode_a == kApplyA)
+    hipLaunchKernelGGL((split_pair_kernel<N, NQ, kApplyA>), grid, block, 0, st, a, b, na);
+  else
+    return (int)hipErrorInvalidValue;
+  return (int)hipGetLastError();
+}
+
+template <int N>
+int launch_pair_n(int nq, int mode_a, const StageParams& a, const StageParams& b,
+                  void* stream) {
+  switch (nq - N) {
+    case 1: return launch_pair_nq<N, N + 1>(mode_a, a, b, stream);
+    case 2: return launch_pair_nq<N, N + 2>(mode_a, a, b, stream);
+    case 3: return launch_pair_nq<N, N + 3>(mode_a, a, b, stream);
+    default: return (int)hipErrorInvalidValue;
+  }
+}
+
+template <int N, int NQ>
 int launch_batch_nq(const BatchParams& p, void* stream) {
   hipLaunchKernelGGL((batch_split_kernel<N, NQ>), dim3(p.nitems), dim3(4 * kWave), 0,
                      static_cast<hipStream_t>(stream), p);
@@ -563,6 +618,18 @@ int launch_batch_split(int N, int nq, const BatchParams& p, void* stream) {
     case 2: return launch_batch_n<2>(nq, p, stream);
     case 3: return launch_batch_n<3>(nq, p, stream);
     case 4: return launch_batch_n<4>(nq, p, stream);
+    default: return (int)hipErrorInvalidValue;
+  }
+}
+
+int launch_stage_pair(int N, int nq, int mode_a, const StageParams& a, const StageParams& b,
+                      void* stream) {
+  if ((int64_t)a.nEG * a.S + (int64_t)b.nEG * b.S >= (1LL << 31)) return (int)hipErrorInvalidValue;
+  switch (N) {
+    case 1: return launch_pair_n<1>(nq, mode_a, a, b, stream);
+    case 2: return launch_pair_n<2>(nq, mode_a, a, b, stream);
+    case 3: return launch_pair_n<3>(nq, mode_a, a, b, stream);
+    case 4: return launch_pair_n<4>(nq, mode_a, a, b, stream);
     default: return (int)hipErrorInvalidValue;
   }
 }

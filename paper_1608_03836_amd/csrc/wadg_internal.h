@@ -111,6 +111,11 @@ int launch_stage_streamed_fp32(int N, int nq, const StageParams& p, void* stream
 // waves (volume p, volume u/v, faces 0+2, faces 1+3); stage and rhs modes.
 int launch_stage_split(int N, int nq, int mode, const StageParams& p, void* stream);
 int launch_stage_split_fp32(int N, int nq, const StageParams& p, void* stream);
+// Split-work kernel over two independent launches in one grid (FP64): the
+// items of launch a in mode_a (kApplyA or kApplyAMass), then the LSRK stage
+// items of launch b; each item as in its own launch.
+int launch_stage_pair(int N, int nq, int mode_a, const StageParams& a, const StageParams& b,
+                      void* stream);
 // Resident-geometry kernel: one workgroup per (element group, slice range)
 // with the group's geometry held in LDS; grid = nEG * ranges.  Only where
 // resident_supported(N, nq, fp32).
