@@ -51,6 +51,16 @@ def test_members_cover_packed_and_multi_group(small):
     assert any(P > 1 and P * K <= 64 for K, P in Ps)
     assert any(P > 1 and P * K > 64 for K, P in Ps)
     assert any(P == 1 and K > 64 for K, P in Ps)
+    # the documented rule: P in [1, min(S, 64)] moving the fewest bytes per
+    # stage (state tiles per item + geometry per virtual group), smallest P
+    Np, nq = 16, 5
+    state_item = 4 * 3 * Np * 64 * 8
+    geo_group = ((6 * nq * nq + 12 * nq) * 8 + 8 * 4) * 64
+    for p, P in zip(probs, batch.pack):
+        K, S = p.mesh.K, p.S
+        cost = {Q: (-(-S // Q)) * (-(-(Q * K) // 64)) * state_item + (-(-(Q * K) // 64)) * geo_group
+                for Q in range(1, min(S, 64) + 1)}
+        assert P == min(cost, key=lambda Q: (cost[Q], Q)), (K, S, P)
 
 
 def test_batch_equals_single_problem_path(W, small):
