@@ -77,8 +77,9 @@ typedef struct wadg_batch_s* wadg_batch;
  *   N        polynomial degree, 1 <= N <= WADG_MAX_N.
  *   nq1      Gauss points per direction and per face, N+1 <= nq1 <= N+3.
  *            (N+1 points are exact to degree 2N+1 in each variable, the
- *            degree prescribed in Section 4; the default of the workloads
- *            is N+2, see the design notes.)
+ *            degree prescribed in Section 4; the workloads use N+2, so that
+ *            the rule has more points than the basis has nodes, as the
+ *            simplex rules of the paper do.)
  *   K        number of elements, K >= 1.
  *   x, y     [K][(N+1)^2] physical coordinates of each element's GLL nodes;
  *            the element map is their degree-N interpolant (isoparametric).
