@@ -178,6 +178,8 @@ def run_fp32(args):
     d = (Q - Q64).reshape(S, -1)
     rel = float(torch.max(torch.linalg.norm(d, dim=1) /
                           torch.linalg.norm(Q64.reshape(S, -1), dim=1)).item())
+    l2 = sol.l2_norms(Q, Q64, S)        # L2 with the Jacobian, per slice
+    rel_l2 = float(np.max(l2[:, 0] / l2[:, 1]))
     del Q64
     calibrate(args, torch)
     elapsed, ev = timed(args, torch, stream,
@@ -200,6 +202,7 @@ def run_fp32(args):
                                 sum(ev) / (args.steps * 5 * prob.nsteps),
                                 measured_traffic(kname, prob.name))
     line["max_rel_err_vs_fp64_sweep"] = rel
+    line["max_rel_l2_err_vs_fp64_sweep"] = rel_l2
     if args.cpu_baseline_seconds > 0:
         line["cpu_baseline"] = cpu_baseline(prob, args.cpu_baseline_seconds)
     print(json.dumps(line), flush=True)
