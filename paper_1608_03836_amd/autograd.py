@@ -29,14 +29,28 @@ class WadgSweep(torch.autograd.Function):
         (chk,) = ctx.saved_tensors
         solver = ctx.solver
         solver.set_c2_scale(ctx.gamma)
-        grad_y0, d_scale = solver.adjoint(chk, grad_qT.detach(), ctx.S, ctx.dt, ctx.nsteps)
+        # padding lanes of the tiled layout hold no state: their gradient is
+        # dropped (the adjoint requires a seed that is zero there), and the
+        # returned gradient is zero there
+        mask = element_mask(solver)
+        seed = grad_qT.detach().reshape(-1) * mask
+        grad_y0, d_scale = solver.adjoint(chk, seed, ctx.S, ctx.dt, ctx.nsteps)
         grad_gamma = torch.tensor(d_scale / ctx.gamma, dtype=torch.float64,
                                   device=grad_qT.device)
-        return grad_y0, grad_gamma, None, None, None, None
+        return grad_y0 * mask, grad_gamma, None, None, None, None
 
 
 def sweep(solver, y0, gamma, S, dt, nsteps):
     return WadgSweep.apply(y0, gamma, solver, S, dt, nsteps)
+
+
+def element_mask(solver):
+    """1.0 on every entry of real elements in one slice of the tiled layout,
+    0.0 on the padding lanes of the last element group."""
+    G = solver.slice_doubles // (3 * solver.Np * 64)
+    k = torch.arange(G * 64).reshape(G, 1, 1, 64)
+    m = (k < solver.K).to(torch.float64).expand(G, 3, solver.Np, 64)
+    return m.reshape(-1).to(solver.device)
 
 
 def pressure_mask(solver):

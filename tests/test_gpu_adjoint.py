@@ -131,6 +131,34 @@ def test_autograd_function_matches_finite_differences(W):
             assert abs(fd - an) <= 1e-9 * J.item(), (fd, an)
 
 
+
+def test_autograd_drops_the_gradient_of_padding_lanes(W):
+    """On a ragged mesh (81 elements, 47 padding lanes in the last group) a
+    loss that also depends on the output's padding lanes gives the same
+    gradients, bit for bit, as the loss over real elements only: padding
+    holds no state, so its gradient is dropped, and the returned gradient is
+    zero there."""
+    import torch
+    from paper_1608_03836_amd.autograd import sweep, element_mask
+    _print_case(test="adjoint-autograd-padding", workload="adj4-K1D9")
+    prob = make_sensitivity_problem("adj4", K1D=9)
+    sol = _solver(W, prob)
+    assert sol.K % 64 != 0
+    em = element_mask(sol)
+    grads = []
+    for with_padding in (False, True):
+        y0 = sol.upload(prob.y0[None]).requires_grad_(True)
+        gamma = torch.tensor(prob.gamma, dtype=torch.float64, requires_grad=True)
+        qT = sweep(sol, y0, gamma, prob.S, prob.dt, prob.nsteps)
+        J = torch.sum((em * qT) ** 2)
+        if with_padding:
+            J = J + 5.0 * torch.sum((1.0 - em) * qT)
+        J.backward()
+        grads.append((y0.grad.clone(), gamma.grad.clone()))
+    assert torch.equal(grads[0][0], grads[1][0]) and torch.equal(grads[0][1], grads[1][1])
+    assert torch.all(grads[1][0][em == 0] == 0) and torch.any(grads[1][0] != 0)
+
+
 def test_full_size_adjoint_fd_and_transpose(W):
     import torch
     _print_case(test="adjoint-full", workload="adj128")
