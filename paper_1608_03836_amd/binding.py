@@ -185,6 +185,35 @@ def _ptr(a):
     raise TypeError(f"cannot pass {type(a)} as a device pointer")
 
 
+def _dev(a, nbytes, name, f64=True):
+    """Device pointer of `a` for a call that reads or writes nbytes through
+    it.  Tensors must be contiguous device tensors (float64 for states) of at
+    least nbytes; raw integer pointers pass through unchecked, as in C."""
+    if a is not None and not isinstance(a, int) and hasattr(a, "data_ptr"):
+        dev = getattr(a, "device", None)
+        if dev is not None and getattr(dev, "type", "cuda") != "cuda":
+            raise ValueError(f"{name} must be a device tensor (it is on {dev})")
+        if f64 and str(getattr(a, "dtype", "torch.float64")) != "torch.float64":
+            raise ValueError(f"{name} must hold float64 values (it holds {a.dtype})")
+        have = a.numel() * a.element_size()
+        if have < nbytes:
+            raise ValueError(f"{name} holds {have} bytes; this call needs {nbytes}")
+    return _ptr(a)
+
+
+def _need(fn, *args):
+    """A size query for the checks above; 0 when the arguments are invalid
+    (the call itself then reports them)."""
+    try:
+        return fn(*args)
+    except WadgError:
+        return 0
+
+
+def _slice_bytes(ctx):
+    return _need(wadg_state_doubles, ctx) * 8
+
+
 def _stream(stream):
     if stream is None:
         try:
@@ -242,12 +271,14 @@ def wadg_workspace_bytes(ctx, S):
 
 
 def wadg_rhs(ctx, Q, dQdt, S, stream=None):
-    _check(LIB.wadg_rhs(ctx, _ptr(Q), _ptr(dQdt), int(S), _stream(stream)))
+    n = int(S) * _slice_bytes(ctx)
+    _check(LIB.wadg_rhs(ctx, _dev(Q, n, "Q"), _dev(dQdt, n, "dQdt"), int(S), _stream(stream)))
 
 
 def wadg_integrate(ctx, Q, work, S, dt, nsteps, stream=None):
-    _check(LIB.wadg_integrate(ctx, _ptr(Q), _ptr(work), int(S), float(dt), int(nsteps),
-                              _stream(stream)))
+    q = _dev(Q, int(S) * _slice_bytes(ctx), "Q")
+    w = _dev(work, _need(wadg_workspace_bytes, ctx, S), "work", f64=False)
+    _check(LIB.wadg_integrate(ctx, q, w, int(S), float(dt), int(nsteps), _stream(stream)))
 
 
 def wadg_workspace_bytes_fp32(ctx, S):
@@ -257,8 +288,9 @@ def wadg_workspace_bytes_fp32(ctx, S):
 
 
 def wadg_integrate_fp32(ctx, Q, work, S, dt, nsteps, stream=None):
-    _check(LIB.wadg_integrate_fp32(ctx, _ptr(Q), _ptr(work), int(S), float(dt), int(nsteps),
-                                   _stream(stream)))
+    q = _dev(Q, int(S) * _slice_bytes(ctx), "Q")
+    w = _dev(work, _need(wadg_workspace_bytes_fp32, ctx, S), "work", f64=False)
+    _check(LIB.wadg_integrate_fp32(ctx, q, w, int(S), float(dt), int(nsteps), _stream(stream)))
 
 
 def wadg_parareal_workspace_bytes(ctx, S, fine_fp32=False):
@@ -272,7 +304,11 @@ def wadg_parareal(ctx, y0, U, work, S, dt, nsteps_fine, nsteps_coarse, max_iter,
     """Returns (iterations, last relative change)."""
     it = ctypes.c_int32()
     ch = ctypes.c_double()
-    _check(LIB.wadg_parareal(ctx, _ptr(y0), _ptr(U), _ptr(work), int(S), float(dt),
+    n1 = _slice_bytes(ctx)
+    y0 = _dev(y0, n1, "y0")
+    U = _dev(U, (int(S) + 1) * n1, "U")
+    work = _dev(work, _need(wadg_parareal_workspace_bytes, ctx, S, fine_fp32), "work", f64=False)
+    _check(LIB.wadg_parareal(ctx, y0, U, work, int(S), float(dt),
                              int(nsteps_fine), int(nsteps_coarse), int(max_iter), float(tol),
                              int(bool(fine_fp32)), ctypes.byref(it), ctypes.byref(ch),
                              _stream(stream)))
@@ -281,8 +317,9 @@ def wadg_parareal(ctx, y0, U, work, S, dt, nsteps_fine, nsteps_coarse, max_iter,
 
 def wadg_norms(ctx, A, B, S, stream=None, check_finite=True):
     out = np.empty((int(S), 4))
-    st = LIB.wadg_norms(ctx, _ptr(A), _ptr(B), int(S), out.ctypes.data_as(_c_double_p),
-                        _stream(stream))
+    n = int(S) * _slice_bytes(ctx)
+    st = LIB.wadg_norms(ctx, _dev(A, n, "A"), _dev(B, n, "B"), int(S),
+                        out.ctypes.data_as(_c_double_p), _stream(stream))
     if st == WADG_E_NONFINITE and not check_finite:
         return out
     _check(st)
@@ -291,8 +328,9 @@ def wadg_norms(ctx, A, B, S, stream=None, check_finite=True):
 
 def wadg_l2_norms(ctx, A, B, S, stream=None, check_finite=True):
     out = np.empty((int(S), 2))
-    st = LIB.wadg_l2_norms(ctx, _ptr(A), _ptr(B), int(S), out.ctypes.data_as(_c_double_p),
-                           _stream(stream))
+    n = int(S) * _slice_bytes(ctx)
+    st = LIB.wadg_l2_norms(ctx, _dev(A, n, "A"), _dev(B, n, "B"), int(S),
+                           out.ctypes.data_as(_c_double_p), _stream(stream))
     if st == WADG_E_NONFINITE and not check_finite:
         return out
     _check(st)
@@ -324,15 +362,20 @@ def wadg_adjoint_workspace_bytes(ctx, nsteps):
 
 
 def wadg_forward_checkpoints(ctx, chk, work, S, dt, nsteps, stream=None):
-    _check(LIB.wadg_forward_checkpoints(ctx, _ptr(chk), _ptr(work), int(S), float(dt),
-                                        int(nsteps), _stream(stream)))
+    c = _dev(chk, (int(S) + 1) * _slice_bytes(ctx), "chk")
+    w = _dev(work, _need(wadg_adjoint_workspace_bytes, ctx, nsteps), "work", f64=False)
+    _check(LIB.wadg_forward_checkpoints(ctx, c, w, int(S), float(dt), int(nsteps),
+                                        _stream(stream)))
 
 
 def wadg_adjoint(ctx, chk, seed, grad, work, S, dt, nsteps, stream=None):
     """Returns dJ_dscale (gamma dJ/dgamma); grad is written on the device."""
     out = ctypes.c_double()
-    _check(LIB.wadg_adjoint(ctx, _ptr(chk), _ptr(seed), _ptr(grad), _ptr(work), int(S),
-                            float(dt), int(nsteps), ctypes.byref(out), _stream(stream)))
+    n1 = _slice_bytes(ctx)
+    args = (_dev(chk, (int(S) + 1) * n1, "chk"), _dev(seed, n1, "seed"), _dev(grad, n1, "grad"),
+            _dev(work, _need(wadg_adjoint_workspace_bytes, ctx, nsteps), "work", f64=False))
+    _check(LIB.wadg_adjoint(ctx, *args, int(S), float(dt), int(nsteps), ctypes.byref(out),
+                            _stream(stream)))
     return out.value
 
 
@@ -341,21 +384,48 @@ def _f64(a):
     return a, a.ctypes.data_as(_c_double_p)
 
 
+_BATCH_NPROB = {}   # problems per live batch handle (host arrays are sized by it)
+
+
+def _batch_nprob(b):
+    return _BATCH_NPROB.get(getattr(b, "value", b))
+
+
 def wadg_batch_create(meshes, S, device=-1):
     """meshes: list of MeshDesc (same N, nq1, tau); S: slices per problem."""
-    arr = (wadg_mesh * len(meshes))(*[m.struct() for m in meshes])
     s = np.ascontiguousarray(S, dtype=np.int32)
+    if s.shape != (len(meshes),):
+        raise ValueError("S must hold one slice count per mesh")
+    arr = (wadg_mesh * len(meshes))(*[m.struct() for m in meshes])
     h = ctypes.c_void_p()
     _check(LIB.wadg_batch_create(arr, len(meshes), s.ctypes.data_as(_c_int32_p), int(device),
                                  ctypes.byref(h)))
+    _BATCH_NPROB[h.value] = len(meshes)
     return h
 
 
 def wadg_batch_destroy(b):
     LIB.wadg_batch_destroy(b)
+    _BATCH_NPROB.pop(getattr(b, "value", b), None)
+
+
+def _batch_dt(b, dt):
+    d, dp = _f64(dt)
+    n = _batch_nprob(b)
+    if n is not None and d.size != n:
+        raise ValueError(f"dt holds {d.size} values; the batch has {n} problems")
+    return d, dp
+
+
+def _batch_state(b, Q, work):
+    wb = _need(wadg_batch_workspace_bytes, b)
+    return _dev(Q, wb // 2, "Q"), _dev(work, wb, "work", f64=False)
 
 
 def wadg_batch_layout(b, nprob):
+    n = _batch_nprob(b)
+    if n is not None and int(nprob) != n:
+        raise ValueError(f"nprob is {nprob}; the batch has {n} problems")
     off = np.zeros(nprob + 1, dtype=np.int64)
     pack = np.zeros(nprob, dtype=np.int32)
     _check(LIB.wadg_batch_layout(b, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
@@ -370,8 +440,9 @@ def wadg_batch_workspace_bytes(b):
 
 
 def wadg_batch_integrate(b, Q, work, dt, nsteps, stream=None):
-    d, dp = _f64(dt)
-    _check(LIB.wadg_batch_integrate(b, _ptr(Q), _ptr(work), dp, int(nsteps), _stream(stream)))
+    d, dp = _batch_dt(b, dt)
+    q, w = _batch_state(b, Q, work)
+    _check(LIB.wadg_batch_integrate(b, q, w, dp, int(nsteps), _stream(stream)))
 
 
 def wadg_batch_set_schedule(b, wg_per_cu, order):
@@ -379,16 +450,18 @@ def wadg_batch_set_schedule(b, wg_per_cu, order):
 
 
 def wadg_batch_tune(b, Q, work, dt, reps=3, stream=None):
-    d, dp = _f64(dt)
+    d, dp = _batch_dt(b, dt)
+    q, w = _batch_state(b, Q, work)
     wg, order, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
-    _check(LIB.wadg_batch_tune(b, _ptr(Q), _ptr(work), dp, int(reps), ctypes.byref(wg),
+    _check(LIB.wadg_batch_tune(b, q, w, dp, int(reps), ctypes.byref(wg),
                                ctypes.byref(order), ctypes.byref(us), _stream(stream)))
     return wg.value, order.value, us.value
 
 
 def wadg_batch_capture(b, Q, work, dt, nsteps):
-    d, dp = _f64(dt)
-    _check(LIB.wadg_batch_capture(b, _ptr(Q), _ptr(work), dp, int(nsteps)))
+    d, dp = _batch_dt(b, dt)
+    q, w = _batch_state(b, Q, work)
+    _check(LIB.wadg_batch_capture(b, q, w, dp, int(nsteps)))
 
 
 def wadg_batch_replay(b, stream=None):

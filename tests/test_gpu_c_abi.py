@@ -58,3 +58,50 @@ def test_c_consumer_matches_python_binding_and_oracle(tmp_path, kernel):
     for s in range(S):
         rel = np.linalg.norm(got[s] - want[s]) / np.linalg.norm(want[s])
         assert rel <= 1e-12, (s, rel)
+
+
+def test_binding_refuses_unusable_tensors():
+    """The Python binding checks every device tensor against the call it is
+    passed to before the library sees its pointer: too small, on the host,
+    or not float64 where a state is expected is a ValueError, and so is a
+    host array of per-problem values of the wrong length.  Nothing is
+    launched in these cases."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    import paper_1608_03836_amd as W
+    print("CASE test=binding-refusals", flush=True)
+    mesh = periodic_quad_mesh(4, 2, eps=0.05)
+    sol = W.Solver(mesh)
+    S, dt = 3, 1e-3
+    Q, work = sol.empty_state(S), sol.workspace(S)
+    with pytest.raises(ValueError, match="Q holds"):
+        sol.integrate(Q[:-1], S, dt, 1, work=work)
+    with pytest.raises(ValueError, match="work holds"):
+        sol.integrate(Q, S, dt, 1, work=work[:-1])
+    with pytest.raises(ValueError, match="device tensor"):
+        sol.integrate(Q.cpu(), S, dt, 1, work=work)
+    with pytest.raises(ValueError, match="float64"):
+        sol.rhs(Q.float(), S)
+    with pytest.raises(ValueError, match="dQdt holds"):
+        sol.rhs(Q, S, out=sol.empty_state(S - 1))
+    with pytest.raises(ValueError, match="B holds"):
+        sol.norms(Q, Q[:7], S)
+    with pytest.raises(ValueError, match="A holds"):
+        sol.l2_norms(Q[:7], None, S)
+    with pytest.raises(ValueError, match="work holds"):
+        sol.integrate_fp32(Q, S, dt, 1, work=sol.workspace_fp32(S)[:-1])
+    with pytest.raises(ValueError, match="chk holds"):
+        sol.adjoint(sol.empty_state(S), sol.empty_state(1), S, dt, 1)
+    meshes = [periodic_quad_mesh(k, 2, eps=0.05) for k in (2, 3)]
+    with pytest.raises(ValueError, match="one slice count per mesh"):
+        W.Batch(meshes, [2])
+    batch = W.Batch(meshes, [2, 3])
+    Qb, wb = batch.upload([np.zeros((s, 3, m.Np, m.K)) for m, s in zip(meshes, (2, 3))]), \
+        batch.workspace()
+    with pytest.raises(ValueError, match="dt holds"):
+        batch.integrate(Qb, [dt], 1, work=wb)
+    with pytest.raises(ValueError, match="Q holds"):
+        batch.integrate(Qb[:-1], [dt, dt], 1, work=wb)
+    batch.integrate(Qb, [dt, dt], 1, work=wb)        # the well-formed call runs
+    torch.cuda.synchronize()

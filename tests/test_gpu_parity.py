@@ -248,9 +248,13 @@ def test_norms_over_more_slices_than_a_grid_row(W):
     flat = Q.reshape(S, -1)
     np.testing.assert_allclose(out[:, 0], np.linalg.norm(flat, axis=1), rtol=1e-13, atol=0)
     assert np.all(out[:, 2] == np.abs(flat).max(axis=1)) and np.all(out[:, 3] == 1.0)
+    # the library refuses S >= 2^25 before touching memory (a raw pointer
+    # reaches it unchecked); the binding already refuses the too-small tensor
     with pytest.raises(W.WadgError) as e:
-        sol.norms(A, None, 2 ** 25)
+        W.binding.wadg_norms(sol.ctx, A.data_ptr(), None, 2 ** 25)
     assert e.value.status == W.binding.WADG_E_INVALID
+    with pytest.raises(ValueError, match="A holds"):
+        sol.norms(A, None, 2 ** 25)
 
 
 
