@@ -361,6 +361,55 @@ def run_parareal(args):
     print(json.dumps(line), flush=True)
 
 
+def _oracle_worker(task):
+    """One process of the all-cores baseline: whole slices of the workload,
+    one after another, on one thread.  Returns (grid-point-steps, seconds)."""
+    workload, slices = task
+    from threadpoolctl import threadpool_limits
+    from workloads import make_problem
+    from oracle import WADGOracle
+    prob = make_problem(workload)
+    with threadpool_limits(1):
+        o = WADGOracle(prob.mesh, nq1=prob.nq1, c2=prob.c2, tau_p=prob.tau_p, tau_u=prob.tau_u)
+        t0 = time.perf_counter()
+        for s in slices:
+            o.integrate(prob.Q0[s], prob.dt, prob.nsteps)
+        el = time.perf_counter() - t0
+    return len(slices) * prob.K * (prob.N + 1) ** 2 * prob.nsteps, el
+
+
+def _host_cpu():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_all_cores(workload, slices_per_worker=2):
+    """The same oracle on the host cores this run may use (at most 16 worker
+    processes; slices are independent, so each worker takes whole slices),
+    started before this process touches the GPU.  Rate: all workers' work
+    over the slowest worker's compute time."""
+    import multiprocessing as mp
+    from workloads import make_problem
+    S = make_problem(workload).S
+    workers = max(1, min(16, os.cpu_count() or 1, S // slices_per_worker))
+    tasks = [(workload, list(range(w * slices_per_worker, (w + 1) * slices_per_worker)))
+             for w in range(workers)]
+    with mp.get_context("spawn").Pool(workers) as pool:
+        res = pool.map(_oracle_worker, tasks)
+    work = sum(r[0] for r in res)
+    wall = max(r[1] for r in res)
+    return {"value": work / wall, "unit": "grid-point-steps/s", "cores": workers,
+            "kind": "oracle", "host_cpu": _host_cpu(), "nproc": os.cpu_count(),
+            "sample": f"{workers} processes x {slices_per_worker} slice(s) x all LSRK steps of "
+                      f"{workload}, numpy FP64, 1 thread each, slowest {wall:.1f} s"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -372,6 +421,10 @@ def main():
              "parareal": run_parareal}
     if args.path in other:
         return other[args.path](args)
+    # the oracle on all host cores first, while this process has not touched
+    # the GPU (its workers are fresh processes)
+    allcores = (cpu_baseline_all_cores(args.workload) if args.cpu_baseline_seconds > 0
+                else None)
     import numpy as np
     import torch
     import paper_1608_03836_amd as W
@@ -459,6 +512,7 @@ def main():
         "this_run": 3 * nodes * S * 5 * prob.nsteps / (elapsed / args.steps)}
     if args.cpu_baseline_seconds > 0:
         line["cpu_baseline"] = cpu_baseline(prob, args.cpu_baseline_seconds)
+        line["cpu_baseline_all_cores"] = allcores
     print(json.dumps(line), flush=True)
 
 

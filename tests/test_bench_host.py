@@ -55,3 +55,13 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert p.returncode == 2
     assert "one GPU" in p.stderr
+
+
+def test_cpu_baseline_all_cores_reports_its_sample():
+    """The all-cores oracle baseline runs whole slices in worker processes
+    and states its core count, host and sample."""
+    import bench
+    b = bench.cpu_baseline_all_cores("wadg4", slices_per_worker=1)
+    assert b["kind"] == "oracle" and b["unit"] == "grid-point-steps/s"
+    assert 1 <= b["cores"] <= 16 and b["value"] > 0
+    assert "wadg4" in b["sample"] and b["nproc"] >= 1 and b["host_cpu"]
