@@ -3,9 +3,10 @@
 One step = one pass of the whole hot path over one batch: every slice of the
 workload advanced by its LSRK steps (5 fused stage launches per step: trace
 gathers, volume term, flux and lift, WADG mass inverse, stage update), then
-the per-slice reductions (norms, finite check).  Default workload: wadg64
-(64 x 64 curvilinear elements of degree 3, i.e. 256 x 256 nodes per field,
-64 time slices of 32 steps, FP64).
+the per-slice reductions (norms, finite check).  Default workload: wadg128
+(128 x 128 curvilinear elements of degree 3, i.e. 512 x 512 nodes per field,
+heterogeneous c^2, 256 time slices of 10 steps, FP64: 4.8 GB of state and
+workspace, far beyond the memory-side cache).
 
 Prints one JSON line.  ``value`` = grid-point-steps/s: slices x nodes per
 slice (one node carries p, u, v) x LSRK steps per slice / seconds per step.
@@ -36,7 +37,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--path", choices=("fp64", "fp32", "batch", "adjoint", "parareal"),
                     default="fp64", help="what to measure (default: the FP64 sweep)")
-    ap.add_argument("--workload", default="wadg64")
+    ap.add_argument("--workload", default="wadg128")
     ap.add_argument("--tile-groups", type=int, default=None,
                     help="schedule: element groups per tile (default: library default)")
     ap.add_argument("--tile-slices", type=int, default=0)
@@ -368,12 +369,12 @@ def _oracle_worker(task):
     from threadpoolctl import threadpool_limits
     from workloads import make_problem
     from oracle import WADGOracle
-    prob = make_problem(workload)
+    prob = make_problem(workload, slices=slices)    # only this worker's start states
     with threadpool_limits(1):
         o = WADGOracle(prob.mesh, nq1=prob.nq1, c2=prob.c2, tau_p=prob.tau_p, tau_u=prob.tau_u)
         t0 = time.perf_counter()
-        for s in slices:
-            o.integrate(prob.Q0[s], prob.dt, prob.nsteps)
+        for i in range(len(slices)):
+            o.integrate(prob.Q0[i], prob.dt, prob.nsteps)
         el = time.perf_counter() - t0
     return len(slices) * prob.K * (prob.N + 1) ** 2 * prob.nsteps, el
 
@@ -395,8 +396,8 @@ def cpu_baseline_all_cores(workload, slices_per_worker=2):
     started before this process touches the GPU.  Rate: all workers' work
     over the slowest worker's compute time."""
     import multiprocessing as mp
-    from workloads import make_problem
-    S = make_problem(workload).S
+    from workloads.configs import CONFIGS
+    S = CONFIGS[workload]["S"]
     workers = max(1, min(16, os.cpu_count() or 1, S // slices_per_worker))
     tasks = [(workload, list(range(w * slices_per_worker, (w + 1) * slices_per_worker)))
              for w in range(workers)]
@@ -507,7 +508,7 @@ def main():
     # same unit, scalar unknowns x RK stages per second
     line["paper_context"] = {
         "value": 9.15e8, "unit": "dof-stages/s",
-        "what": "strong-weak WADG stage rate at N=3 (Section 5.6, time per unknown and stage)",
+        "what": "strong-weak WADG stage rate at N=3 (Section 6.5.1, time per unknown and stage)",
         "hardware": "one NVIDIA GTX 980, FP32 (inferred), 3D curvilinear tetrahedra",
         "this_run": 3 * nodes * S * 5 * prob.nsteps / (elapsed / args.steps)}
     if args.cpu_baseline_seconds > 0:

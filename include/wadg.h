@@ -9,14 +9,14 @@
  *     blocks M_{J^k}  (Section 4, opening);
  *   - A_h Q is the strong-weak DG form of the first-order acoustic system,
  *     rho = 1, penalties tau_p, tau_u (Section 4.1, equations of the
- *     strong-weak formulation; Section 5.4 for its volume/surface terms);
+ *     strong-weak formulation; Section 6.4 for its volume/surface terms);
  *   - the mass inverse is replaced by the weight-adjusted approximation
  *       M_{J}^{-1}     ~ Mhat^{-1} M_{1/J}   Mhat^{-1}   (velocity),
  *       M_{J/c2}^{-1}  ~ Mhat^{-1} M_{c2/J}  Mhat^{-1}   (pressure),
- *     applied matrix-free as P_q diag(w_q) V_q  (Section 4; Section 5.2,
- *     equation of the matrix-free product; Section 6 for heterogeneous c2);
+ *     applied matrix-free as P_q diag(w_q) V_q  (Section 4; Section 6.2,
+ *     equation of the matrix-free product; Section 7 for heterogeneous c2);
  *   - time stepping by the low-storage five-stage fourth-order Runge-Kutta
- *     scheme (Section 4.2.1).
+ *     scheme (Section 5.2).
  * The system is autonomous, so no start time is needed: a slice is advanced
  * by nsteps steps of size dt from the state it holds.
  *
@@ -113,8 +113,8 @@ typedef struct {
 int wadg_quadrature_points(const wadg_mesh* mesh, double* xq, double* yq);
 
 /* Host-only: the per-element geometric data the device kernels stream
- * (Section 5.4: geometric factors at quadrature points; Section 5.2: 1/J at
- * quadrature points; Section 6: c2/J), returned untiled.  Caller-owned host
+ * (Section 6.4: geometric factors at quadrature points; Section 6.2: 1/J at
+ * quadrature points; Section 7: c2/J), returned untiled.  Caller-owned host
  * arrays:
  *   vol  [6][nq1*nq1][K]: W ys, -W xs, -W yr, W xr (quadrature weight W
  *        times J times r_x, r_y, s_x, s_y), c2/J, 1/J;
@@ -124,6 +124,21 @@ int wadg_quadrature_points(const wadg_mesh* mesh, double* xq, double* yq);
  * a value is non-finite or the faces do not conform (the arrays' contents
  * are then unspecified).  No GPU needed; runs on the host's threads. */
 int wadg_geometry(const wadg_mesh* mesh, double* vol, double* face);
+
+/* Host-only: the CFL number of a step of size dt on the mesh with c^2 =
+ * c2_scale * c2q,
+ *   nu = dt c_max (N+1)^2 / h,
+ * c_max^2 the largest c^2 at a volume quadrature point and h the smallest
+ * element size 4 |D_k| / |dD_k| (area over perimeter, both by the context's
+ * quadrature rules: the side length of a square element).  The paper fixes
+ * no step size; WADG_CFL_MAX is the largest nu that the parareal coarse
+ * step may take: the spectra of the assembled operator on curved periodic
+ * meshes (N = 1..4, tau = 0 and 1) keep every eigenvalue inside the
+ * stability region of the Runge-Kutta scheme of Section 5.2 up to nu = 1.38
+ * or more.  nu: host out.  Returns WADG_E_INVALID / WADG_E_GEOMETRY /
+ * WADG_E_UNSUPPORTED as wadg_geometry does.  No GPU needed. */
+#define WADG_CFL_MAX 1.25
+int wadg_cfl_number(const wadg_mesh* mesh, double dt, double c2_scale, double* nu);
 
 /* Build a context on HIP device `device` (-1: the current device): validates
  * the mesh, builds reference operators and geometry on the host (on up to
@@ -145,14 +160,14 @@ int wadg_state_doubles(wadg_ctx ctx, size_t* count);
 int wadg_workspace_bytes(wadg_ctx ctx, int32_t S, size_t* bytes);
 
 /* One evaluation of the right-hand side dQ/dt = Mtilde^{-1} A_h Q for S
- * slices (Section 4, opening; the WADG inverse of Section 5.2).
+ * slices (Section 4, opening; the WADG inverse of Section 6.2).
  *   Q     device, S slices in the tiled state layout; input, not modified.
  *   dQdt  device, same layout; output; must not alias Q.
  *   stream  hipStream_t or NULL (the null stream).  Asynchronous. */
 int wadg_rhs(wadg_ctx ctx, const double* Q, double* dQdt, int32_t S, void* stream);
 
 /* Advance each of S independent slice states by nsteps LSRK(5,4) steps of
- * size dt (Section 4.2.1), all slices concurrently.
+ * size dt (Section 5.2), all slices concurrently.
  *   Q     device, S slices in the tiled state layout; in: start states,
  *         out: end states.
  *   work  device workspace of wadg_workspace_bytes(S) bytes, 256-B aligned,
@@ -190,7 +205,10 @@ int wadg_integrate_fp32(wadg_ctx ctx, double* Q, void* work, int32_t S, double d
  *   U   device, S+1 slices: out, U_s ~ y(t0 + s dT).
  *   work  device workspace of wadg_parareal_workspace_bytes bytes.
  *   iterations, last_change: host out.  Synchronises `stream` once per
- *   iteration.  Returns WADG_E_NONFINITE if an iterate is not finite. */
+ *   iteration.  Returns WADG_E_INVALID, before any work, when the coarse
+ *   step dt * nsteps_fine / nsteps_coarse has a CFL number (wadg_cfl_number
+ *   at the context's c^2 scale) above WADG_CFL_MAX, and WADG_E_NONFINITE if
+ *   an iterate is not finite. */
 int wadg_parareal_workspace_bytes(wadg_ctx ctx, int32_t S, int32_t fine_fp32, size_t* bytes);
 int wadg_parareal(wadg_ctx ctx, const double* y0, double* U, void* work, int32_t S, double dt,
                   int32_t nsteps_fine, int32_t nsteps_coarse, int32_t max_iter, double tol,
@@ -198,7 +216,7 @@ int wadg_parareal(wadg_ctx ctx, const double* y0, double* U, void* work, int32_t
 
 /* Wave-speed scale: every later launch of `ctx` uses c^2 = scale * c2q (the
  * c2q given to wadg_create).  c^2 enters the scheme only through the
- * pressure mass weights c^2/J (Section 6), which are multiplied by `scale`.
+ * pressure mass weights c^2/J (Section 7), which are multiplied by `scale`.
  * Default 1 (bitwise the unscaled scheme).  Returns WADG_E_INVALID unless
  * scale is finite and > 0. */
 int wadg_set_c2_scale(wadg_ctx ctx, double scale);
@@ -217,7 +235,7 @@ int wadg_set_c2_scale(wadg_ctx ctx, double scale);
  *   grad = dJ/dq(0) (device, one slice; may alias seed) and the host scalar
  *   dJ_dscale = gamma dJ/dgamma for c^2 = gamma c2q at the current scale
  *   gamma.  It runs the reverse sweep of the 2N-storage LSRK recursion
- *   (Section 4.2.1) with the transposed operator L^T = D A D Mtilde^{-1},
+ *   (Section 5.2) with the transposed operator L^T = D A D Mtilde^{-1},
  *   D = diag(1,-1,-1) (the strong-weak DG operator A of Section 4.1 has
  *   skew p-u coupling and symmetric penalty blocks; Mtilde^{-1} is the
  *   symmetric WADG inverse of Section 4), recomputing each slice's forward
@@ -239,7 +257,7 @@ int wadg_adjoint(wadg_ctx ctx, const double* chk, const double* seed, double* gr
 
 /* Batches of independent problems (many meshes of one degree, each with
  * its own slices and dt), advanced together: one launch per LSRK stage
- * covers every (problem, slice, 64-element group) work item -- Section 5.1's
+ * covers every (problem, slice, 64-element group) work item -- Section 6.1's
  * batching of elements per workgroup, taken across problems.
  *
  * wadg_batch_create: meshes[nprob] (host; all with the same N, nq1, tau_p,
@@ -274,10 +292,16 @@ int wadg_adjoint(wadg_ctx ctx, const double* chk, const double* seed, double* gr
  *   wg_per_cu, order, best_us per stage).  Q is read only; work is scratch.
  *   Synchronises `stream`.
  * wadg_batch_capture: records the whole nsteps sweep of wadg_batch_integrate
- *   for these Q, work and dt into a HIP graph (on a stream of its own);
- *   wadg_batch_replay launches it on `stream` (each replay advances Q by
- *   nsteps steps again).  wadg_batch_release_graph frees it; set_schedule
- *   and tune refuse while a graph is held. */
+ *   for these Q, work and dt into a HIP graph (on a stream of its own); the
+ *   graph reads its own copy of the per-problem dt, so later integrate calls
+ *   with other dt do not change what it computes.  wadg_batch_replay
+ *   launches it on `stream` (each replay advances Q by nsteps steps again).
+ *   wadg_batch_release_graph frees it; set_schedule and tune refuse while a
+ *   graph is held.
+ * A call that changes the device-side work list (set_schedule, tune) or
+ * the per-problem dt (integrate, tune, capture with dt other than the last)
+ * first waits for the device to drain, so that no queued launch of the
+ * batch reads a table while it is rewritten. */
 int wadg_batch_create(const wadg_mesh* meshes, int32_t nprob, const int32_t* S, int32_t device,
                       wadg_batch* out);
 void wadg_batch_destroy(wadg_batch b);
@@ -298,27 +322,36 @@ int wadg_batch_release_graph(wadg_batch b);
  *   else 0, over the 3*(N+1)^2*K state entries of slice s (padding is
  *   skipped).  B may be NULL (treated as zero: out[s][0] = ||A_s||,
  *   out[s][1] = 0).
- *   A, B  device, S slices in the tiled state layout;  out: host [S][4].
- * Synchronises `stream`.  Deterministic: fixed reduction order.  Returns
- * WADG_E_NONFINITE (after filling out) if some A entry is not finite, and
- * WADG_E_INVALID for S >= 2^25 (64 partial sums per slice in one launch). */
-int wadg_norms(wadg_ctx ctx, const double* A, const double* B, int32_t S, double* out,
-               void* stream);
+ *   A, B     device, S slices in the tiled state layout;  out: host [S][4].
+ *   scratch  caller-owned device memory of scratch_bytes bytes, at least
+ *            wadg_norms_workspace_bytes(S) (= 8 * 260 * S: 64 partial sums
+ *            of 4 values per slice, then the S x 4 sums), 8-byte aligned,
+ *            not overlapping A or B; its contents on entry are ignored.
+ * The library allocates nothing.  Synchronises `stream`.  Deterministic:
+ * fixed reduction order.  Returns WADG_E_NONFINITE (after filling out) if
+ * some A entry is not finite, WADG_E_INVALID for a missing or short scratch
+ * and for S >= 2^25 (64 partial sums per slice in one launch). */
+int wadg_norms_workspace_bytes(wadg_ctx ctx, int32_t S, size_t* bytes);
+int wadg_norms(wadg_ctx ctx, const double* A, const double* B, int32_t S, void* scratch,
+               size_t scratch_bytes, double* out, void* stream);
 
-/* L2 norms with the element maps' Jacobians (the norm of Section 4.2's L2
+/* L2 norms with the element maps' Jacobians (the norm of Section 5.2's L2
  * errors), per slice:
  *   out[s][0] = ||A_s - B_s||_{L2},  out[s][1] = ||B_s||_{L2},
  * the square root of the integral over the mesh of p^2 + u^2 + v^2 of the
  * difference (of B), by the context's volume rule (nq1 x nq1 Gauss points
  * per element, each field interpolated there from its nodes, weighted by
  * w_q J_q).  B may be NULL (treated as zero: out[s][1] = 0).
- *   A, B  device, S slices in the tiled state layout;  out: host [S][2].
- * Synchronises `stream`.  Deterministic: fixed reduction order.  The context
- * keeps 16 (S ceil(K/64) + S) bytes of device scratch, grown on demand
- * (draining `stream` first).  Returns WADG_E_NONFINITE (after filling out)
- * if a norm is not finite. */
-int wadg_l2_norms(wadg_ctx ctx, const double* A, const double* B, int32_t S, double* out,
-                  void* stream);
+ *   A, B     device, S slices in the tiled state layout;  out: host [S][2].
+ *   scratch  caller-owned device memory of at least
+ *            wadg_l2_norms_workspace_bytes(S) (= 16 S (ceil(K/64) + 1))
+ *            bytes, 8-byte aligned, not overlapping A or B.
+ * The library allocates nothing.  Synchronises `stream`.  Deterministic:
+ * fixed reduction order.  Returns WADG_E_NONFINITE (after filling out) if a
+ * norm is not finite, WADG_E_INVALID for a missing or short scratch. */
+int wadg_l2_norms_workspace_bytes(wadg_ctx ctx, int32_t S, size_t* bytes);
+int wadg_l2_norms(wadg_ctx ctx, const double* A, const double* B, int32_t S, void* scratch,
+                  size_t scratch_bytes, double* out, void* stream);
 
 /* Tuning: the order in which (slice, 64-element group) work items are
  * launched.  Items are grouped in tiles of groups_per_tile element groups x
@@ -331,7 +364,7 @@ int wadg_l2_norms(wadg_ctx ctx, const double* A, const double* B, int32_t S, dou
  * groups_per_tile < 1 or slices_per_tile < 0. */
 int wadg_set_schedule(wadg_ctx ctx, int32_t groups_per_tile, int32_t slices_per_tile);
 
-/* Tuning: which stage kernel runs (Section 5.4's volume, surface and update
+/* Tuning: which stage kernel runs (Section 6.4's volume, surface and update
  * kernels, fused).
  *   WADG_KERNEL_STREAMED: one 128-thread workgroup (two waves) per (slice,
  *     64-element group), the group's geometry read from global memory for

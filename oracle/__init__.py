@@ -9,11 +9,11 @@ discontinuous Galerkin methods: curvilinear meshes"):
 * ``wadg``    -- strong-weak DG right-hand side on curvilinear quads
                  (Section 4.1), the weight-adjusted mass inverse
                  M_J^{-1} ~ Mhat^{-1} M_{1/J} Mhat^{-1} (Section 4, eq. for
-                 the WADG inverse; Section 5.2; Section 6 for c^2), the exact
+                 the WADG inverse; Section 6.2; Section 7 for c^2), the exact
                  curvilinear-DG mass inverse as a comparator, L2 errors,
                  the weight-adjusted energy.
 * ``lsrk``    -- low-storage five-stage fourth-order Runge-Kutta (the
-                 paper's time integrator, Section 4.2.1, Carpenter-Kennedy).
+                 paper's time integrator, Section 5.2, Carpenter-Kennedy).
 * ``heat``    -- 1D periodic heat equation by second-order differences, a
                  method-of-lines system whose Fourier modes have closed forms.
 * ``parareal``-- serial-reference parareal iteration over time slices.

@@ -10,10 +10,10 @@ Two routes, both plain and both different from the GPU's:
 
 * ``gradient`` -- from the definitions.  The semi-discrete operator is
   linear, dQ/dt = L Q, and c^2 enters it only through the pressure mass
-  inverse M_{c^2/J} (Section 6), linearly, so L(gamma) = E(gamma) L_1 with
+  inverse M_{c^2/J} (Section 7), linearly, so L(gamma) = E(gamma) L_1 with
   E = diag(gamma on the p rows, 1 on the u, v rows) and L_1 the operator at
   gamma = 1 (assembled densely from the oracle's right-hand side).  One
-  step of the LSRK scheme (Section 4.2.1) on a linear autonomous system is
+  step of the LSRK scheme (Section 5.2) on a linear autonomous system is
   Phi = R(dt L), R the stability polynomial, so
       dJ/dy0    = (Phi^T)^n g,   g = dJ/dq(T) = 2 (p(T) - p_target) on p,
       dJ/dgamma = g . qdot_n,    qdot_{m+1} = Phi qdot_m + Phidot q_m,

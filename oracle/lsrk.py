@@ -1,4 +1,4 @@
-"""Low-storage five-stage fourth-order Runge-Kutta (paper, Section 4.2.1:
+"""Low-storage five-stage fourth-order Runge-Kutta (paper, Section 5.2:
 the 2D and 3D experiments are integrated with the low-storage 4th-order
 five-stage scheme of Carpenter and Kennedy).
 

@@ -14,7 +14,7 @@ What is computed, and where the paper defines it:
   Section 4.1 on geometric factors of polynomial maps).
 * WADG mass inverse (Section 4, the weight-adjusted approximation):
       M_{J}^{-1}      ~ Mhat^{-1} M_{1/J} Mhat^{-1}       (velocity)
-      M_{J/c^2}^{-1}  ~ Mhat^{-1} M_{c^2/J} Mhat^{-1}     (pressure, Section 6)
+      M_{J/c^2}^{-1}  ~ Mhat^{-1} M_{c^2/J} Mhat^{-1}     (pressure, Section 7)
   with M_w = V_q^T diag(w_q W_q) V_q formed explicitly per element.
 * Exact curvilinear DG comparator: M_{J/c^2}^{-1}, M_J^{-1} by dense solves
   (Section 4: what WADG avoids storing).
@@ -226,7 +226,7 @@ class WADGOracle:
         together): the square root of the integral of p^2 + u^2 + v^2 over
         every element, with the element map's Jacobian, by an nq-point tensor
         Gauss rule (default: the volume rule nq1).  The norm of the L2 errors
-        of Section 4.2, applied to a difference of two discrete states."""
+        of Section 5.2, applied to a difference of two discrete states."""
         ref = self.ref if nq is None or nq == self.nq1 else ReferenceQuad(self.N, nq)
         Qm = self.to_modal(np.asarray(Q, dtype=np.float64))
         xr, xs = self.cx @ ref.Vr.T, self.cx @ ref.Vs.T

@@ -17,8 +17,8 @@ class WadgSweep(torch.autograd.Function):
     @staticmethod
     def forward(ctx, y0, gamma, solver, S, dt, nsteps):
         g = float(gamma)
-        solver.set_c2_scale(g)
-        chk = solver.forward_checkpoints(y0.detach(), S, dt, nsteps)
+        with _scaled(solver, g):
+            chk = solver.forward_checkpoints(y0.detach(), S, dt, nsteps)
         ctx.solver, ctx.S, ctx.dt, ctx.nsteps, ctx.gamma = solver, S, dt, nsteps, g
         ctx.save_for_backward(chk)
         n1 = solver.slice_doubles
@@ -28,16 +28,33 @@ class WadgSweep(torch.autograd.Function):
     def backward(ctx, grad_qT):
         (chk,) = ctx.saved_tensors
         solver = ctx.solver
-        solver.set_c2_scale(ctx.gamma)
         # padding lanes of the tiled layout hold no state: their gradient is
         # dropped (the adjoint requires a seed that is zero there), and the
         # returned gradient is zero there
         mask = element_mask(solver)
         seed = grad_qT.detach().reshape(-1) * mask
-        grad_y0, d_scale = solver.adjoint(chk, seed, ctx.S, ctx.dt, ctx.nsteps)
+        with _scaled(solver, ctx.gamma):
+            grad_y0, d_scale = solver.adjoint(chk, seed, ctx.S, ctx.dt, ctx.nsteps)
         grad_gamma = torch.tensor(d_scale / ctx.gamma, dtype=torch.float64,
                                   device=grad_qT.device)
         return grad_y0 * mask, grad_gamma, None, None, None, None
+
+
+class _scaled:
+    """Run with c^2 = gamma * c2 on the solver, then restore the scale it had
+    before, so that a differentiable sweep leaves the solver's later plain
+    calls as they were."""
+
+    def __init__(self, solver, gamma):
+        self.solver, self.gamma = solver, gamma
+
+    def __enter__(self):
+        self.prev = self.solver.c2_scale
+        self.solver.set_c2_scale(self.gamma)
+
+    def __exit__(self, *exc):
+        self.solver.set_c2_scale(self.prev)
+        return False
 
 
 def sweep(solver, y0, gamma, S, dt, nsteps):

@@ -29,6 +29,7 @@ WADG_KERNEL_AUTO = 0
 WADG_KERNEL_STREAMED = 1
 WADG_KERNEL_RESIDENT = 2
 WADG_KERNEL_SPLIT = 3
+WADG_CFL_MAX = 1.25
 TILE_LANES = 64
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
@@ -65,6 +66,8 @@ def _load():
     sig = {
         "wadg_quadrature_points": (ctypes.c_int, [ctypes.POINTER(wadg_mesh), _c_double_p, _c_double_p]),
         "wadg_geometry": (ctypes.c_int, [ctypes.POINTER(wadg_mesh), _c_double_p, _c_double_p]),
+        "wadg_cfl_number": (ctypes.c_int, [ctypes.POINTER(wadg_mesh), ctypes.c_double,
+                                           ctypes.c_double, _c_double_p]),
         "wadg_create": (ctypes.c_int, [ctypes.POINTER(wadg_mesh), ctypes.c_int32, ctypes.POINTER(vp)]),
         "wadg_destroy": (None, [vp]),
         "wadg_state_doubles": (ctypes.c_int, [vp, ctypes.POINTER(sz)]),
@@ -82,8 +85,11 @@ def _load():
                                          ctypes.c_double, ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_double), vp]),
-        "wadg_norms": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, _c_double_p, vp]),
-        "wadg_l2_norms": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, _c_double_p, vp]),
+        "wadg_norms_workspace_bytes": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.POINTER(sz)]),
+        "wadg_norms": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, vp, sz, _c_double_p, vp]),
+        "wadg_l2_norms_workspace_bytes": (ctypes.c_int, [vp, ctypes.c_int32,
+                                                         ctypes.POINTER(sz)]),
+        "wadg_l2_norms": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, vp, sz, _c_double_p, vp]),
         "wadg_set_schedule": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32]),
         "wadg_set_kernel": (ctypes.c_int, [vp, ctypes.c_int32]),
         "wadg_set_c2_scale": (ctypes.c_int, [vp, ctypes.c_double]),
@@ -117,11 +123,12 @@ def _load():
 
 
 LIB = _load()
-EXPORTED = ("wadg_quadrature_points", "wadg_geometry", "wadg_create", "wadg_destroy",
+EXPORTED = ("wadg_quadrature_points", "wadg_geometry", "wadg_cfl_number", "wadg_create", "wadg_destroy",
             "wadg_state_doubles", "wadg_workspace_bytes", "wadg_rhs", "wadg_integrate",
             "wadg_workspace_bytes_fp32", "wadg_integrate_fp32",
             "wadg_parareal_workspace_bytes", "wadg_parareal",
-            "wadg_norms", "wadg_l2_norms", "wadg_set_schedule", "wadg_set_kernel", "wadg_kernel_in_use",
+            "wadg_norms_workspace_bytes", "wadg_norms", "wadg_l2_norms_workspace_bytes",
+            "wadg_l2_norms", "wadg_set_schedule", "wadg_set_kernel", "wadg_kernel_in_use",
             "wadg_set_c2_scale", "wadg_adjoint_workspace_bytes", "wadg_forward_checkpoints",
             "wadg_adjoint", "wadg_batch_create", "wadg_batch_destroy", "wadg_batch_layout",
             "wadg_batch_workspace_bytes", "wadg_batch_integrate", "wadg_batch_set_schedule",
@@ -247,6 +254,13 @@ def wadg_geometry(mesh):
     return vol, face
 
 
+def wadg_cfl_number(mesh, dt, c2_scale=1.0):
+    nu = ctypes.c_double()
+    m = mesh.struct()
+    _check(LIB.wadg_cfl_number(ctypes.byref(m), float(dt), float(c2_scale), ctypes.byref(nu)))
+    return nu.value
+
+
 def wadg_create(mesh, device=-1):
     h = ctypes.c_void_p()
     m = mesh.struct()
@@ -315,10 +329,29 @@ def wadg_parareal(ctx, y0, U, work, S, dt, nsteps_fine, nsteps_coarse, max_iter,
     return it.value, ch.value
 
 
-def wadg_norms(ctx, A, B, S, stream=None, check_finite=True):
+def wadg_norms_workspace_bytes(ctx, S):
+    n = ctypes.c_size_t()
+    _check(LIB.wadg_norms_workspace_bytes(ctx, int(S), ctypes.byref(n)))
+    return n.value
+
+
+def _scratch(scratch, need, nbytes):
+    """Device pointer and byte size of a scratch buffer: a tensor (its own
+    size is passed, so the library refuses one that is too short) or a raw
+    integer address taken to hold `nbytes` (or `need` if None), as in C."""
+    if scratch is None:
+        return None, 0
+    if isinstance(scratch, int):
+        return scratch, int(need if nbytes is None else nbytes)
+    p = _dev(scratch, 0, "scratch", f64=False)
+    return p, scratch.numel() * scratch.element_size()
+
+
+def wadg_norms(ctx, A, B, S, scratch, stream=None, check_finite=True, scratch_bytes=None):
     out = np.empty((int(S), 4))
     n = int(S) * _slice_bytes(ctx)
-    st = LIB.wadg_norms(ctx, _dev(A, n, "A"), _dev(B, n, "B"), int(S),
+    sp, sb = _scratch(scratch, _need(wadg_norms_workspace_bytes, ctx, S), scratch_bytes)
+    st = LIB.wadg_norms(ctx, _dev(A, n, "A"), _dev(B, n, "B"), int(S), sp, sb,
                         out.ctypes.data_as(_c_double_p), _stream(stream))
     if st == WADG_E_NONFINITE and not check_finite:
         return out
@@ -326,10 +359,17 @@ def wadg_norms(ctx, A, B, S, stream=None, check_finite=True):
     return out
 
 
-def wadg_l2_norms(ctx, A, B, S, stream=None, check_finite=True):
+def wadg_l2_norms_workspace_bytes(ctx, S):
+    n = ctypes.c_size_t()
+    _check(LIB.wadg_l2_norms_workspace_bytes(ctx, int(S), ctypes.byref(n)))
+    return n.value
+
+
+def wadg_l2_norms(ctx, A, B, S, scratch, stream=None, check_finite=True, scratch_bytes=None):
     out = np.empty((int(S), 2))
     n = int(S) * _slice_bytes(ctx)
-    st = LIB.wadg_l2_norms(ctx, _dev(A, n, "A"), _dev(B, n, "B"), int(S),
+    sp, sb = _scratch(scratch, _need(wadg_l2_norms_workspace_bytes, ctx, S), scratch_bytes)
+    st = LIB.wadg_l2_norms(ctx, _dev(A, n, "A"), _dev(B, n, "B"), int(S), sp, sb,
                            out.ctypes.data_as(_c_double_p), _stream(stream))
     if st == WADG_E_NONFINITE and not check_finite:
         return out

@@ -91,7 +91,11 @@ int main(int argc, char** argv) {
   hip_check(hipMemcpy(dq, q, qbytes, hipMemcpyHostToDevice), "hipMemcpy");
   check(wadg_integrate(ctx, dq, dw, S, sc[0], nsteps, NULL), "wadg_integrate");
   double* norms = (double*)malloc((size_t)S * 4 * sizeof(double));
-  check(wadg_norms(ctx, dq, NULL, S, norms, NULL), "wadg_norms");
+  size_t nbytes = 0;
+  void* dn = NULL;
+  check(wadg_norms_workspace_bytes(ctx, S, &nbytes), "wadg_norms_workspace_bytes");
+  hip_check(hipMalloc(&dn, nbytes), "hipMalloc");
+  check(wadg_norms(ctx, dq, NULL, S, dn, nbytes, norms, NULL), "wadg_norms");
   hip_check(hipMemcpy(q, dq, qbytes, hipMemcpyDeviceToHost), "hipMemcpy");
 
   FILE* g = fopen(argv[2], "wb");
@@ -103,6 +107,7 @@ int main(int argc, char** argv) {
   fclose(g);
   hip_check(hipFree(dq), "hipFree");
   hip_check(hipFree(dw), "hipFree");
+  hip_check(hipFree(dn), "hipFree");
   wadg_destroy(ctx);
   free(hdr);
   free(sc);

@@ -1,7 +1,7 @@
 // Adjoint mass step of the discrete adjoint sweep (FP64, gfx950).
 //
 // The semi-discrete operator is L = Mtilde^{-1} A, with Mtilde^{-1} the
-// block-diagonal weight-adjusted inverse (Section 4; Section 6 for c^2) and
+// block-diagonal weight-adjusted inverse (Section 4; Section 7 for c^2) and
 // A the strong-weak DG operator (Section 4.1).  In the strong-weak form the
 // volume and central-flux couplings of p with (u, v) are exact negative
 // transposes of each other and the penalty blocks are symmetric, so

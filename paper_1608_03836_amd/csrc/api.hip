@@ -48,6 +48,30 @@ int check_mesh(const wadg_mesh* m) {
   return WADG_OK;
 }
 
+void mesh_scales(const double* vol, const double* face, int K, int nq, const double* wq,
+                 bool tiled, double* h_min, double* c2_max) {
+  const int nqq = nq * nq;
+  const int KB = wadg::kWave;
+  // value of plane p (of P planes) of element k
+  auto at = [&](const double* a, int P, int p, int k) {
+    return tiled ? a[((size_t)(k / KB) * P + p) * KB + k % KB] : a[(size_t)p * K + k];
+  };
+  double h = INFINITY, c2 = 0.0;
+  for (int k = 0; k < K; ++k) {
+    double area = 0.0, perim = 0.0;
+    for (int q = 0; q < nqq; ++q) {
+      const double rJ = at(vol, 6 * nqq, 5 * nqq + q, k);      // 1/J
+      area += wq[q % nq] * wq[q / nq] / rJ;
+      c2 = std::max(c2, at(vol, 6 * nqq, 4 * nqq + q, k) / rJ);
+    }
+    for (int f = 0; f < 4; ++f)
+      for (int j = 0; j < nq; ++j) perim += at(face, 12 * nq, 2 * 4 * nq + f * nq + j, k);
+    h = std::min(h, 4.0 * area / perim);
+  }
+  *h_min = h;
+  *c2_max = c2;
+}
+
 int check_slices(wadg_ctx c, int32_t S) {
   if (!c) return fail(WADG_E_INVALID, "context is NULL");
   if (S < 1) return fail(WADG_E_INVALID, "S must be >= 1");
@@ -72,9 +96,6 @@ void free_ctx(wadg_ctx c) {
   if (c->d_vol32) (void)hipFree(c->d_vol32);
   if (c->d_face32) (void)hipFree(c->d_face32);
   if (c->d_nbr) (void)hipFree(c->d_nbr);
-  if (c->d_partials) (void)hipFree(c->d_partials);
-  if (c->d_out) (void)hipFree(c->d_out);
-  if (c->d_l2) (void)hipFree(c->d_l2);
   for (hipEvent_t e : {c->ev_in, c->ev_rec[0], c->ev_rec[1], c->ev_rev[0], c->ev_rev[1]})
     if (e) (void)hipEventDestroy(e);
   if (c->aux) (void)hipStreamDestroy(c->aux);
@@ -107,6 +128,25 @@ int wadg_geometry(const wadg_mesh* mesh, double* vol, double* face) {
   return WADG_OK;
 }
 
+int wadg_cfl_number(const wadg_mesh* mesh, double dt, double c2_scale, double* nu) {
+  int st = check_mesh(mesh);
+  if (st) return st;
+  if (!nu) return fail(WADG_E_INVALID, "nu is NULL");
+  if (!(dt > 0.0) || !std::isfinite(dt) || !(c2_scale > 0.0) || !std::isfinite(c2_scale))
+    return fail(WADG_E_INVALID, "dt and c2_scale must be finite and > 0");
+  wadg::RefOps ops;
+  std::string err;
+  if (!wadg::build_ref_ops(mesh->N, mesh->nq1, &ops, &err)) return fail(WADG_E_UNSUPPORTED, err);
+  const size_t nq = mesh->nq1, K = mesh->K;
+  std::vector<double> vol(6 * nq * nq * K), face(12 * nq * K);
+  int g = wadg::build_geometry(mesh_in(mesh), ops, vol.data(), face.data(), nullptr, false, &err);
+  if (g) return fail(g == -1 ? WADG_E_INVALID : WADG_E_GEOMETRY, err);
+  double h = 0.0, c2 = 0.0;
+  mesh_scales(vol.data(), face.data(), mesh->K, mesh->nq1, ops.wq, false, &h, &c2);
+  *nu = cfl_number(dt, mesh->N, h, c2 * c2_scale);
+  return WADG_OK;
+}
+
 int wadg_create(const wadg_mesh* mesh, int32_t device, wadg_ctx* out) {
   if (!out) return fail(WADG_E_INVALID, "out is NULL");
   *out = nullptr;
@@ -128,12 +168,17 @@ int wadg_create(const wadg_mesh* mesh, int32_t device, wadg_ctx* out) {
   int g = wadg::build_geometry(mesh_in(mesh), ops, vol.get(), face.get(), nbr.get(), true, &err);
   if (g) return fail(g == -1 ? WADG_E_INVALID : WADG_E_GEOMETRY, err);
 
+  double h_min = 0.0, c2_max = 0.0;
+  mesh_scales(vol.get(), face.get(), mesh->K, nq, ops.wq, true, &h_min, &c2_max);
+
   int dev = device;
   if (dev < 0) WADG_HIP(hipGetDevice(&dev));
   DeviceGuard guard(dev);
   if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select HIP device " + std::to_string(dev));
 
   wadg_ctx c = new wadg_ctx_s();
+  c->h_min = h_min;
+  c->c2_max = c2_max;
   c->device = dev;
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
@@ -355,6 +400,12 @@ int wadg_parareal(wadg_ctx ctx, const double* y0, double* U, void* work, int32_t
   if (nsteps_fine < 1 || nsteps_coarse < 1 || max_iter < 0)
     return fail(WADG_E_INVALID, "nsteps_fine, nsteps_coarse >= 1 and max_iter >= 0 required");
   if (!(tol >= 0.0)) return fail(WADG_E_INVALID, "tol must be >= 0");
+  const double dtc = dt * nsteps_fine / nsteps_coarse;
+  const double nu_c = cfl_number(dtc, ctx->N, ctx->h_min, ctx->c2_max * ctx->c2_scale);
+  if (!(nu_c <= WADG_CFL_MAX))
+    return fail(WADG_E_INVALID, "coarse step dt * nsteps_fine / nsteps_coarse has CFL number " +
+                                    std::to_string(nu_c) + " > " + std::to_string(WADG_CFL_MAX) +
+                                    ": raise nsteps_coarse");
   const size_t n1 = ctx->slice_doubles();
   const size_t ubytes = (S + 1) * n1 * sizeof(double);
   const size_t wbytes = parareal_bytes(ctx, S, fine_fp32);
@@ -372,7 +423,6 @@ int wadg_parareal(wadg_ctx ctx, const double* y0, double* U, void* work, int32_t
   char* fwork = reinterpret_cast<char*>(cwork + 2 * n1);
   double* partials = reinterpret_cast<double*>(fwork + fine_work_bytes(ctx, S, fine_fp32));
   double* dout = partials + (size_t)S * kNormBlocks * 4;
-  const double dtc = dt * nsteps_fine / nsteps_coarse;
   const int32_t tile = (int32_t)ctx->tile();
   const size_t sb = n1 * sizeof(double);
 
@@ -428,36 +478,31 @@ int wadg_parareal(wadg_ctx ctx, const double* y0, double* U, void* work, int32_t
   return WADG_OK;
 }
 
-int wadg_norms(wadg_ctx ctx, const double* A, const double* B, int32_t S, double* out,
-               void* stream) {
-  int st = check_slices(ctx, S);
-  if (st) return st;
-  if (!A || !out) return fail(WADG_E_INVALID, "A and out must not be NULL");
-  if ((int64_t)S * kNormBlocks > INT32_MAX)
-    return fail(WADG_E_INVALID, "too many slices for one reduction (S * 64 must stay below 2^31)");
-  DeviceGuard guard(ctx->device);
-  if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select the context's device");
-  hipStream_t hs = static_cast<hipStream_t>(stream);
-  if (S > ctx->norms_cap) {
-    // scratch grows with the largest S seen; the stream is drained first so
-    // that no queued reduction still reads the old buffers
-    WADG_HIP(hipStreamSynchronize(hs));
-    if (ctx->d_partials) (void)hipFree(ctx->d_partials);
-    if (ctx->d_out) (void)hipFree(ctx->d_out);
-    ctx->d_partials = nullptr;
-    ctx->d_out = nullptr;
-    ctx->norms_cap = 0;
-    WADG_HIP(hipMalloc(&ctx->d_partials, (size_t)S * kNormBlocks * 4 * sizeof(double)));
-    WADG_HIP(hipMalloc(&ctx->d_out, (size_t)S * 4 * sizeof(double)));
-    ctx->norms_cap = S;
-  }
-  const int64_t per = (int64_t)ctx->slice_doubles();
-  int e = wadg::launch_norms(A, B, S, per, (int32_t)ctx->tile(), ctx->K, ctx->d_partials,
-                             kNormBlocks, ctx->d_out, stream);
-  if (e) return hip_fail((hipError_t)e, "norms kernel launch");
-  WADG_HIP(hipMemcpyAsync(out, ctx->d_out, (size_t)S * 4 * sizeof(double),
-                          hipMemcpyDeviceToHost, hs));
-  WADG_HIP(hipStreamSynchronize(hs));
+namespace {
+
+size_t norms_scratch_doubles(int32_t S) { return (size_t)S * (kNormBlocks * 4 + 4); }
+size_t l2_scratch_doubles(wadg_ctx ctx, int32_t S) {
+  return ((size_t)S * ctx->groups() + S) * 2;
+}
+
+// Caller-owned device scratch of a reduction: present, 8-byte aligned, at
+// least `need` doubles and not overlapping the operands.
+int check_scratch(const void* scratch, size_t bytes, size_t need, const double* A,
+                  const double* B, size_t nA) {
+  if (!scratch) return fail(WADG_E_INVALID, "scratch must not be NULL");
+  if (reinterpret_cast<uintptr_t>(scratch) % alignof(double))
+    return fail(WADG_E_INVALID, "scratch must be 8-byte aligned");
+  if (bytes < need * sizeof(double))
+    return fail(WADG_E_INVALID, "scratch holds " + std::to_string(bytes) + " bytes; " +
+                                    std::to_string(need * sizeof(double)) + " needed");
+  const size_t sb = need * sizeof(double);
+  if (overlaps(scratch, sb, A, nA) || (B && overlaps(scratch, sb, B, nA)))
+    return fail(WADG_E_INVALID, "scratch must not overlap A or B");
+  return WADG_OK;
+}
+
+// Square roots and the finite flag of the S x 4 sums of a norms launch.
+int finish_norms(int32_t S, double* out) {
   bool all_finite = true;
   for (int s = 0; s < S; ++s) {
     out[4 * s + 0] = std::sqrt(out[4 * s + 0]);
@@ -469,27 +514,77 @@ int wadg_norms(wadg_ctx ctx, const double* A, const double* B, int32_t S, double
   return WADG_OK;
 }
 
-int wadg_l2_norms(wadg_ctx ctx, const double* A, const double* B, int32_t S, double* out,
-                  void* stream) {
+// The reduction of wadg_norms into device scratch `partials` (S x 64 x 4)
+// and `dout` (S x 4), then the sums copied to `out` (synchronises).
+int run_norms(wadg_ctx ctx, const double* A, const double* B, int32_t S, double* partials,
+              double* dout, double* out, void* stream) {
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  const int64_t per = (int64_t)ctx->slice_doubles();
+  int e = wadg::launch_norms(A, B, S, per, (int32_t)ctx->tile(), ctx->K, partials, kNormBlocks,
+                             dout, stream);
+  if (e) return hip_fail((hipError_t)e, "norms kernel launch");
+  WADG_HIP(hipMemcpyAsync(out, dout, (size_t)S * 4 * sizeof(double), hipMemcpyDeviceToHost, hs));
+  WADG_HIP(hipStreamSynchronize(hs));
+  return finish_norms(S, out);
+}
+
+int check_norms_args(wadg_ctx ctx, const double* A, int32_t S, const double* out) {
   int st = check_slices(ctx, S);
   if (st) return st;
   if (!A || !out) return fail(WADG_E_INVALID, "A and out must not be NULL");
+  if ((int64_t)S * kNormBlocks > INT32_MAX)
+    return fail(WADG_E_INVALID, "too many slices for one reduction (S * 64 must stay below 2^31)");
+  return WADG_OK;
+}
+
+}  // namespace
+
+int wadg_norms_workspace_bytes(wadg_ctx ctx, int32_t S, size_t* bytes) {
+  int st = check_slices(ctx, S);
+  if (st) return st;
+  if (!bytes) return fail(WADG_E_INVALID, "bytes is NULL");
+  if ((int64_t)S * kNormBlocks > INT32_MAX)
+    return fail(WADG_E_INVALID, "too many slices for one reduction (S * 64 must stay below 2^31)");
+  *bytes = norms_scratch_doubles(S) * sizeof(double);
+  return WADG_OK;
+}
+
+int wadg_norms(wadg_ctx ctx, const double* A, const double* B, int32_t S, void* scratch,
+               size_t scratch_bytes, double* out, void* stream) {
+  int st = check_norms_args(ctx, A, S, out);
+  if (st) return st;
+  if ((st = check_scratch(scratch, scratch_bytes, norms_scratch_doubles(S), A, B,
+                          ctx->state_doubles(S) * sizeof(double))))
+    return st;
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select the context's device");
+  double* partials = static_cast<double*>(scratch);
+  return run_norms(ctx, A, B, S, partials, partials + (size_t)S * kNormBlocks * 4, out, stream);
+}
+
+int wadg_l2_norms_workspace_bytes(wadg_ctx ctx, int32_t S, size_t* bytes) {
+  int st = check_slices(ctx, S);
+  if (st) return st;
+  if (!bytes) return fail(WADG_E_INVALID, "bytes is NULL");
+  *bytes = l2_scratch_doubles(ctx, S) * sizeof(double);
+  return WADG_OK;
+}
+
+int wadg_l2_norms(wadg_ctx ctx, const double* A, const double* B, int32_t S, void* scratch,
+                  size_t scratch_bytes, double* out, void* stream) {
+  int st = check_slices(ctx, S);
+  if (st) return st;
+  if (!A || !out) return fail(WADG_E_INVALID, "A and out must not be NULL");
+  if ((st = check_scratch(scratch, scratch_bytes, l2_scratch_doubles(ctx, S), A, B,
+                          ctx->state_doubles(S) * sizeof(double))))
+    return st;
   DeviceGuard guard(ctx->device);
   if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select the context's device");
   hipStream_t hs = static_cast<hipStream_t>(stream);
   const int32_t nEG = ctx->groups();
-  const size_t need = ((size_t)S * nEG + S) * 2;
-  if (need > ctx->l2_cap) {
-    // grown like the norms scratch: the stream is drained first
-    WADG_HIP(hipStreamSynchronize(hs));
-    if (ctx->d_l2) (void)hipFree(ctx->d_l2);
-    ctx->d_l2 = nullptr;
-    ctx->l2_cap = 0;
-    WADG_HIP(hipMalloc(&ctx->d_l2, need * sizeof(double)));
-    ctx->l2_cap = need;
-  }
-  double* dout = ctx->d_l2 + (size_t)S * nEG * 2;
-  int e = wadg::launch_l2_norms(ctx->N, ctx->nq1, A, B, ctx->d_vol, S, nEG, ctx->K, ctx->d_l2,
+  double* partials = static_cast<double*>(scratch);
+  double* dout = partials + (size_t)S * nEG * 2;
+  int e = wadg::launch_l2_norms(ctx->N, ctx->nq1, A, B, ctx->d_vol, S, nEG, ctx->K, partials,
                                 dout, stream);
   if (e) return hip_fail((hipError_t)e, "L2 norms kernel launch");
   WADG_HIP(hipMemcpyAsync(out, dout, (size_t)S * 2 * sizeof(double), hipMemcpyDeviceToHost, hs));

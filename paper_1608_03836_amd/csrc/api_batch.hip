@@ -21,12 +21,13 @@ struct wadg_batch_s {
   std::vector<int32_t> pack, K, S;            // per problem: copies per lane group, elements, slices
   std::vector<int32_t> Kv, Sv, nEG, g0;       // packed (virtual) mesh and its slices
   std::vector<int64_t> offset;                 // [nprob + 1] state offsets in doubles
-  std::vector<double> dt;                      // per problem (last uploaded)
+  std::vector<double> dt;                      // per problem (last uploaded to d_prob)
   int64_t groups = 0, items = 0;
   double* d_vol = nullptr;
   double* d_face = nullptr;
   int32_t* d_nbr = nullptr;
-  wadg::BatchProb* d_prob = nullptr;
+  wadg::BatchProb* d_prob = nullptr;           // descriptors of eager sweeps
+  wadg::BatchProb* d_prob_graph = nullptr;     // descriptors the captured graph reads
   int32_t* d_items = nullptr;
   int grid_mult = 0;                           // persistent workgroups per CU (0: one per item)
   int order = 0;                               // 0 problem-major, 1 interleaved
@@ -43,7 +44,7 @@ void free_batch(wadg_batch b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
   for (void* ptr : {(void*)b->d_vol, (void*)b->d_face, (void*)b->d_nbr, (void*)b->d_prob,
-                    (void*)b->d_items})
+                    (void*)b->d_prob_graph, (void*)b->d_items})
     if (ptr) (void)hipFree(ptr);
   delete b;
 }
@@ -74,24 +75,44 @@ std::vector<int32_t> batch_items(const wadg_batch b) {
   return it;
 }
 
+// Device tables that launches already queued may still read (the work
+// list, the descriptors) are rewritten only after the device has drained:
+// a rewrite is then ordered after every earlier launch of the batch, on
+// whatever stream it ran, and (the copy being synchronous) before every
+// later one.  Rewrites happen only when the schedule or a dt changes.
 int batch_upload_items(wadg_batch b) {
   std::vector<int32_t> it = batch_items(b);
+  WADG_HIP(hipDeviceSynchronize());
   WADG_HIP(hipMemcpy(b->d_items, it.data(), it.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   return WADG_OK;
 }
 
+int check_dt(const wadg_batch b, const double* dt) {
+  for (int i = 0; i < b->nprob; ++i)
+    if (!(dt[i] > 0.0) || !std::isfinite(dt[i]))
+      return fail(WADG_E_INVALID, "dt[" + std::to_string(i) + "] must be finite and > 0");
+  return WADG_OK;
+}
+
+int write_descriptors(const wadg_batch b, const double* dt, wadg::BatchProb* dst) {
+  std::vector<wadg::BatchProb> pr(b->nprob);
+  for (int i = 0; i < b->nprob; ++i)
+    pr[i] = wadg::BatchProb{b->offset[i], b->nEG[i], b->Sv[i], b->Kv[i], b->g0[i], dt[i]};
+  WADG_HIP(hipDeviceSynchronize());
+  WADG_HIP(hipMemcpy(dst, pr.data(), pr.size() * sizeof(wadg::BatchProb),
+                     hipMemcpyHostToDevice));
+  return WADG_OK;
+}
+
+// The descriptors of eager sweeps, rewritten when a dt differs from the
+// last upload.  The captured graph keeps its own (d_prob_graph).
 int batch_upload_dt(wadg_batch b, const double* dt) {
+  int st = check_dt(b, dt);
+  if (st) return st;
   bool same = !b->dt.empty();
   for (int i = 0; same && i < b->nprob; ++i) same = b->dt[i] == dt[i];
   if (same) return WADG_OK;
-  std::vector<wadg::BatchProb> pr(b->nprob);
-  for (int i = 0; i < b->nprob; ++i) {
-    if (!(dt[i] > 0.0) || !std::isfinite(dt[i]))
-      return fail(WADG_E_INVALID, "dt[" + std::to_string(i) + "] must be finite and > 0");
-    pr[i] = wadg::BatchProb{b->offset[i], b->nEG[i], b->Sv[i], b->Kv[i], b->g0[i], dt[i]};
-  }
-  WADG_HIP(hipMemcpy(b->d_prob, pr.data(), pr.size() * sizeof(wadg::BatchProb),
-                     hipMemcpyHostToDevice));
+  if ((st = write_descriptors(b, dt, b->d_prob))) return st;
   b->dt.assign(dt, dt + b->nprob);
   return WADG_OK;
 }
@@ -101,9 +122,10 @@ int batch_grid(const wadg_batch b) {
   return b->grid_mult * b->cus;
 }
 
-int batch_stage(wadg_batch b, const double* qin, double* qout, double* res, int i, void* stream) {
+int batch_stage(wadg_batch b, const wadg::BatchProb* prob, const double* qin, double* qout,
+                double* res, int i, void* stream) {
   wadg::BatchParams p{};
-  p.prob = b->d_prob;
+  p.prob = prob;
   p.items = b->d_items;
   p.nitems = (int32_t)b->items;
   p.Qin = qin;
@@ -124,7 +146,8 @@ int batch_stage(wadg_batch b, const double* qin, double* qout, double* res, int 
   return WADG_OK;
 }
 
-int batch_sweep(wadg_batch b, double* Q, double* work, int32_t nsteps, void* stream) {
+int batch_sweep(wadg_batch b, const wadg::BatchProb* prob, double* Q, double* work,
+                int32_t nsteps, void* stream) {
   const size_t n = (size_t)b->offset[b->nprob];
   double* res = work;
   double* other = work + n;
@@ -132,7 +155,7 @@ int batch_sweep(wadg_batch b, double* Q, double* work, int32_t nsteps, void* str
   for (int stp = 0; stp < nsteps; ++stp)
     for (int i = 0; i < 5; ++i) {
       double* out = cur == Q ? other : Q;
-      int st = batch_stage(b, cur, out, res, i, stream);
+      int st = batch_stage(b, prob, cur, out, res, i, stream);
       if (st) return st;
       cur = out;
     }
@@ -282,6 +305,7 @@ int wadg_batch_create(const wadg_mesh* meshes, int32_t nprob, const int32_t* S, 
       (e = hipMalloc(&b->d_face, face.size() * sizeof(double))) != hipSuccess ||
       (e = hipMalloc(&b->d_nbr, nbr.size() * sizeof(int32_t))) != hipSuccess ||
       (e = hipMalloc(&b->d_prob, (size_t)nprob * sizeof(wadg::BatchProb))) != hipSuccess ||
+      (e = hipMalloc(&b->d_prob_graph, (size_t)nprob * sizeof(wadg::BatchProb))) != hipSuccess ||
       (e = hipMalloc(&b->d_items, (size_t)b->items * 2 * sizeof(int32_t))) != hipSuccess ||
       (e = hipMemcpy(b->d_vol, vol.data(), vol.size() * sizeof(double),
                      hipMemcpyHostToDevice)) != hipSuccess ||
@@ -334,7 +358,7 @@ int wadg_batch_integrate(wadg_batch b, double* Q, double* work, const double* dt
   if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select the batch's device");
   int st = batch_upload_dt(b, dt);
   if (st) return st;
-  return batch_sweep(b, Q, work, nsteps, stream);
+  return batch_sweep(b, b->d_prob, Q, work, nsteps, stream);
 }
 
 int wadg_batch_set_schedule(wadg_batch b, int32_t wg_per_cu, int32_t order) {
@@ -384,9 +408,10 @@ int wadg_batch_tune(wadg_batch b, const double* Q, double* work, const double* d
   for (int o = 0; o < 2 && !st; ++o) {
     for (int m : mults) {
       if ((st = wadg_batch_set_schedule(b, m, o))) break;
-      if ((st = batch_stage(b, Q, work, work + n, 1, stream))) break;
+      if ((st = batch_stage(b, b->d_prob, Q, work, work + n, 1, stream))) break;
       if (hipEventRecord(e0, hs) != hipSuccess) { st = hip_fail(hipErrorUnknown, "event"); break; }
-      for (int r = 0; r < reps && !st; ++r) st = batch_stage(b, Q, work, work + n, 1, stream);
+      for (int r = 0; r < reps && !st; ++r)
+        st = batch_stage(b, b->d_prob, Q, work, work + n, 1, stream);
       if (st) break;
       float ms = 0.f;
       if (hipEventRecord(e1, hs) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -424,16 +449,19 @@ int wadg_batch_capture(wadg_batch b, double* Q, double* work, const double* dt, 
     return fail(WADG_E_INVALID, "work must not alias Q");
   DeviceGuard guard(b->device);
   if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select the batch's device");
-  int st = batch_upload_dt(b, dt);
+  int st = check_dt(b, dt);
   if (st) return st;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   b->exec = nullptr;
   b->graph = nullptr;
+  // the graph's own descriptors, written once here (after any replay of an
+  // earlier graph has drained); eager sweeps never touch them
+  if ((st = write_descriptors(b, dt, b->d_prob_graph))) return st;
   if (!b->capture_stream)
     WADG_HIP(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
   WADG_HIP(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
-  st = batch_sweep(b, Q, work, nsteps, b->capture_stream);
+  st = batch_sweep(b, b->d_prob_graph, Q, work, nsteps, b->capture_stream);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(b->capture_stream, &g);
   if (st) {

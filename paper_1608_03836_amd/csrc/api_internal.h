@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <string>
 
 #include "wadg.h"
@@ -19,17 +20,14 @@ struct wadg_ctx_s {
   int kernel = WADG_KERNEL_AUTO;
   int cus = 256;         // compute units of the device
   double c2_scale = 1.0; // multiplies c^2 (wadg_set_c2_scale)
+  double h_min = 0.0;    // min over elements of 4 area / perimeter (mesh_scales)
+  double c2_max = 0.0;   // max of c^2 over the volume points (unscaled)
   unsigned order_flip = 0;  // item order of the next stage launch (launch_stage)
   double* d_vol = nullptr;
   double* d_face = nullptr;
   float* d_vol32 = nullptr;      // geometry rounded to FP32 (FP32-bulk path)
   float* d_face32 = nullptr;
   int32_t* d_nbr = nullptr;
-  double* d_partials = nullptr;  // norms scratch, grown on demand
-  double* d_out = nullptr;
-  int32_t norms_cap = 0;
-  double* d_l2 = nullptr;        // L2-norm scratch (partials and sums), grown on demand
-  size_t l2_cap = 0;             // its size in doubles
   // adjoint: a second stream (default priority) for the forward recompute
   // that overlaps the reverse sweep, and the events that order the two
   hipStream_t aux = nullptr;
@@ -74,6 +72,19 @@ struct DeviceGuard {
 };
 
 int check_mesh(const wadg_mesh* m);
+
+// Length and speed scales of a mesh from its geometry arrays (untiled,
+// tiled = false: vol [6][nq^2][K], face [3][4][nq][K]; or tiled in groups
+// of 64 lanes): h = min over elements of 4 |D_k| / |dD_k| (the side of a
+// square element: area = sum_q w_q J_q, perimeter = sum over faces and
+// points of w sJ) and the largest c^2 = (c2/J) / (1/J) at a volume point.
+void mesh_scales(const double* vol, const double* face, int K, int nq, const double* wq,
+                 bool tiled, double* h_min, double* c2_max);
+
+// CFL number of a step dt: dt c_max (N+1)^2 / h.
+inline double cfl_number(double dt, int N, double h_min, double c2_max) {
+  return dt * std::sqrt(c2_max) * (N + 1) * (N + 1) / h_min;
+}
 int check_slices(wadg_ctx c, int32_t S);
 
 inline wadg::MeshIn mesh_in(const wadg_mesh* m) {

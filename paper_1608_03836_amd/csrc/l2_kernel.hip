@@ -1,5 +1,5 @@
 // Per-slice L2 norms with the element maps' Jacobians (the norm of the L2
-// errors of Section 4.2), on the tiled state layout:
+// errors of Section 5.2), on the tiled state layout:
 //
 //   ||A_s - B_s||^2 = sum_k sum_q w_q J_kq sum_f ((V_q (A_s - B_s)_f)_kq)^2
 //

@@ -8,7 +8,7 @@ namespace wadg {
 namespace host {
 
 // LSRK(5,4) 2N-storage coefficients (Carpenter & Kennedy 1994), the
-// integrator of the paper's experiments (Section 4.2.1).
+// integrator of the paper's experiments (Section 5.2).
 const double kRkA[5] = {0.0,
                         -567301805773.0 / 1357537059087.0,
                         -2404267990393.0 / 2016746695238.0,

@@ -3,7 +3,7 @@
 //
 // The 1D operators are the compile-time tables of reference_tables.h.
 // Geometry: isoparametric map (degree-N interpolant of the GLL node
-// coordinates); metric terms of Section 5.4 at volume quadrature points,
+// coordinates); metric terms of Section 6.4 at volume quadrature points,
 // outward normals and surface Jacobians at face quadrature points.
 
 #include <algorithm>

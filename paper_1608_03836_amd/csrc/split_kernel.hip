@@ -10,7 +10,7 @@
 //           inverse and update;
 //   wave 1  velocity volume term, then the u mass inverse and update;
 //   wave 2  traces, fluxes and lifts of faces 0 and 2 for all three fields
-//           (Section 5.4: each face's traces interpolated once), then the
+//           (Section 6.4: each face's traces interpolated once), then the
 //           v mass inverse and update;
 //   wave 3  the same for faces 1 and 3.
 //

@@ -5,15 +5,15 @@
 // written once here, so they produce bit-identical results:
 //
 //   * pressure / velocity volume term of one quadrature column (Section 4.1,
-//     strong-weak form; Section 5.4, volume kernel), through the tensor
+//     strong-weak form; Section 6.4, volume kernel), through the tensor
 //     factors of V_q and its derivatives and the weighted metric terms;
-//   * penalised numerical flux on one face and its lift (Section 5.4,
+//   * penalised numerical flux on one face and its lift (Section 6.4,
 //     surface kernel; with GLL nodes the lift of a face touches only that
 //     face's nodes);
 //   * the weight-adjusted mass inverse P_q diag(w) (V_q Mhat^{-1})
-//     (Section 5.2, matrix-free product; w = c2/J for p, 1/J for u and v,
-//     Section 6);
-//   * the 2N-storage LSRK update (Section 4.2.1).
+//     (Section 6.2, matrix-free product; w = c2/J for p, 1/J for u and v,
+//     Section 7);
+//   * the 2N-storage LSRK update (Section 5.2).
 //
 // Operands are nodal values of one element (lane) read through accessors,
 // so the caller decides where they live (LDS tile, registers).

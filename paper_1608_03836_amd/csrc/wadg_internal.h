@@ -19,7 +19,7 @@ constexpr int kWave = 64;    // elements per workgroup: one element per lane
 //   D[i][a]  = l_a'(x_i)
 //   Vt[i][a] = (V M1^{-1})[i][a]        interpolation of Mhat^{-1} b
 //   P[a][i]  = (M1^{-1} V^T W)[a][i]    quadrature-based L2 projection
-// with M1 the 1D nodal mass matrix.  Section 5.2 defines V_q and
+// with M1 the 1D nodal mass matrix.  Section 6.2 defines V_q and
 // P_q = Mhat^{-1} V_q^T diag(w_q); Mhat = M1 (x) M1 and V_q = V (x) V.
 struct RefOps {
   int N = 0, nq = 0;

@@ -107,12 +107,23 @@ class Solver:
                                  max_iter, tol, fine_fp32, stream)
         return U, it, ch
 
+    def scratch(self, nbytes):
+        """Device scratch of at least nbytes for the reductions, kept by the
+        solver and grown when a call needs more (torch device memory)."""
+        have = getattr(self, "_scratch", None)
+        if have is None or have.numel() * 8 < nbytes:
+            self._scratch = self.torch.empty(max(1, -(-nbytes // 8)), dtype=self.torch.float64,
+                                             device=self.device)
+        return self._scratch
+
     def norms(self, A, Bt=None, S=1, stream=None, check_finite=True):
-        return B.wadg_norms(self.ctx, A, Bt, S, stream, check_finite=check_finite)
+        sc = self.scratch(B.wadg_norms_workspace_bytes(self.ctx, S))
+        return B.wadg_norms(self.ctx, A, Bt, S, sc, stream, check_finite=check_finite)
 
     def l2_norms(self, A, Bt=None, S=1, stream=None, check_finite=True):
         """Per slice (||A - Bt||_L2, ||Bt||_L2) with the element Jacobians."""
-        return B.wadg_l2_norms(self.ctx, A, Bt, S, stream, check_finite=check_finite)
+        sc = self.scratch(B.wadg_l2_norms_workspace_bytes(self.ctx, S))
+        return B.wadg_l2_norms(self.ctx, A, Bt, S, sc, stream, check_finite=check_finite)
 
     def set_schedule(self, groups_per_tile, slices_per_tile=0):
         B.wadg_set_schedule(self.ctx, groups_per_tile, slices_per_tile)
@@ -128,6 +139,9 @@ class Solver:
     def set_c2_scale(self, gamma):
         """Use c^2 = gamma * c2 (the wave speed given at construction)."""
         B.wadg_set_c2_scale(self.ctx, gamma)
+        self.c2_scale = float(gamma)
+
+    c2_scale = 1.0      # the context's current scale (the library's default)
 
     def adjoint_workspace(self, nsteps):
         n = B.wadg_adjoint_workspace_bytes(self.ctx, nsteps) // 8 + 1

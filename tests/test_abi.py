@@ -130,7 +130,10 @@ def test_null_arguments():
     assert W.LIB.wadg_create(None, 0, ctypes.byref(ctypes.c_void_p())) == W.WADG_E_INVALID
     assert W.LIB.wadg_rhs(None, None, None, 1, None) == W.WADG_E_INVALID
     assert W.LIB.wadg_integrate(None, None, None, 1, 0.1, 1, None) == W.WADG_E_INVALID
-    assert W.LIB.wadg_norms(None, None, None, 1, None, None) == W.WADG_E_INVALID
+    assert W.LIB.wadg_norms(None, None, None, 1, None, 0, None, None) == W.WADG_E_INVALID
+    assert W.LIB.wadg_l2_norms(None, None, None, 1, None, 0, None, None) == W.WADG_E_INVALID
+    assert W.LIB.wadg_norms_workspace_bytes(None, 1, None) == W.WADG_E_INVALID
+    assert W.LIB.wadg_l2_norms_workspace_bytes(None, 1, None) == W.WADG_E_INVALID
     assert W.LIB.wadg_workspace_bytes(None, 1, None) == W.WADG_E_INVALID
     W.LIB.wadg_destroy(None)
     for st in (0, -1, -2, -3, -4, -5, -99):
@@ -184,3 +187,53 @@ def test_mesh_arrays_of_the_wrong_shape_are_refused():
         W.MeshDesc(2, 4, m.x, m.y, m.etoe, m.etof[:, :3])
     with pytest.raises(ValueError, match="y"):
         W.MeshDesc(2, 4, m.x, m.y[:-1], m.etoe, m.etof)
+
+
+def test_cfl_number_of_affine_and_curved_meshes():
+    """wadg_cfl_number: on an affine K1D x K1D mesh of the unit torus with
+    c^2 = 1 the element size is exactly 1/K1D, so nu = dt (N+1)^2 K1D; with
+    c^2 = gamma c0^2 the speed is sqrt(gamma max c0^2) over the volume
+    points (NumPy over wadg_quadrature_points); a curved mesh has smaller
+    elements somewhere, so a larger nu; bad arguments are refused."""
+    for N in (1, 3):
+        m = periodic_quad_mesh(6, N, eps=0.0)
+        d = W.MeshDesc(N, N + 2, m.x, m.y, m.etoe, m.etof)
+        nu = W.wadg_cfl_number(d, 1e-3)
+        assert abs(nu - 1e-3 * (N + 1) ** 2 * 6) <= 1e-13 * nu
+        xq, yq = W.wadg_quadrature_points(d)
+        c2 = c2_layered(xq, yq)
+        dc = W.MeshDesc(N, N + 2, m.x, m.y, m.etoe, m.etof, c2)
+        nu2 = W.wadg_cfl_number(dc, 1e-3, 1.7)
+        assert abs(nu2 - nu * np.sqrt(1.7 * c2.max())) <= 1e-13 * nu2
+        mc = periodic_quad_mesh(6, N, eps=0.05)
+        assert W.wadg_cfl_number(W.MeshDesc(N, N + 2, mc.x, mc.y, mc.etoe, mc.etof), 1e-3) > nu
+    for dt, sc in ((0.0, 1.0), (-1.0, 1.0), (np.inf, 1.0), (1e-3, 0.0), (1e-3, np.nan)):
+        assert _status(W.wadg_cfl_number, d, dt, sc) == W.WADG_E_INVALID
+    assert W.LIB.wadg_cfl_number(None, 1e-3, 1.0, None) == W.WADG_E_INVALID
+
+
+@pytest.mark.parametrize("N,warp,tau,c2", [(1, "skew", 1.0, None), (2, "skew", 1.0, None),
+                                           (3, "skew", 1.0, None), (3, "diag", 0.0, "layered"),
+                                           (4, "skew", 1.0, None)])
+def test_cfl_bound_is_inside_the_stability_region(N, warp, tau, c2):
+    """The parareal coarse-step bound: at nu = WADG_CFL_MAX (the library's
+    CFL number of the step) every eigenvalue lambda of the assembled WADG
+    operator (the oracle's, curved periodic 4 x 4 meshes) satisfies
+    |R(dt lambda)| <= 1 for the stability polynomial R of the LSRK(5,4)
+    scheme, so the coarse sweep does not grow."""
+    from oracle.lsrk import stability_polynomial_coeffs
+    c2f = c2_layered if c2 == "layered" else None
+    m = periodic_quad_mesh(4, N, eps=0.05, warp=warp)
+    d = W.MeshDesc(N, N + 2, m.x, m.y, m.etoe, m.etof)
+    if c2f is not None:
+        xq, yq = W.wadg_quadrature_points(d)
+        d = W.MeshDesc(N, N + 2, m.x, m.y, m.etoe, m.etof, c2f(xq, yq))
+    dt = W.WADG_CFL_MAX / W.wadg_cfl_number(d, 1.0)
+    lam = np.linalg.eigvals(WADGOracle(m, c2=c2f, tau_p=tau, tau_u=tau).assemble())
+    z = dt * lam
+    R = sum(float(g) * z ** k for k, g in enumerate(stability_polynomial_coeffs()))
+    assert np.max(np.abs(R)) <= 1.0 + 1e-12
+    # and the bound is not vacuous: twice the step leaves the region
+    z2 = 2 * z
+    R2 = sum(float(g) * z2 ** k for k, g in enumerate(stability_polynomial_coeffs()))
+    assert np.max(np.abs(R2)) > 1.0

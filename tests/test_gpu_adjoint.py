@@ -11,8 +11,10 @@ with the transposed operator, recomputing each slice from its checkpoint).
   directions of the start state, and the dot-product identity
   <Phi x, w> = <x, Phi^T w> of the forward and adjoint sweeps.
 
-Tolerances: gradients against the oracle 1e-10 relative (both sides FP64;
-rounding over ~30 stages); finite differences as derived in the tests.
+Tolerances: gradients against the oracle 1e-12 relative in the l2 norm and
+element by element (max |difference| <= 1e-12 max |oracle|), dJ/dgamma 1e-12
+relative (both sides FP64; the measured errors are near 1e-14); finite
+differences as derived in the tests.
 """
 
 import numpy as np
@@ -49,6 +51,15 @@ def _seed(sol, qT_nat, p_target):
     return sol.upload(g[None])
 
 
+def _assert_gradient(g_gpu, g_orc, dg_gpu, dg_orc, tol=1e-12):
+    """The FP64 bar, element by element: relative l2 error and max |error|
+    over max |oracle| of the start-state gradient, relative error of
+    dJ/dgamma."""
+    assert np.linalg.norm(g_gpu - g_orc) <= tol * np.linalg.norm(g_orc)
+    assert np.max(np.abs(g_gpu - g_orc)) <= tol * np.max(np.abs(g_orc))
+    assert abs(dg_gpu - dg_orc) <= tol * abs(dg_orc), (dg_gpu, dg_orc)
+
+
 def test_adjoint_matches_oracle(W):
     _print_case(test="adjoint-oracle", workload="adj4")
     prob = make_sensitivity_problem("adj4")
@@ -69,10 +80,10 @@ def test_adjoint_matches_oracle(W):
     J, g_orc, dgamma = obj.gradient(prob.y0, prob.p_target, prob.gamma, prob.dt,
                                     prob.S * prob.nsteps)
     rel = np.linalg.norm(g_gpu - g_orc) / np.linalg.norm(g_orc)
-    print(f"adj4: |grad - oracle|/|oracle| = {rel:.3e}; dJ/dgamma gpu {dscale / prob.gamma:.15e}"
-          f" oracle {dgamma:.15e}", flush=True)
-    assert rel <= 1e-10
-    assert abs(dscale / prob.gamma - dgamma) <= 1e-10 * abs(dgamma)
+    mx = np.max(np.abs(g_gpu - g_orc)) / np.max(np.abs(g_orc))
+    print(f"adj4: |grad - oracle|/|oracle| = {rel:.3e}, max {mx:.3e}; dJ/dgamma gpu "
+          f"{dscale / prob.gamma:.15e} oracle {dgamma:.15e}", flush=True)
+    _assert_gradient(g_gpu, g_orc, dscale / prob.gamma, dgamma)
 
 
 @pytest.mark.parametrize("N", [1, 2, 4])
@@ -94,8 +105,7 @@ def test_adjoint_other_degrees_match_oracle(W, N):
                                     prob.S * prob.nsteps)
     rel = np.linalg.norm(g_gpu - g_orc) / np.linalg.norm(g_orc)
     print(f"adj4 N={N}: |grad - oracle|/|oracle| = {rel:.3e}", flush=True)
-    assert rel <= 1e-10
-    assert abs(dscale / prob.gamma - dgamma) <= 1e-10 * abs(dgamma)
+    _assert_gradient(g_gpu, g_orc, dscale / prob.gamma, dgamma)
 
 
 def test_autograd_function_matches_finite_differences(W):
@@ -113,7 +123,18 @@ def test_autograd_function_matches_finite_differences(W):
         return torch.sum((mask * (qT - target)) ** 2)
 
     y0 = sol.upload(prob.y0[None]).requires_grad_(True)
+    plain = sol.upload(prob.y0[None])
+    sol.integrate(plain, 1, prob.dt, 3)
     gamma = torch.tensor(prob.gamma, dtype=torch.float64, requires_grad=True)
+    J = J_of(y0 * 1.0, gamma * 1.1)
+    J.backward()
+    # the differentiable sweep leaves the solver's c^2 scale as it found it
+    assert sol.c2_scale == prob.gamma
+    again = sol.upload(prob.y0[None])
+    sol.integrate(again, 1, prob.dt, 3)
+    assert torch.equal(plain, again)
+    y0.grad = None
+    gamma.grad = None
     J = J_of(y0, gamma)
     J.backward()
     with torch.no_grad():
@@ -209,7 +230,7 @@ def test_full_size_adjoint_fd_and_transpose(W):
     lhs = torch.sum(Phix * w).item()
     rhs = torch.sum(x * PhiTw).item()
     print(f"adj128: <Phi x, w> = {lhs:.15e}, <x, Phi^T w> = {rhs:.15e}", flush=True)
-    assert abs(lhs - rhs) <= 1e-10 * torch.linalg.norm(x).item() * torch.linalg.norm(w).item()
+    assert abs(lhs - rhs) <= 1e-12 * torch.linalg.norm(x).item() * torch.linalg.norm(w).item()
 
 
 def test_adjoint_kernel_variants_bitwise(W):

@@ -105,3 +105,40 @@ def test_binding_refuses_unusable_tensors():
         batch.integrate(Qb[:-1], [dt, dt], 1, work=wb)
     batch.integrate(Qb, [dt, dt], 1, work=wb)        # the well-formed call runs
     torch.cuda.synchronize()
+
+
+def test_reductions_take_caller_scratch():
+    """wadg_norms and wadg_l2_norms run in caller-owned device scratch: the
+    size queries give S (64 x 4 + 4) and 2 S (ceil(K/64) + 1) doubles, a
+    buffer one byte short, a missing one or one that overlaps an operand is
+    refused before any launch, and a buffer of exactly the queried size
+    gives the same sums as a larger one."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    import paper_1608_03836_amd as W
+    from paper_1608_03836_amd import binding as B
+    print("CASE test=reduction-scratch", flush=True)
+    mesh = periodic_quad_mesh(9, 3, eps=0.05)       # 81 elements: 2 groups
+    sol = W.Solver(mesh)
+    S = 5
+    nb = B.wadg_norms_workspace_bytes(sol.ctx, S)
+    lb = B.wadg_l2_norms_workspace_bytes(sol.ctx, S)
+    assert nb == 8 * S * (64 * 4 + 4)
+    assert lb == 8 * 2 * S * (2 + 1)
+    Q = sol.upload(np.random.default_rng(3).standard_normal((S, 3, mesh.Np, mesh.K)))
+    exact = torch.empty(nb // 8, dtype=torch.float64, device="cuda")
+    big = torch.empty(nb // 8 + 1000, dtype=torch.float64, device="cuda")
+    a = B.wadg_norms(sol.ctx, Q, None, S, exact)
+    assert np.array_equal(a, B.wadg_norms(sol.ctx, Q, None, S, big))
+    for fn, need in ((B.wadg_norms, nb), (B.wadg_l2_norms, lb)):
+        with pytest.raises(W.WadgError, match="needed") as e:
+            fn(sol.ctx, Q, None, S, big.data_ptr(), scratch_bytes=need - 1)
+        assert e.value.status == B.WADG_E_INVALID
+        with pytest.raises(W.WadgError, match="scratch must not be NULL"):
+            fn(sol.ctx, Q, None, S, None)
+        with pytest.raises(W.WadgError, match="overlap"):
+            fn(sol.ctx, Q, None, S, Q.data_ptr(), scratch_bytes=need)
+    la = B.wadg_l2_norms(sol.ctx, Q, None, S, big[: lb // 8])
+    assert np.array_equal(la, sol.l2_norms(Q, None, S))
+    torch.cuda.synchronize()

@@ -1,4 +1,4 @@
-"""Pins for the oracle's time integrator (LSRK(5,4), paper Section 4.2.1).
+"""Pins for the oracle's time integrator (LSRK(5,4), paper Section 5.2).
 
 The coefficients are checked against mathematics, not against a retyped
 copy: the Butcher tableau derived from the 2N-storage recursion must satisfy

@@ -139,7 +139,7 @@ def test_conservation_exact_when_J_in_QN(N):
     assert d <= 1e-13 * tot
 
 
-# -- Section 4: energy stability, Section 4.2.1: spectra ----------------------
+# -- Section 4: energy stability, Section 5.2.1: spectra ----------------------
 
 def test_energy_nonincreasing_upwind():
     """tau = 1: the weight-adjusted energy does not increase (Section 4:
@@ -162,7 +162,7 @@ def _spectrum(tau, nq1=None, warp="skew", c2=None):
 
 @pytest.mark.parametrize("nq1", [3, 4, 5])
 def test_central_flux_spectrum_is_imaginary(nq1):
-    """tau = 0: purely imaginary eigenvalues (Section 4.2.1), for any volume
+    """tau = 0: purely imaginary eigenvalues (Section 5.2.1), for any volume
     and surface quadrature in the strong-weak form (Section 4.1)."""
     lam = _spectrum(0.0, nq1=nq1, c2=c2_layered)
     assert np.max(np.abs(lam.real)) <= 1e-11 * np.max(np.abs(lam))
@@ -190,7 +190,7 @@ def test_stepper_equals_dense_matrix_polynomial(N):
     assert np.max(np.abs(got - want)) <= 1e-13 * np.max(np.abs(want))
 
 
-# -- convergence against exact solutions (slopes of Section 4.2) -------------
+# -- convergence against exact solutions (slopes of Section 5.2) -------------
 
 @pytest.mark.parametrize("N", [1, 2, 3])
 def test_convergence_rate(N):
@@ -208,7 +208,7 @@ def test_convergence_rate(N):
 
 
 def test_wadg_nearly_identical_to_dg(golden_dir):
-    """WADG and curvilinear DG errors are nearly identical (Section 4.2.1).
+    """WADG and curvilinear DG errors are nearly identical (Section 5.2).
     The paper's own printed errors differ by < 1e-4 relative; here, on a
     curved periodic mesh, the two differ by < 1e-2 relative and the gap
     shrinks under refinement."""
@@ -291,7 +291,7 @@ def test_periodic_cover_evolves_copy_by_copy():
     np.testing.assert_allclose(rx[..., 4], rb[..., 0], rtol=0, atol=1e-12 * np.max(np.abs(rb)))
 
 
-# -- Section 4.2: the L2 norm with the element maps' Jacobians ---------------
+# -- Section 5.2: the L2 norm with the element maps' Jacobians ---------------
 
 def test_l2_norm_of_constant_fields_is_the_area():
     """A constant field c on one component: ||Q||^2 = c^2 x area of the unit
