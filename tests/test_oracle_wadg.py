@@ -9,6 +9,8 @@ breaks the frame-rotation invariance and convergence pins; a wrong metric
 term breaks convergence; a wrong LSRK loop breaks the brute-force pin.
 """
 
+import os
+
 import numpy as np
 import pytest
 
@@ -331,3 +333,135 @@ def test_l2_norm_is_the_curvilinear_mass_norm():
     assert abs(o.l2_norm(Q) ** 2 - want) <= 1e-13 * want
     zero = lambda x, y, t: np.zeros((3,) + x.shape)
     assert abs(o.l2_norm(Q, nq=7) - o.l2_error(Q, zero, 0.0, nq_err=7)) <= 1e-14 * o.l2_norm(Q)
+
+
+# -- Block-Fourier closed form on the affine torus (Section 4.1 operator,
+#    Section 5.2 time stepping) ----------------------------------------------
+
+def _lagrange_1d(nodes, x):
+    """Values and derivatives of the Lagrange basis on `nodes` at points x,
+    by the product formula (independent of any modal basis)."""
+    n = len(nodes)
+    L = np.ones((n, len(x)))
+    dL = np.zeros((n, len(x)))
+    for a in range(n):
+        for c in range(n):
+            if c == a:
+                continue
+            term = np.ones(len(x)) / (nodes[a] - nodes[c])
+            for d in range(n):
+                if d != a and d != c:
+                    term = term * (x - nodes[d]) / (nodes[a] - nodes[d])
+            dL[a] += term
+            L[a] *= (x - nodes[c]) / (nodes[a] - nodes[c])
+    return L, dL
+
+
+def _block_symbol(N, h, theta, tau_p, tau_u):
+    """The 3 (N+1)^2 x 3 (N+1)^2 Bloch symbol of the strong-weak DG operator
+    (Section 4.1, rho = c^2 = 1) on a uniform square mesh of side h: for a
+    state whose element at lattice position (i, j) holds exp(i theta.(i, j))
+    times the nodal vector q, dQ/dt at that element is exp(i theta.(i, j))
+    L(theta) q.  Built from 1D GLL Lagrange factors with exactly integrated
+    1D mass / stiffness matrices (a fine Gauss rule), in Kronecker form --
+    none of the oracle's modal machinery or quadrature is used."""
+    Np1 = N + 1
+    r = np.polynomial.legendre.Legendre.basis(N).deriv().roots() if N > 1 else np.zeros(0)
+    nodes = np.concatenate(([-1.0], np.sort(np.real(r)), [1.0]))
+    tq, wq = np.polynomial.legendre.leggauss(2 * N + 4)
+    L, dL = _lagrange_1d(nodes, tq)
+    M1 = (L * wq) @ L.T                       # int l_a l_c
+    S1 = (dL * wq) @ L.T                      # S1[a, c] = int l_a' l_c
+    eL, _ = _lagrange_1d(nodes, np.array([-1.0]))
+    eR, _ = _lagrange_1d(nodes, np.array([1.0]))
+    eL, eR = eL[:, 0], eR[:, 0]
+    kr = np.kron                               # node n = a + (N+1) b: kron(Y_b, X_a)
+    hh = 0.5 * h
+    mass = hh * hh * kr(M1, M1)
+    Vx, Vy = hh * kr(M1, S1), hh * kr(S1, M1)            # int u d_x v, int v d_y v
+    Gx, Gy = -hh * kr(M1, S1.T), -hh * kr(S1.T, M1)      # -int d_x p v, -int d_y p v
+    tx, ty = np.exp(1j * theta[0]), np.exp(1j * theta[1])
+    faces = [  # (nx, ny, own-trace operator, neighbour-trace operator)
+        (1.0, 0.0, hh * kr(M1, np.outer(eR, eR)), tx * hh * kr(M1, np.outer(eR, eL))),
+        (-1.0, 0.0, hh * kr(M1, np.outer(eL, eL)), np.conj(tx) * hh * kr(M1, np.outer(eL, eR))),
+        (0.0, 1.0, hh * kr(np.outer(eR, eR), M1), ty * hh * kr(np.outer(eR, eL), M1)),
+        (0.0, -1.0, hh * kr(np.outer(eL, eL), M1), np.conj(ty) * hh * kr(np.outer(eL, eR), M1)),
+    ]
+    n = Np1 * Np1
+    Z = np.zeros((n, n), dtype=complex)
+    App, Apu, Apv = Z.copy(), Vx.astype(complex), Vy.astype(complex)
+    Aup, Auu, Auv = Gx.astype(complex), Z.copy(), Z.copy()
+    Avp, Avu, Avv = Gy.astype(complex), Z.copy(), Z.copy()
+    for nx, ny, To, Tn in faces:
+        S, D = Tn + To, Tn - To               # sum and jump (neighbour minus own)
+        # -1/2 ((u+ + u-).n - tau_p [p])
+        App += 0.5 * tau_p * D
+        Apu += -0.5 * nx * S
+        Apv += -0.5 * ny * S
+        # -1/2 ([p] - tau_u [u].n) n
+        for (Ap, Au, Av), nc in (((Aup, Auu, Auv), nx), ((Avp, Avu, Avv), ny)):
+            Ap += -0.5 * nc * D
+            Au += 0.5 * tau_u * nc * nx * D
+            Av += 0.5 * tau_u * nc * ny * D
+    A = np.block([[App, Apu, Apv], [Aup, Auu, Auv], [Avp, Avu, Avv]])
+    Minv = np.linalg.inv(mass)
+    return np.kron(np.eye(3), Minv) @ A
+
+
+def _lsrk_matrix_steps(Lhat, dt, nsteps, q0, golden_dir):
+    """Step dq/dt = Lhat q with the 2N-storage recursion of the published
+    table (tests/golden), written here on its own."""
+    rows = [ln.split() for ln in open(os.path.join(golden_dir, "lsrk54_carpenter_kennedy.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    A = [int(r[1]) / int(r[2]) for r in rows]
+    B = [int(r[3]) / int(r[4]) for r in rows]
+    q = q0.astype(complex)
+    res = np.zeros_like(q)
+    for _ in range(nsteps):
+        for a, b in zip(A, B):
+            res = a * res + dt * (Lhat @ q)
+            q = q + b * res
+    return q
+
+
+@pytest.mark.parametrize("N,K1D,mn,tau", [(2, 4, (1, 2), 1.0), (3, 4, (1, 0), 1.0),
+                                          (3, 5, (2, 3), 0.0), (1, 6, (5, 1), 0.5)])
+def test_block_fourier_closed_form(N, K1D, mn, tau, golden_dir):
+    """On the affine torus (eps = 0, c^2 = 1) every element is the same square
+    and the operator commutes with lattice shifts, so a Bloch state
+    Q_(i,j) = Re(exp(i theta.(i,j)) q0), theta = 2 pi (m, n)/K1D, stays one:
+    after n LSRK steps it is Re(exp(i theta.(i,j)) R(dt L(theta))^n q0) with
+    the 48 x 48 (for N = 3) symbol L(theta) built independently above.  The
+    oracle's stepped sweep must match it to 1e-12 relative."""
+    mesh = periodic_quad_mesh(K1D, N, eps=0.0)
+    h = 1.0 / K1D
+    theta = 2 * np.pi * np.array(mn) / K1D
+    Lhat = _block_symbol(N, h, theta, tau, tau)
+    rng = np.random.default_rng(7 + N)
+    n = (N + 1) ** 2
+    q0 = rng.standard_normal(3 * n) + 1j * rng.standard_normal(3 * n)
+    k = np.arange(K1D * K1D)
+    phase = np.exp(1j * (theta[0] * (k % K1D) + theta[1] * (k // K1D)))   # k = i + K1D j
+    Q0 = np.real(q0.reshape(3, n)[:, :, None] * phase[None, None, :])
+    dt, nsteps = 0.2 * h / (N + 1) ** 2, 12
+    want = np.real(_lsrk_matrix_steps(Lhat, dt, nsteps, q0, golden_dir).reshape(3, n)[:, :, None]
+                   * phase[None, None, :])
+    got = WADGOracle(mesh, tau_p=tau, tau_u=tau).integrate(Q0, dt, nsteps)
+    assert np.linalg.norm(got - want) <= 1e-12 * np.linalg.norm(want)
+    # not vacuous: the state moved
+    assert np.linalg.norm(want - Q0) > 1e-3 * np.linalg.norm(Q0)
+
+
+def test_block_symbol_detects_a_flux_sign_error(golden_dir):
+    """The closed form is sharp: flipping the sign of the pressure penalty in
+    the symbol (a plausible oracle mistake) moves the result far outside the
+    1e-12 bar."""
+    N, K1D = 2, 4
+    h = 1.0 / K1D
+    theta = 2 * np.pi * np.array([1, 1]) / K1D
+    good = _block_symbol(N, h, theta, 1.0, 1.0)
+    bad = _block_symbol(N, h, theta, -1.0, 1.0)
+    q0 = np.random.default_rng(3).standard_normal(3 * (N + 1) ** 2).astype(complex)
+    a = _lsrk_matrix_steps(good, 1e-3, 5, q0, golden_dir)
+    b = _lsrk_matrix_steps(bad, 1e-3, 5, q0, golden_dir)
+    assert np.linalg.norm(a - b) > 1e-6 * np.linalg.norm(a)
