@@ -16,7 +16,10 @@ import os
 
 import numpy as np
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libwadg.so")
+# WADG_LIBRARY names another build of the same library (the host-sanitizer
+# build that the CPU tests load); by default the in-tree libwadg.so
+LIB_PATH = os.environ.get("WADG_LIBRARY") or os.path.join(
+    os.path.dirname(os.path.abspath(__file__)), "libwadg.so")
 
 WADG_OK = 0
 WADG_E_INVALID = -1

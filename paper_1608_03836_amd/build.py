@@ -30,6 +30,70 @@ FLAGS = [
 ]
 
 
+# Host-sanitizer build (CPU tests only): host code under AddressSanitizer
+# and UndefinedBehaviorSanitizer, device code unsanitized.
+SAN_DIR = os.path.join(PKG, "_build_san")
+SAN_LIB = os.path.join(SAN_DIR, "libwadg.so")
+SAN_FLAGS = "-Xarch_host -fsanitize=address -Xarch_host -fsanitize=undefined".split() + [
+    "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all"]
+
+
+def sanitizer_runtime():
+    """Path of the compiler's AddressSanitizer runtime (preloaded into the
+    Python process that loads the sanitized library)."""
+    out = subprocess.run([os.path.join(os.path.dirname(os.path.realpath(HIPCC)), "..", "llvm",
+                                       "bin", "clang"), "-print-file-name=libclang_rt.asan-x86_64.so"],
+                         check=True, capture_output=True, text=True).stdout.strip()
+    if not os.path.isabs(out) or not os.path.exists(out):
+        raise RuntimeError("AddressSanitizer runtime not found")
+    return out
+
+
+def _source_stamp(flags):
+    import hashlib
+    h = hashlib.sha256(" ".join(flags).encode())
+    for d, names in ((CSRC, sorted(os.listdir(CSRC))), (INCLUDE, sorted(os.listdir(INCLUDE)))):
+        for n in names:
+            with open(os.path.join(d, n), "rb") as f:
+                h.update(n.encode() + f.read())
+    return h.hexdigest()
+
+
+def build_host_sanitized(verbose=False, jobs=None):
+    """Build ``_build_san/libwadg.so``: every source with the host pass under
+    ASan + UBSan (-O1, frame pointers kept).  Skips the build when the
+    sources, headers and flags are unchanged since the last one.  Returns the
+    library path."""
+    from concurrent.futures import ThreadPoolExecutor
+    flags = ["--offload-arch=gfx950", "-O1", "-g1", "-std=c++17", "-fPIC",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"] + SAN_FLAGS
+    stamp = _source_stamp(flags)
+    stamp_file = os.path.join(SAN_DIR, "stamp")
+    if os.path.exists(SAN_LIB) and os.path.exists(stamp_file) and open(stamp_file).read() == stamp:
+        return SAN_LIB
+    os.makedirs(SAN_DIR, exist_ok=True)
+    common = flags + ["-I", INCLUDE, "-I", CSRC]
+
+    def compile_one(src):
+        obj = os.path.join(SAN_DIR, os.path.splitext(src)[0] + ".o")
+        lang = ["-x", "hip"] if src.endswith(".cpp") else []
+        cmd = [HIPCC] + common + ["-c"] + lang + [os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True, capture_output=not verbose)
+        return obj
+
+    n = jobs or min(len(SOURCES), max(1, os.cpu_count() or 1))
+    with ThreadPoolExecutor(max_workers=n) as ex:
+        objs = list(ex.map(compile_one, SOURCES))
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-shared-libsan"] + SAN_FLAGS + \
+        objs + ["-o", SAN_LIB]
+    subprocess.run(cmd, check=True, capture_output=not verbose)
+    with open(stamp_file, "w") as f:
+        f.write(stamp)
+    return SAN_LIB
+
+
 def build(verbose=False, extra_flags=(), jobs=None):
     """Compile every source into ``libwadg.so`` next to this file: one
     relocatable device-and-host object per source, compiled in parallel, then
