@@ -335,6 +335,24 @@ int wadg_norms_workspace_bytes(wadg_ctx ctx, int32_t S, size_t* bytes);
 int wadg_norms(wadg_ctx ctx, const double* A, const double* B, int32_t S, void* scratch,
                size_t scratch_bytes, double* out, void* stream);
 
+/* wadg_norms for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc)
+ * and hold no scratch buffer of their own: the same reduction, the same
+ * kernels and launch shape (so bitwise the same out as wadg_norms), run in
+ * a fixed 2,129,920-byte scratch array that the library keeps on every GPU
+ * it runs on until the process ends.  Its device address is taken once
+ * per device when the first context on that device is created.
+ *   A, B, S, out, stream: as for wadg_norms; S <= WADG_NORMS_NOALLOC_MAX_S.
+ * Allocates nothing.  Every call on one GPU shares that GPU's array, so
+ * calls that overlap on one GPU (other streams, other threads) race; calls
+ * on one stream do not.  The kernels overwrite every scratch value they
+ * read, so nothing is cleared between calls.  Synchronises `stream`.
+ * Returns WADG_E_INVALID, before any HIP call, for S above the maximum,
+ * and as wadg_norms otherwise. */
+#define WADG_NORMS_NOALLOC_MAX_S 1024
+int wadg_norms_noalloc(wadg_ctx ctx, const double* A, const double* B, int32_t S, double* out,
+                       void* stream);
+
 /* L2 norms with the element maps' Jacobians (the norm of Section 5.2's L2
  * errors), per slice:
  *   out[s][0] = ||A_s - B_s||_{L2},  out[s][1] = ||B_s||_{L2},

@@ -33,6 +33,7 @@ WADG_KERNEL_STREAMED = 1
 WADG_KERNEL_RESIDENT = 2
 WADG_KERNEL_SPLIT = 3
 WADG_CFL_MAX = 1.25
+WADG_NORMS_NOALLOC_MAX_S = 1024
 TILE_LANES = 64
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
@@ -90,6 +91,7 @@ def _load():
                                          ctypes.POINTER(ctypes.c_double), vp]),
         "wadg_norms_workspace_bytes": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.POINTER(sz)]),
         "wadg_norms": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, vp, sz, _c_double_p, vp]),
+        "wadg_norms_noalloc": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, _c_double_p, vp]),
         "wadg_l2_norms_workspace_bytes": (ctypes.c_int, [vp, ctypes.c_int32,
                                                          ctypes.POINTER(sz)]),
         "wadg_l2_norms": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, vp, sz, _c_double_p, vp]),
@@ -130,7 +132,8 @@ EXPORTED = ("wadg_quadrature_points", "wadg_geometry", "wadg_cfl_number", "wadg_
             "wadg_state_doubles", "wadg_workspace_bytes", "wadg_rhs", "wadg_integrate",
             "wadg_workspace_bytes_fp32", "wadg_integrate_fp32",
             "wadg_parareal_workspace_bytes", "wadg_parareal",
-            "wadg_norms_workspace_bytes", "wadg_norms", "wadg_l2_norms_workspace_bytes",
+            "wadg_norms_workspace_bytes", "wadg_norms", "wadg_norms_noalloc",
+            "wadg_l2_norms_workspace_bytes",
             "wadg_l2_norms", "wadg_set_schedule", "wadg_set_kernel", "wadg_kernel_in_use",
             "wadg_set_c2_scale", "wadg_adjoint_workspace_bytes", "wadg_forward_checkpoints",
             "wadg_adjoint", "wadg_batch_create", "wadg_batch_destroy", "wadg_batch_layout",
@@ -356,6 +359,17 @@ def wadg_norms(ctx, A, B, S, scratch, stream=None, check_finite=True, scratch_by
     sp, sb = _scratch(scratch, _need(wadg_norms_workspace_bytes, ctx, S), scratch_bytes)
     st = LIB.wadg_norms(ctx, _dev(A, n, "A"), _dev(B, n, "B"), int(S), sp, sb,
                         out.ctypes.data_as(_c_double_p), _stream(stream))
+    if st == WADG_E_NONFINITE and not check_finite:
+        return out
+    _check(st)
+    return out
+
+
+def wadg_norms_noalloc(ctx, A, B, S, stream=None, check_finite=True):
+    out = np.empty((int(S), 4))
+    n = int(S) * _slice_bytes(ctx)
+    st = LIB.wadg_norms_noalloc(ctx, _dev(A, n, "A"), _dev(B, n, "B"), int(S),
+                                out.ctypes.data_as(_c_double_p), _stream(stream))
     if st == WADG_E_NONFINITE and not check_finite:
         return out
     _check(st)

@@ -9,7 +9,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -88,6 +90,31 @@ using namespace wadg::host;
 namespace {
 
 constexpr int kNormBlocks = 64;
+
+// Scratch of wadg_norms_noalloc: the 64 x 4 partial sums and the 4 sums of
+// up to WADG_NORMS_NOALLOC_MAX_S slices.  Host code never uses this name as
+// an address: each device's copy is reached through the address that
+// hipGetSymbolAddress returns with that device current (noalloc_scratch).
+constexpr size_t kNoallocDoubles = (size_t)WADG_NORMS_NOALLOC_MAX_S * (kNormBlocks * 4 + 4);
+static __device__ __align__(256) double scratch[kNoallocDoubles];
+
+// The device address of `scratch` on device `dev`, which must be current;
+// looked up once per device and kept until the process ends.
+int noalloc_scratch(int dev, double** out) {
+  static std::mutex mu;
+  static std::map<int, double*> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(dev);
+  if (it == addr.end()) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                               "hipGetSymbolAddress(norms scratch)");
+    it = addr.emplace(dev, static_cast<double*>(p)).first;
+  }
+  *out = it->second;
+  return WADG_OK;
+}
 
 void free_ctx(wadg_ctx c) {
   if (!c) return;
@@ -207,6 +234,10 @@ int wadg_create(const wadg_mesh* mesh, int32_t device, wadg_ctx* out) {
       (e = hipStreamSynchronize(nullptr)) != hipSuccess) {
     free_ctx(c);
     return hip_fail(e, "wadg_create device setup");
+  }
+  if ((st = noalloc_scratch(dev, &c->d_noalloc)) != WADG_OK) {
+    free_ctx(c);
+    return st;
   }
   *out = c;
   return WADG_OK;
@@ -559,6 +590,21 @@ int wadg_norms(wadg_ctx ctx, const double* A, const double* B, int32_t S, void* 
   DeviceGuard guard(ctx->device);
   if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select the context's device");
   double* partials = static_cast<double*>(scratch);
+  return run_norms(ctx, A, B, S, partials, partials + (size_t)S * kNormBlocks * 4, out, stream);
+}
+
+int wadg_norms_noalloc(wadg_ctx ctx, const double* A, const double* B, int32_t S, double* out,
+                       void* stream) {
+  int st = check_norms_args(ctx, A, S, out);
+  if (st) return st;
+  if (S > WADG_NORMS_NOALLOC_MAX_S)
+    return fail(WADG_E_INVALID, "S = " + std::to_string(S) + " exceeds the static scratch (" +
+                                    std::to_string(WADG_NORMS_NOALLOC_MAX_S) +
+                                    " slices); use wadg_norms with caller scratch");
+  if (!ctx->d_noalloc) return fail(WADG_E_DEVICE, "the context has no static norms scratch");
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select the context's device");
+  double* partials = ctx->d_noalloc;
   return run_norms(ctx, A, B, S, partials, partials + (size_t)S * kNormBlocks * 4, out, stream);
 }
 

@@ -28,6 +28,7 @@ struct wadg_ctx_s {
   float* d_vol32 = nullptr;      // geometry rounded to FP32 (FP32-bulk path)
   float* d_face32 = nullptr;
   int32_t* d_nbr = nullptr;
+  double* d_noalloc = nullptr;    // this device's static norms scratch (not owned)
   // adjoint: a second stream (default priority) for the forward recompute
   // that overlaps the reverse sweep, and the events that order the two
   hipStream_t aux = nullptr;
