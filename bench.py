@@ -28,6 +28,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# wadg_kernel_in_use value -> kernel name (WADG_KERNEL_STREAMED .. _PIPE)
+KERNEL_NAMES = {1: "stage_kernel", 2: "resident_kernel", 3: "split_kernel", 4: "pipe_kernel"}
 
 
 def parse():
@@ -41,7 +43,8 @@ def parse():
     ap.add_argument("--tile-groups", type=int, default=None,
                     help="schedule: element groups per tile (default: library default)")
     ap.add_argument("--tile-slices", type=int, default=0)
-    ap.add_argument("--kernel", choices=("auto", "streamed", "resident", "split"), default="auto",
+    ap.add_argument("--kernel", choices=("auto", "streamed", "resident", "split", "pipe"),
+                    default="auto",
                     help="stage-kernel variant (default: the library's choice)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size before the timed "
@@ -194,8 +197,7 @@ def run_fp32(args):
                   {"workload": prob.name, "path": "fp32-bulk", "elements": K, "degree": N,
                    "nq1": prob.nq1, "slices": S, "lsrk_steps_per_slice": prob.nsteps,
                    "parallelism": "single-gpu"})
-    k = {W.WADG_KERNEL_STREAMED: "stage_kernel", W.WADG_KERNEL_RESIDENT: "resident_kernel",
-         W.WADG_KERNEL_SPLIT: "split_kernel"}[sol.kernel_in_use(fp32=True)]
+    k = KERNEL_NAMES[sol.kernel_in_use(fp32=True)]
     # the events bracket the whole call: 5 nsteps stage launches plus the two
     # FP64<->FP32 conversions at the ends of the sweep
     kname = f"{k}<float,{N},{prob.nq1},false>"
@@ -436,9 +438,9 @@ def main():
     if args.tile_groups:
         sol.set_schedule(args.tile_groups, args.tile_slices)
     sol.set_kernel({"auto": W.WADG_KERNEL_AUTO, "streamed": W.WADG_KERNEL_STREAMED,
-                    "resident": W.WADG_KERNEL_RESIDENT, "split": W.WADG_KERNEL_SPLIT}[args.kernel])
-    kname = {W.WADG_KERNEL_STREAMED: "stage_kernel", W.WADG_KERNEL_RESIDENT: "resident_kernel",
-             W.WADG_KERNEL_SPLIT: "split_kernel"}[sol.kernel_in_use()]
+                    "resident": W.WADG_KERNEL_RESIDENT, "split": W.WADG_KERNEL_SPLIT,
+                    "pipe": W.WADG_KERNEL_PIPE}[args.kernel])
+    kname = KERNEL_NAMES[sol.kernel_in_use()]
     kname += f"<double,{prob.N},{prob.nq1},false>"
     S, K, N = prob.S, prob.K, prob.N
     Q = sol.upload(prob.Q0)

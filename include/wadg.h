@@ -68,6 +68,7 @@ extern "C" {
 #define WADG_KERNEL_STREAMED 1  /* geometry read from global memory per item */
 #define WADG_KERNEL_RESIDENT 2  /* geometry held in LDS per element group    */
 #define WADG_KERNEL_SPLIT 3     /* one work item over four waves            */
+#define WADG_KERNEL_PIPE 4      /* persistent, pipelined over slice runs    */
 
 typedef struct wadg_ctx_s* wadg_ctx;
 typedef struct wadg_batch_s* wadg_batch;
@@ -395,6 +396,15 @@ int wadg_set_schedule(wadg_ctx ctx, int32_t groups_per_tile, int32_t slices_per_
  *     slices; ignores wadg_set_schedule.  Its FP64 geometry fits for N <= 2,
  *     or N = 3 with nq1 <= 5; elsewhere a RESIDENT request falls back to
  *     the streamed kernel for that precision.
+ *   WADG_KERNEL_PIPE: LSRK stages only (FP64 and FP32-bulk): one
+ *     512-thread workgroup per CU that owns one element group and a run of
+ *     its slices, keeps the group's geometry on chip for the whole run and
+ *     streams the next slice's input tile into LDS while computing the
+ *     current one; ignores wadg_set_schedule.  Needs two input tiles, the
+ *     metric planes, the face terms and one field of the load vector in
+ *     LDS (N <= 3 in FP64, every N in FP32); launches of fewer than two
+ *     slices, right-hand sides and the adjoint's launches take the split
+ *     kernel.
  *   WADG_KERNEL_AUTO (default): LSRK stages (FP64 and FP32) take the split
  *     kernel, right-hand-side launches the resident kernel where it fits,
  *     else the split kernel -- the fastest measured on MI355X.
@@ -402,8 +412,8 @@ int wadg_set_schedule(wadg_ctx ctx, int32_t groups_per_tile, int32_t slices_per_
  * launches (apply-A) take the split kernel under AUTO and SPLIT, else the
  * streamed kernel (the resident kernel has no apply-A mode).  Returns
  * WADG_E_INVALID for an
- * unknown value and WADG_E_UNSUPPORTED when the resident kernel is
- * requested for an (N, nq1) whose FP64 geometry does not fit. */
+ * unknown value and WADG_E_UNSUPPORTED when the resident or pipelined
+ * kernel is requested for an (N, nq1) whose FP64 data do not fit. */
 int wadg_set_kernel(wadg_ctx ctx, int32_t kernel);
 
 /* The kernel variant that `ctx` launches for LSRK stages (rhs == 0; FP64

@@ -13,7 +13,8 @@ from .binding import (  # noqa: F401
     wadg_workspace_bytes_fp32, wadg_integrate_fp32, wadg_parareal_workspace_bytes,
     wadg_parareal, wadg_norms_workspace_bytes, wadg_norms, wadg_l2_norms_workspace_bytes,
     wadg_l2_norms, wadg_set_schedule, wadg_set_kernel, wadg_kernel_in_use, WADG_KERNEL_AUTO,
-    WADG_KERNEL_STREAMED, WADG_KERNEL_RESIDENT, WADG_KERNEL_SPLIT, wadg_set_c2_scale,
+    WADG_KERNEL_STREAMED, WADG_KERNEL_RESIDENT, WADG_KERNEL_SPLIT, WADG_KERNEL_PIPE,
+    wadg_set_c2_scale,
     wadg_adjoint_workspace_bytes, wadg_forward_checkpoints, wadg_adjoint, wadg_status_string,
     wadg_last_error, MeshDesc, WadgError, tile_state, untile_state,
 )

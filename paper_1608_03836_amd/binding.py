@@ -32,6 +32,7 @@ WADG_KERNEL_AUTO = 0
 WADG_KERNEL_STREAMED = 1
 WADG_KERNEL_RESIDENT = 2
 WADG_KERNEL_SPLIT = 3
+WADG_KERNEL_PIPE = 4
 WADG_CFL_MAX = 1.25
 WADG_NORMS_NOALLOC_MAX_S = 1024
 TILE_LANES = 64

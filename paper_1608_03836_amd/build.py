@@ -16,11 +16,19 @@ LIB = os.path.join(PKG, "libwadg.so")
 DEMO = os.path.join(PKG, "abi_demo")
 
 SOURCES = ["reference.cpp", "stage_kernel.hip", "resident_kernel.hip", "split_kernel.hip",
+           "pipe_kernel.hip",
            "adjoint_kernel.hip",
            "norms_kernel.hip", "l2_kernel.hip", "convert_kernel.hip", "parareal_kernel.hip", "launch.hip",
            "api.hip", "api_adjoint.hip", "api_batch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+# Per-source flags.  The pipelined kernel loops over work items with every
+# operator entry a compile-time constant; machine-level loop-invariant code
+# motion would keep all of them in scalar registers across the loop and
+# spill most, so it is switched off for that file (the constants are then
+# rebuilt where they are used, as in the kernels without a loop).
+SOURCE_FLAGS = {"pipe_kernel.hip": ["-mllvm", "-disable-machine-licm"]}
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -77,7 +85,8 @@ def build_host_sanitized(verbose=False, jobs=None):
     def compile_one(src):
         obj = os.path.join(SAN_DIR, os.path.splitext(src)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmd = [HIPCC] + common + ["-c"] + lang + [os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC] + common + SOURCE_FLAGS.get(src, []) + ["-c"] + lang + \
+            [os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True, capture_output=not verbose)
@@ -107,7 +116,7 @@ def build(verbose=False, extra_flags=(), jobs=None):
         path = os.path.join(CSRC, src)
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmd = [HIPCC] + common + ["-c"] + lang + [path, "-o", obj]
+        cmd = [HIPCC] + common + SOURCE_FLAGS.get(src, []) + ["-c"] + lang + [path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

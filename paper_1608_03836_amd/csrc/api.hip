@@ -276,10 +276,13 @@ int wadg_set_schedule(wadg_ctx ctx, int32_t groups_per_tile, int32_t slices_per_
 int wadg_set_kernel(wadg_ctx ctx, int32_t kernel) {
   if (!ctx) return fail(WADG_E_INVALID, "context is NULL");
   if (kernel != WADG_KERNEL_AUTO && kernel != WADG_KERNEL_STREAMED &&
-      kernel != WADG_KERNEL_RESIDENT && kernel != WADG_KERNEL_SPLIT)
+      kernel != WADG_KERNEL_RESIDENT && kernel != WADG_KERNEL_SPLIT &&
+      kernel != WADG_KERNEL_PIPE)
     return fail(WADG_E_INVALID, "unknown kernel variant");
   if (kernel == WADG_KERNEL_RESIDENT && !wadg::resident_supported(ctx->N, ctx->nq1, false))
     return fail(WADG_E_UNSUPPORTED, "the element group's geometry does not fit in LDS");
+  if (kernel == WADG_KERNEL_PIPE && !wadg::pipe_supported(ctx->N, ctx->nq1, false))
+    return fail(WADG_E_UNSUPPORTED, "the pipelined kernel's tiles do not fit in LDS");
   ctx->kernel = kernel;
   return WADG_OK;
 }
@@ -296,7 +299,7 @@ int wadg_kernel_in_use(wadg_ctx ctx, int32_t rhs, int32_t fp32, int32_t* kernel)
   if (!ctx) return fail(WADG_E_INVALID, "context is NULL");
   if (!kernel) return fail(WADG_E_INVALID, "kernel is NULL");
   if (rhs && fp32) return fail(WADG_E_INVALID, "there is no FP32 right-hand-side launch");
-  *kernel = kernel_path(ctx, fp32 != 0, rhs ? wadg::kRhs : wadg::kStage);
+  *kernel = kernel_path(ctx, fp32 != 0, rhs ? wadg::kRhs : wadg::kStage, INT32_MAX);
   return WADG_OK;
 }
 

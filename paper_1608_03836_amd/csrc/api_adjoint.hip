@@ -132,7 +132,7 @@ int wadg_adjoint(wadg_ctx ctx, const double* chk, const double* seed, double* gr
   // ybar and rbar): one launch per stage instead of two, except at the
   // first stage of each slice (its residuals are recomputed just before)
   // and the last (no next stage in the slice).
-  const bool fused = kernel_path(ctx, false, wadg::kApplyA) == WADG_KERNEL_SPLIT;
+  const bool fused = kernel_path(ctx, false, wadg::kApplyA, 1) == WADG_KERNEL_SPLIT;
   const int G = ctx->groups();
   WADG_HIP(hipMemsetAsync(part, 0, (size_t)G * sizeof(double), hs));
   WADG_HIP(hipMemcpyAsync(yb, seed, sb, hipMemcpyDeviceToDevice, hs));
@@ -148,7 +148,7 @@ int wadg_adjoint(wadg_ctx ctx, const double* chk, const double* seed, double* gr
   // it runs on the context's second stream while the reverse sweep of slice
   // s runs on `stream`: ev_rec[b] = residual set b is ready, ev_rev[b] = the
   // reverse sweep that read set b is done.
-  const bool paired = fused && kernel_path(ctx, false, wadg::kStage) == WADG_KERNEL_SPLIT;
+  const bool paired = fused && kernel_path(ctx, false, wadg::kStage, 1) == WADG_KERNEL_SPLIT;
   hipStream_t aux = nullptr;
   if (!paired) {
     if (!ctx->aux) {

@@ -99,7 +99,10 @@ inline bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 }
 
 // The stage kernel that runs for this context, precision and launch mode.
-int kernel_path(wadg_ctx c, bool fp32, int mode);
+// The kernel variant for a launch of S slices (WADG_KERNEL_PIPE needs at
+// least kPipeMinSlices of them; S = 0 asks for a large launch).
+constexpr int32_t kPipeMinSlices = 2;
+int kernel_path(wadg_ctx c, bool fp32, int mode, int32_t S);
 // Launch one stage of `mode` with the context's kernel choice and the
 // alternating work-item order.
 int launch_stage(wadg_ctx c, int mode, bool fp32, const wadg::StageParams& p0, void* stream);

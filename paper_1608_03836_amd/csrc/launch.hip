@@ -27,7 +27,11 @@ const double kRkB[5] = {1432997174477.0 / 9575080441755.0,
 // geometry fits in LDS, else the split-work kernel; the adjoint's apply-A
 // launches take the split-work kernel (the resident kernel has no apply-A
 // mode, so an explicit RESIDENT or STREAMED choice runs them streamed).
-int kernel_path(wadg_ctx c, bool fp32, int mode) {
+int kernel_path(wadg_ctx c, bool fp32, int mode, int32_t S) {
+  if (mode == wadg::kStage && c->kernel == WADG_KERNEL_PIPE && S >= kPipeMinSlices &&
+      wadg::pipe_supported(c->N, c->nq1, fp32))
+    return WADG_KERNEL_PIPE;
+  if (c->kernel == WADG_KERNEL_PIPE) return WADG_KERNEL_SPLIT;  // its other launches
   const bool fits = wadg::resident_supported(c->N, c->nq1, fp32);
   if (mode == wadg::kApplyAMass) return WADG_KERNEL_SPLIT;   // split kernel only
   if (mode == wadg::kApplyA)   // no resident apply-A mode
@@ -41,7 +45,10 @@ int kernel_path(wadg_ctx c, bool fp32, int mode) {
 }
 
 int launch_stage(wadg_ctx c, int mode, bool fp32, const wadg::StageParams& p0, void* stream) {
-  const int path = kernel_path(c, fp32, mode);
+  const int path = kernel_path(c, fp32, mode, p0.S);
+  if (path == WADG_KERNEL_PIPE)
+    return fp32 ? wadg::launch_stage_pipe_fp32(c->N, c->nq1, p0, c->cus, stream)
+                : wadg::launch_stage_pipe(c->N, c->nq1, p0, c->cus, stream);
   // alternate the item order from one launch to the next (item_of)
   wadg::StageParams p = p0;
   c->order_flip ^= 1;

@@ -138,6 +138,12 @@ int launch_to_fp64(const float* in, double* out, size_t n, void* stream);
 // Device copy of n doubles as a kernel (capture-safe; no runtime copy node).
 int launch_copy(const double* in, double* out, size_t n, void* stream);
 bool stage_supported(int N, int nq);
+// Persistent pipelined kernel (pipe_kernel.hip): one eight-wave workgroup
+// per (element group, slice run), grid = nEG * chunks with chunks chosen
+// from the CU count; LSRK stage mode only, where its LDS fits.
+bool pipe_supported(int N, int nq, bool fp32);
+int launch_stage_pipe(int N, int nq, const StageParams& p, int cus, void* stream);
+int launch_stage_pipe_fp32(int N, int nq, const StageParams& p, int cus, void* stream);
 
 // Batched stage over many independent problems (same N, nq, penalties):
 // one work item = one 64-element group of one slice of one problem.

@@ -129,7 +129,7 @@ class Solver:
         B.wadg_set_schedule(self.ctx, groups_per_tile, slices_per_tile)
 
     def set_kernel(self, kernel):
-        """WADG_KERNEL_AUTO, _STREAMED, _RESIDENT or _SPLIT (see wadg_set_kernel)."""
+        """WADG_KERNEL_AUTO, _STREAMED, _RESIDENT, _SPLIT or _PIPE (see wadg_set_kernel)."""
         B.wadg_set_kernel(self.ctx, kernel)
 
     def kernel_in_use(self, rhs=False, fp32=False):
