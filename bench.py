@@ -54,6 +54,13 @@ def parse():
     return ap.parse_args()
 
 
+def kernel_choice(W, name):
+    """--kernel value -> WADG_KERNEL_* constant."""
+    return {"auto": W.WADG_KERNEL_AUTO, "streamed": W.WADG_KERNEL_STREAMED,
+            "resident": W.WADG_KERNEL_RESIDENT, "split": W.WADG_KERNEL_SPLIT,
+            "pipe": W.WADG_KERNEL_PIPE}[name]
+
+
 def stage_bytes(K, S, N, nq1, word=8):
     """Algorithmic HBM bytes of one stage launch, averaged over the 5 stages:
     per element and slice, read Q_in and write Q_out and res (3 (N+1)^2
@@ -171,6 +178,7 @@ def run_fp32(args):
     from workloads import make_problem
     prob = make_problem(args.workload)
     sol = W.Solver.from_problem(prob)
+    sol.set_kernel(kernel_choice(W, args.kernel))
     S, K, N = prob.S, prob.K, prob.N
     stream = torch.cuda.current_stream()
     Q64 = sol.upload(prob.Q0)
@@ -437,9 +445,7 @@ def main():
     sol = W.Solver.from_problem(prob)
     if args.tile_groups:
         sol.set_schedule(args.tile_groups, args.tile_slices)
-    sol.set_kernel({"auto": W.WADG_KERNEL_AUTO, "streamed": W.WADG_KERNEL_STREAMED,
-                    "resident": W.WADG_KERNEL_RESIDENT, "split": W.WADG_KERNEL_SPLIT,
-                    "pipe": W.WADG_KERNEL_PIPE}[args.kernel])
+    sol.set_kernel(kernel_choice(W, args.kernel))
     kname = KERNEL_NAMES[sol.kernel_in_use()]
     kname += f"<double,{prob.N},{prob.nq1},false>"
     S, K, N = prob.S, prob.K, prob.N

@@ -56,9 +56,15 @@ struct Pipe {
   static constexpr unsigned tile_alloc = rows * 1024u / sizeof(R);
   static constexpr unsigned metric = 4u * NQ2 * kWave;         // planes 0..3 of the geometry
   static constexpr unsigned xf = 4u * 3 * NP1 * kWave;         // face terms [4][3][NP1][64]
-  static constexpr unsigned bv = (unsigned)NP * kWave;         // b_v [NP][64]
-  static constexpr size_t lds_bytes = (2 * tile_alloc + metric + xf + bv) * sizeof(R);
-  static constexpr bool fits = lds_bytes <= 160u * 1024u;
+  static constexpr unsigned wts = 2u * NQ2 * kWave;            // mass weights [2][NQ2][64]
+  static constexpr size_t lds_base = (2 * tile_alloc + metric + xf) * sizeof(R);
+  // the mass weights (c^2/J scaled, 1/J) live in LDS where they fit, else
+  // in the registers of the update waves
+  static constexpr bool weights_in_lds = lds_base + wts * sizeof(R) <= 160u * 1024u;
+  static constexpr size_t lds_bytes = lds_base + (weights_in_lds ? wts * sizeof(R) : 0);
+  // instantiated only with the weights in LDS: the update waves' registers
+  // are needed for the nodal values
+  static constexpr bool fits = weights_in_lds;
 };
 
 // Lane-parallel copy of `n16` 16-byte chunks from global memory into LDS by
@@ -83,6 +89,95 @@ __device__ __forceinline__ void tile_to_lds(rsrc_t src, void* dst, int lane) {
 // Wait until every vector memory operation of this wave has completed
 // (vmcnt = 0; the other counters left at their maxima).
 __device__ __forceinline__ void wait_vm_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// Component C (1: u, 2: v) of the velocity volume term of quadrature
+// column i: the operations velocity_volume_column performs for that
+// component, in the same order, without the other component's.
+template <typename R, int N, int NQ, int C, typename FP>
+__device__ __forceinline__ void velocity_component_column(int i, const FP& P,
+                                                          const R (&g)[4][NQ],
+                                                          R (&b)[(N + 1) * (N + 1)]) {
+  constexpr ct::Ops<R, N, NQ> T = ct::make_ops<R, N, NQ>();
+  constexpr int NP1 = N + 1;
+  R td[NP1], tp[NP1];
+#pragma unroll
+  for (int bb = 0; bb < NP1; ++bb) {
+    R sd = R(0), sp = R(0);
+#pragma unroll
+    for (int a = 0; a < NP1; ++a) {
+      const R pa = P(a + NP1 * bb);
+      sd = mad(T.D[i][a], pa, sd);
+      sp = mad(T.V[i][a], pa, sp);
+    }
+    td[bb] = sd;
+    tp[bb] = sp;
+  }
+  R cc[NP1];
+#pragma unroll
+  for (int bb = 0; bb < NP1; ++bb) cc[bb] = R(0);
+#pragma unroll
+  for (int j = 0; j < NQ; ++j) {
+    R pr = R(0), ps = R(0);
+#pragma unroll
+    for (int bb = 0; bb < NP1; ++bb) {
+      pr = mad(T.V[j][bb], td[bb], pr);
+      ps = mad(T.D[j][bb], tp[bb], ps);
+    }
+    const R G = C == 1 ? mad(g[0][j], pr, g[2][j] * ps) : mad(g[1][j], pr, g[3][j] * ps);
+#pragma unroll
+    for (int bb = 0; bb < NP1; ++bb) cc[bb] = mad(T.V[j][bb], G, cc[bb]);
+  }
+#pragma unroll
+  for (int bb = 0; bb < NP1; ++bb)
+#pragma unroll
+    for (int a = 0; a < NP1; ++a) b[a + NP1 * bb] = mad(-T.V[i][a], cc[bb], b[a + NP1 * bb]);
+}
+
+// The mass inverse of wadg_inverse with every accumulator formed by the
+// same operations in the same order, but all quadrature columns' partial
+// results computed before any is projected back: the columns proceed in
+// parallel instead of one after another, for a wave that has its SIMD to
+// itself.
+template <typename R, int N, int NQ>
+__device__ __forceinline__ void wadg_inverse_wide(const R (&b)[(N + 1) * (N + 1)],
+                                                  const R (&w)[NQ * NQ],
+                                                  R (&dq)[(N + 1) * (N + 1)]) {
+  constexpr ct::Ops<R, N, NQ> T = ct::make_ops<R, N, NQ>();
+  constexpr int NP1 = N + 1;
+  R t[NQ][NP1];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i)
+#pragma unroll
+    for (int bb = 0; bb < NP1; ++bb) {
+      R acc = R(0);
+#pragma unroll
+      for (int a = 0; a < NP1; ++a) acc = mad(T.Vt[i][a], b[a + NP1 * bb], acc);
+      t[i][bb] = acc;
+    }
+  R c[NQ][NP1];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+#pragma unroll
+    for (int bb = 0; bb < NP1; ++bb) c[i][bb] = R(0);
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) {
+      R rq = R(0);
+#pragma unroll
+      for (int bb = 0; bb < NP1; ++bb) rq = mad(T.Vt[j][bb], t[i][bb], rq);
+      rq *= w[i + NQ * j];
+#pragma unroll
+      for (int bb = 0; bb < NP1; ++bb) c[i][bb] = mad(T.P[bb][j], rq, c[i][bb]);
+    }
+  }
+#pragma unroll
+  for (int n = 0; n < NP1 * NP1; ++n) dq[n] = R(0);
+#pragma unroll
+  for (int i = 0; i < NQ; ++i)
+#pragma unroll
+    for (int bb = 0; bb < NP1; ++bb)
+#pragma unroll
+      for (int a = 0; a < NP1; ++a) dq[a + NP1 * bb] = mad(T.P[a][i], c[i][bb], dq[a + NP1 * bb]);
+}
 
 // Face wave of face F: its factors and neighbour offsets held for the
 // whole run, its traces gathered one slice ahead.  Barriers as the other
@@ -125,7 +220,113 @@ __device__ __forceinline__ void pipe_face_role(const StageParams& p, const Stage
       gather_trace<R, N>(
           make_rsrc(Qin + (size_t)(s0 + it + 1) * slice_vals, (unsigned)(slice_vals * sizeof(R))),
           nbo, F, tr);
-    __syncthreads();                                         // face terms, b_v ready
+    __syncthreads();                                         // face terms ready
+    __syncthreads();                                         // item done
+  }
+}
+
+// Update wave of field C (0: p, 1: u, 2: v): its volume term (the
+// pressure term, or one component of the velocity term), then -- once the
+// face terms are in LDS -- the face terms in face order 0..3, the mass
+// inverse and the stage update of its field.  Mass weights c^2/J (times the
+// c^2 scale) or 1/J held for the whole run; the residual requested one
+// slice ahead.  Barriers: one after the prologue, two per item.
+template <typename R, int N, int NQ, int C>
+__device__ __forceinline__ void pipe_update_role(const StageParams& p, const StageScalars<R>& k,
+                                                 int g, int s0, int nit, int lane, unsigned kb,
+                                                 bool active, rsrc_t vol,
+                                                 R (*tq)[Pipe<R, N, NQ>::tile_alloc],
+                                                 const R* xm, const R* xf, R* xw) {
+  using L = Pipe<R, N, NQ>;
+  constexpr int NP1 = L::NP1, NP = L::NP, NQ2 = L::NQ2;
+  constexpr unsigned tile = L::tile;
+  constexpr unsigned KP = kWave * sizeof(R);
+  R* Qout = static_cast<R*>(p.Qout);
+  R* res = static_cast<R*>(p.res);
+  R* resw = static_cast<R*>(p.res_out ? p.res_out : p.res);
+  const size_t slice_vals = (size_t)p.nEG * tile;
+  auto grp = [&](int s) { return (size_t)s * slice_vals + (size_t)g * tile; };
+  constexpr bool kLdsW = L::weights_in_lds;
+  // mass weights: c^2/J times the c^2 scale (p) or 1/J (u, v); in LDS the
+  // pressure wave writes plane 0 and the u wave plane 1
+  R wq[kLdsW ? 1 : NQ2];
+  if constexpr (kLdsW) {
+    if constexpr (C != 2) {
+#pragma unroll
+      for (int q = 0; q < NQ2; ++q) {
+        R x = ldr<R>(vol, kb, ((C == 0 ? 4 : 5) * NQ2 + q) * KP);
+        if constexpr (C == 0) x *= k.c2s;
+        xw[(C * NQ2 + q) * kWave + lane] = x;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < NQ2; ++q) wq[q] = ldr<R>(vol, kb, ((C == 0 ? 4 : 5) * NQ2 + q) * KP);
+    if constexpr (C == 0) {
+#pragma unroll
+      for (int q = 0; q < NQ2; ++q) wq[q] *= k.c2s;
+    }
+  }
+  R resv[NP];
+  load_res<R, NP, kStage>(k, make_rsrc(res + grp(s0), tile * sizeof(R)), C, kb, resv);
+  __syncthreads();                                           // prologue done
+  for (int it = 0; it < nit; ++it) {
+    const int s = s0 + it;
+    const R* t = tq[it & 1];
+    auto Pt = [&](int n) { return t[n * kWave + lane]; };
+    // the nodal values the volume term reads, in registers for all of its
+    // columns: u and v (pressure), p (velocity)
+    R x0[NP], x1[C == 0 ? NP : 1];
+#pragma unroll
+    for (int n = 0; n < NP; ++n) {
+      x0[n] = t[((C == 0 ? NP : 0) + n) * kWave + lane];
+      if constexpr (C == 0) x1[n] = t[(2 * NP + n) * kWave + lane];
+    }
+    auto X0 = [&](int n) { return x0[n]; };
+    auto X1 = [&](int n) { return x1[n]; };
+    R b[NP];
+#pragma unroll
+    for (int n = 0; n < NP; ++n) b[n] = R(0);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      // this column's metric terms, requested before its first products
+      // (which need only the nodal values) so that they arrive meanwhile
+      R gc[4][NQ];
+      order();
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int jj = 0; jj < NQ; ++jj)
+          if (C == 0 || q == C - 1 || q == C + 1)
+            gc[q][jj] = xm[(q * NQ2 + i + NQ * jj) * kWave + lane];
+          else
+            gc[q][jj] = R(0);
+      if constexpr (C == 0)
+        pressure_volume_column<R, N, NQ>(i, X0, X1, gc, b);
+      else
+        velocity_component_column<R, N, NQ, C>(i, X0, gc, b);
+      pin(b);
+    }
+    __syncthreads();                                         // face terms ready
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+      for (int m = 0; m < NP1; ++m)
+        b[fnode<N>(f, m)] += xf[((f * 3 + C) * NP1 + m) * kWave + lane];
+    R dq[NP];
+    if constexpr (kLdsW) {
+      R wl[NQ2];
+#pragma unroll
+      for (int q = 0; q < NQ2; ++q) wl[q] = xw[((C == 0 ? 0 : 1) * NQ2 + q) * kWave + lane];
+      wadg_inverse_wide<R, N, NQ>(b, wl, dq);
+    } else {
+      wadg_inverse_wide<R, N, NQ>(b, wq, dq);
+    }
+    const rsrc_t qo = make_rsrc(Qout + grp(s), tile * sizeof(R));
+    const rsrc_t rw = make_rsrc(resw + grp(s), tile * sizeof(R));
+    finish_field<R, NP, kStage>(k, qo, rw, Pt, C, kb, active, resv, dq);
+    if (it + 1 < nit)
+      load_res<R, NP, kStage>(k, make_rsrc(res + grp(s + 1), tile * sizeof(R)), C, kb, resv);
     __syncthreads();                                         // item done
   }
 }
@@ -134,17 +335,19 @@ __device__ __forceinline__ void pipe_face_role(const StageParams& p, const Stage
 
 // Workgroup b: element group g and slices [s0, s1) (see launch below);
 // grid = nEG * chunks, chunk j of group g holds slices
-// [j S / chunks, (j + 1) S / chunks).  LSRK stage mode only.
+// [j S / chunks, (j + 1) S / chunks).  LSRK stage mode only.  Waves 0..2
+// (one per SIMD) carry the volume terms and the updates of p, u, v; wave 4
+// shares SIMD 0 with the pressure wave as the loader; waves 3, 5, 6, 7 the
+// faces 0..3.
 template <typename R, int N, int NQ>
 __global__ __launch_bounds__(8 * kWave) void pipe_kernel(const StageParams p, int chunks) {
   using L = Pipe<R, N, NQ>;
-  constexpr int NP1 = L::NP1, NP = L::NP, NQ2 = L::NQ2;
-  constexpr unsigned tile = L::tile;
+  constexpr int NQ2 = L::NQ2;
   constexpr unsigned KP = kWave * sizeof(R);
   __shared__ __attribute__((aligned(1024))) R tq[2][L::tile_alloc];
   __shared__ __attribute__((aligned(16))) R xm[L::metric];
   __shared__ __attribute__((aligned(16))) R xf[L::xf];
-  __shared__ __attribute__((aligned(16))) R xv[L::bv];
+  __shared__ __attribute__((aligned(16))) R xw[L::weights_in_lds ? L::wts : 1];
 
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -163,116 +366,45 @@ __global__ __launch_bounds__(8 * kWave) void pipe_kernel(const StageParams p, in
   if (nit <= 0) return;
   const bool active = g * kWave + lane < p.K;
   const StageScalars<R> k = stage_scalars<R>(p);
-
   const R* Qin = static_cast<const R*>(p.Qin);
-  R* Qout = static_cast<R*>(p.Qout);
-  R* res = static_cast<R*>(p.res);
-  R* resw = static_cast<R*>(p.res_out ? p.res_out : p.res);
-  const size_t slice_vals = (size_t)p.nEG * tile;
-  auto grp = [&](int s) { return (size_t)s * slice_vals + (size_t)g * tile; };
+  const size_t slice_vals = (size_t)p.nEG * L::tile;
   const rsrc_t vol = make_rsrc(static_cast<const R*>(p.vol) + (size_t)g * 6 * NQ2 * kWave,
                                6u * NQ2 * KP);
   const rsrc_t face = make_rsrc(static_cast<const R*>(p.face) + (size_t)g * 12 * NQ * kWave,
                                 12u * NQ * KP);
+  constexpr int kLoader = 4;
 
-  auto P = [&](const R* t, int n) { return t[n * kWave + lane]; };
-
-  // ---------------------------------------------------------------- prologue
-  // metric planes 0..3 of the group into LDS (all waves but the loader)
-  if (wave < 7) copy_to_lds(vol, xm, L::metric * sizeof(R) / 16u, tid, 7 * kWave);
-  if (wave == 7)
-    tile_to_lds<L::rows>(make_rsrc(Qin + grp(s0), L::tile_bytes), tq[0], lane);
-
-  // ------------------------------------------------------------------ roles
-  if (wave == 0 || wave == 1 || wave == 6) {
-    // update waves: field c = 0 (p), 1 (u), 2 (v).  Mass weights c^2/J
-    // (times the c^2 scale) or 1/J, held for the whole run.
-    const int c = wave == 6 ? 2 : wave;
-    R wq[NQ2];
-#pragma unroll
-    for (int q = 0; q < NQ2; ++q) wq[q] = ldr<R>(vol, kb, ((c == 0 ? 4 : 5) * NQ2 + q) * KP);
-    if (c == 0) {
-#pragma unroll
-      for (int q = 0; q < NQ2; ++q) wq[q] *= k.c2s;
-    }
-    R resv[NP];
-    load_res<R, NP, kStage>(k, make_rsrc(res + grp(s0), tile * sizeof(R)), c, kb, resv);
-    __syncthreads();                                         // prologue done
-    for (int it = 0; it < nit; ++it) {
-      const int s = s0 + it;
-      const R* t = tq[it & 1];
-      auto Pt = [&](int n) { return P(t, n); };
-      auto Ut = [&](int n) { return P(t, NP + n); };
-      auto Vt = [&](int n) { return P(t, 2 * NP + n); };
-      R b0[NP], b1[NP];
-      if (c == 0) {
-#pragma unroll
-        for (int n = 0; n < NP; ++n) b0[n] = R(0);
-#pragma unroll
-        for (int i = 0; i < NQ; ++i) {
-          R gc[4][NQ];
-          order();
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int jj = 0; jj < NQ; ++jj) gc[q][jj] = xm[(q * NQ2 + i + NQ * jj) * kWave + lane];
-          pressure_volume_column<R, N, NQ>(i, Ut, Vt, gc, b0);
-          pin(b0);
-        }
-      } else if (c == 1) {
-#pragma unroll
-        for (int n = 0; n < NP; ++n) b0[n] = b1[n] = R(0);
-#pragma unroll
-        for (int i = 0; i < NQ; ++i) {
-          R gc[4][NQ];
-          order();
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int jj = 0; jj < NQ; ++jj) gc[q][jj] = xm[(q * NQ2 + i + NQ * jj) * kWave + lane];
-          velocity_volume_column<R, N, NQ>(i, Pt, gc, b0, b1);
-          pin(b0);
-          pin(b1);
-        }
-#pragma unroll
-        for (int n = 0; n < NP; ++n) xv[n * kWave + lane] = b1[n];
-      }
-      __syncthreads();                                       // face terms, b_v ready
-      if (c == 2) {
-#pragma unroll
-        for (int n = 0; n < NP; ++n) b0[n] = xv[n * kWave + lane];
-      }
-#pragma unroll
-      for (int f = 0; f < 4; ++f)
-#pragma unroll
-        for (int m = 0; m < NP1; ++m)
-          b0[fnode<N>(f, m)] += xf[((f * 3 + c) * NP1 + m) * kWave + lane];
-      R dq[NP];
-      wadg_inverse<R, N, NQ>(b0, wq, dq);
-      const rsrc_t qo = make_rsrc(Qout + grp(s), tile * sizeof(R));
-      const rsrc_t rw = make_rsrc(resw + grp(s), tile * sizeof(R));
-      finish_field<R, NP, kStage>(k, qo, rw, Pt, c, kb, active, resv, dq);
-      if (it + 1 < nit)
-        load_res<R, NP, kStage>(k, make_rsrc(res + grp(s + 1), tile * sizeof(R)), c, kb, resv);
-      __syncthreads();                                       // item done
-    }
-  } else if (wave == 7) {
-    // loader: the next slice's tile while this one is computed
+  // prologue: metric planes 0..3 of the group into LDS (every wave but the
+  // loader), the first tile by the loader
+  if (wave != kLoader)
+    copy_to_lds(vol, xm, L::metric * sizeof(R) / 16u, (wave < kLoader ? wave : wave - 1) * kWave + lane,
+                7 * kWave);
+  if (wave == 0) {
+    pipe_update_role<R, N, NQ, 0>(p, k, g, s0, nit, lane, kb, active, vol, tq, xm, xf, xw);
+  } else if (wave == 1) {
+    pipe_update_role<R, N, NQ, 1>(p, k, g, s0, nit, lane, kb, active, vol, tq, xm, xf, xw);
+  } else if (wave == 2) {
+    pipe_update_role<R, N, NQ, 2>(p, k, g, s0, nit, lane, kb, active, vol, tq, xm, xf, xw);
+  } else if (wave == kLoader) {
+    // the next slice's tile while this one is computed
+    tile_to_lds<L::rows>(make_rsrc(Qin + (size_t)s0 * slice_vals + (size_t)g * L::tile,
+                                   L::tile_bytes), tq[0], lane);
     wait_vm_all();
     __syncthreads();                                         // prologue done
     for (int it = 0; it < nit; ++it) {
       if (it + 1 < nit)
-        tile_to_lds<L::rows>(make_rsrc(Qin + grp(s0 + it + 1), L::tile_bytes), tq[(it + 1) & 1],
-                             lane);
-      __syncthreads();                                       // face terms, b_v ready
+        tile_to_lds<L::rows>(make_rsrc(Qin + (size_t)(s0 + it + 1) * slice_vals +
+                                           (size_t)g * L::tile, L::tile_bytes),
+                             tq[(it + 1) & 1], lane);
+      __syncthreads();                                       // face terms ready
       wait_vm_all();                                         // next tile in LDS
       __syncthreads();                                       // item done
     }
-  } else if (wave == 2) {
-    pipe_face_role<R, N, NQ, 0>(p, k, g, s0, nit, lane, kb, face, tq, xf);
   } else if (wave == 3) {
+    pipe_face_role<R, N, NQ, 0>(p, k, g, s0, nit, lane, kb, face, tq, xf);
+  } else if (wave == 5) {
     pipe_face_role<R, N, NQ, 1>(p, k, g, s0, nit, lane, kb, face, tq, xf);
-  } else if (wave == 4) {
+  } else if (wave == 6) {
     pipe_face_role<R, N, NQ, 2>(p, k, g, s0, nit, lane, kb, face, tq, xf);
   } else {
     pipe_face_role<R, N, NQ, 3>(p, k, g, s0, nit, lane, kb, face, tq, xf);
@@ -295,7 +427,10 @@ int launch_nq(const StageParams& p, int cus, void* stream) {
   if constexpr (!Pipe<R, N, NQ>::fits) {
     return (int)hipErrorInvalidValue;
   } else {
-    const int chunks = pipe_chunks(p.nEG, p.S, cus);
+    // two workgroups per CU where two fit in LDS (16 waves of at most 128
+    // registers: FP32), else one
+    const int per_cu = Pipe<R, N, NQ>::lds_bytes <= 80u * 1024u ? 2 : 1;
+    const int chunks = pipe_chunks(p.nEG, p.S, cus * per_cu);
     if ((int64_t)p.nEG * chunks >= (1LL << 31)) return (int)hipErrorInvalidValue;
     hipLaunchKernelGGL((pipe_kernel<R, N, NQ>), dim3(p.nEG * chunks), dim3(8 * kWave), 0,
                        static_cast<hipStream_t>(stream), p, chunks);

@@ -2,7 +2,7 @@
 split kernel (bitwise: same arithmetic in the same order) and against the
 oracle, on shapes that exercise its slice runs -- one run per group and
 several, runs of one slice (no prefetch), more runs than slices, a ragged
-last element group, N = 1..3 with every quadrature that fits -- in FP64 and
+last element group, N = 1..3 with quadratures that fit -- in FP64 and
 FP32-bulk; and its selection rules."""
 
 import numpy as np
@@ -32,7 +32,7 @@ CASES = [  # (N, nq1 - N, K1D, S, nsteps)
     (3, 2, 9, 7, 3),      # 2 groups (ragged second) x 7 runs of one slice
     (3, 2, 128, 3, 1),    # 256 groups x 1 run of 3 slices
     (3, 1, 17, 64, 1),    # 5 groups (last ragged) x 51 runs
-    (3, 3, 9, 5, 2),
+    (2, 2, 9, 6, 2),
     (2, 3, 9, 5, 2),
     (1, 1, 8, 3, 2),
     (1, 2, 24, 300, 1),   # 9 groups x 28 runs of 10-11 slices
@@ -85,7 +85,8 @@ def test_pipe_matches_oracle(W):
 def test_pipe_selection_rules(W):
     """PIPE applies to LSRK stages of two or more slices; right-hand sides
     and one-slice sweeps take the split kernel; PIPE is refused where its
-    FP64 tiles do not fit in LDS (N = 4)."""
+    FP64 tiles, metric planes and weights do not fit in LDS (N = 4, and
+    N = 3 with six quadrature points per direction)."""
     _print_case(test="pipe-selection")
     mesh = periodic_quad_mesh(4, 3, eps=0.05, warp="skew")
     s = W.Solver(mesh)
@@ -99,8 +100,9 @@ def test_pipe_selection_rules(W):
     s.set_kernel(W.WADG_KERNEL_SPLIT)
     s.integrate(b, 1, 1e-3, 2)
     assert np.array_equal(s.download(a, 1), s.download(b, 1))
-    m4 = periodic_quad_mesh(4, 4, eps=0.05, warp="skew")
-    s4 = W.Solver(m4)
-    with pytest.raises(W.WadgError) as e:
-        s4.set_kernel(W.WADG_KERNEL_PIPE)
-    assert e.value.status == W.binding.WADG_E_UNSUPPORTED
+    for N, nq1 in ((4, 6), (3, 6)):
+        m = periodic_quad_mesh(4, N, eps=0.05, warp="skew")
+        sn = W.Solver(m, nq1=nq1)
+        with pytest.raises(W.WadgError) as e:
+            sn.set_kernel(W.WADG_KERNEL_PIPE)
+        assert e.value.status == W.binding.WADG_E_UNSUPPORTED
