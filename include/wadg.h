@@ -405,8 +405,9 @@ int wadg_set_schedule(wadg_ctx ctx, int32_t groups_per_tile, int32_t slices_per_
  *     LDS (N <= 3 in FP64, every N in FP32); launches of fewer than two
  *     slices, right-hand sides and the adjoint's launches take the split
  *     kernel.
- *   WADG_KERNEL_AUTO (default): LSRK stages (FP64 and FP32) take the split
- *     kernel, right-hand-side launches the resident kernel where it fits,
+ *   WADG_KERNEL_AUTO (default): LSRK stages (FP64 and FP32) of two or more
+ *     slices take the pipelined kernel where it fits, else the split
+ *     kernel; right-hand-side launches the resident kernel where it fits,
  *     else the split kernel -- the fastest measured on MI355X.
  * All variants give bitwise-identical results.  The adjoint's operator
  * launches (apply-A) take the split kernel under AUTO and SPLIT, else the

@@ -22,14 +22,16 @@ const double kRkB[5] = {1432997174477.0 / 9575080441755.0,
 
 // Kernel variant that runs for this context, precision and launch mode.
 // Automatic choice, from measurement on MI355X (64x64 and 128x128
-// elements, N = 3, FP64 and FP32): LSRK stages take the split-work kernel;
-// right-hand-side launches take the resident-geometry kernel where the
-// geometry fits in LDS, else the split-work kernel; the adjoint's apply-A
-// launches take the split-work kernel (the resident kernel has no apply-A
-// mode, so an explicit RESIDENT or STREAMED choice runs them streamed).
+// elements, N = 3, FP64 and FP32): LSRK stages of two or more slices take
+// the pipelined kernel where its LDS plan fits, else the split-work
+// kernel; right-hand-side launches take the resident-geometry kernel where
+// the geometry fits in LDS, else the split-work kernel; the adjoint's
+// apply-A launches take the split-work kernel (the resident kernel has no
+// apply-A mode, so an explicit RESIDENT or STREAMED choice runs them
+// streamed).
 int kernel_path(wadg_ctx c, bool fp32, int mode, int32_t S) {
-  if (mode == wadg::kStage && c->kernel == WADG_KERNEL_PIPE && S >= kPipeMinSlices &&
-      wadg::pipe_supported(c->N, c->nq1, fp32))
+  if (mode == wadg::kStage && (c->kernel == WADG_KERNEL_PIPE || c->kernel == WADG_KERNEL_AUTO) &&
+      S >= kPipeMinSlices && wadg::pipe_supported(c->N, c->nq1, fp32))
     return WADG_KERNEL_PIPE;
   if (c->kernel == WADG_KERNEL_PIPE) return WADG_KERNEL_SPLIT;  // its other launches
   const bool fits = wadg::resident_supported(c->N, c->nq1, fp32);

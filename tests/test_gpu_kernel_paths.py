@@ -86,15 +86,17 @@ def test_resident_matches_oracle_many_slices_per_pair(W):
 
 
 def test_kernel_selection_rules(W):
-    """AUTO: LSRK stages (FP64 and FP32) take the split kernel, wadg_rhs the
-    resident kernel where the geometry fits in LDS (N = 3 with nq1 <= 5),
-    else the split kernel.  An explicit choice applies to every launch; the
-    resident kernel is refused where the FP64 geometry does not fit."""
+    """AUTO: LSRK stages (FP64 and FP32) take the pipelined kernel where its
+    LDS plan fits (N = 3 with nq1 <= 5 in FP64; every nq1 in FP32), else the
+    split kernel; wadg_rhs the resident kernel where the geometry fits in
+    LDS (N = 3 with nq1 <= 5), else the split kernel.  An explicit choice
+    applies to every launch; the resident kernel is refused where the FP64
+    geometry does not fit."""
     _print_case(test="kernel-selection")
     mesh = periodic_quad_mesh(4, 3, eps=0.05, warp="skew")
     s5 = W.Solver(mesh, nq1=5)
-    assert s5.kernel_in_use() == W.WADG_KERNEL_SPLIT
-    assert s5.kernel_in_use(fp32=True) == W.WADG_KERNEL_SPLIT
+    assert s5.kernel_in_use() == W.WADG_KERNEL_PIPE
+    assert s5.kernel_in_use(fp32=True) == W.WADG_KERNEL_PIPE
     assert s5.kernel_in_use(rhs=True) == W.WADG_KERNEL_RESIDENT
     for kern in (W.WADG_KERNEL_RESIDENT, W.WADG_KERNEL_STREAMED, W.WADG_KERNEL_SPLIT):
         s5.set_kernel(kern)
@@ -103,6 +105,7 @@ def test_kernel_selection_rules(W):
         assert s5.kernel_in_use(rhs=True) == kern
     s6 = W.Solver(mesh, nq1=6)
     assert s6.kernel_in_use() == W.WADG_KERNEL_SPLIT
+    assert s6.kernel_in_use(fp32=True) == W.WADG_KERNEL_PIPE
     assert s6.kernel_in_use(rhs=True) == W.WADG_KERNEL_SPLIT
     with pytest.raises(W.WadgError) as e:
         s6.set_kernel(W.WADG_KERNEL_RESIDENT)

@@ -471,7 +471,7 @@ def test_random_configurations_match_oracle(W):
     FP64 bar."""
     rng = np.random.default_rng(2024)
     kernels = (W.WADG_KERNEL_AUTO, W.WADG_KERNEL_STREAMED, W.WADG_KERNEL_RESIDENT,
-               W.WADG_KERNEL_SPLIT)
+               W.WADG_KERNEL_SPLIT, W.WADG_KERNEL_PIPE)
     for case in range(24):
         N = int(rng.integers(1, 5))
         nq1 = N + int(rng.integers(1, 4))
@@ -485,6 +485,8 @@ def test_random_configurations_match_oracle(W):
         kern = int(rng.choice(kernels))
         if kern == W.WADG_KERNEL_RESIDENT and not (N <= 2 or (N == 3 and nq1 <= 5)):
             kern = W.WADG_KERNEL_AUTO     # its FP64 geometry does not fit in LDS
+        if kern == W.WADG_KERNEL_PIPE and not (N <= 2 or (N == 3 and nq1 <= 5)):
+            kern = W.WADG_KERNEL_AUTO     # its FP64 LDS plan does not fit
         _print_case(test="random", case=case, N=N, nq1=nq1, K1D=K1D, warp=warp, rot=rot,
                     eps=eps, tau=tau, S=S, n=n, kernel=kern)
         mesh = periodic_quad_mesh(K1D, N, eps=eps, warp=warp, rotate_seed=rot)
