@@ -76,22 +76,33 @@ def stage_bytes(K, S, N, nq1, word=8):
 def measured_traffic(kernel, workload):
     """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated) from the
     rocprofv3 counter runs recorded in profiles/hbm_traffic.json, or None when
-    there is no record for this kernel and workload or the kernel's sources
-    have changed since the counters were taken."""
-    import hashlib
+    there is no record for this kernel and workload or the code of the
+    kernel's sources has changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
     for rec in json.load(open(path))["records"]:
         if rec["kernel"] != kernel or rec["workload"] != workload:
             continue
-        h = hashlib.sha1()
-        for src in rec["sources"]:
-            with open(os.path.join(ROOT, src), "rb") as f:
-                h.update(f.read())
-        if h.hexdigest() == rec["sources_sha1"]:
+        if sources_digest(rec["sources"]) == rec["sources_sha1"]:
             return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
     return None
+
+
+def sources_digest(sources):
+    """SHA-1 of the code of the listed source files with their comments and
+    white space removed, so that a counter record stays valid across
+    comment-only edits and lapses with any change to the code."""
+    import hashlib
+    import re
+    h = hashlib.sha1()
+    for src in sources:
+        with open(os.path.join(ROOT, src)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(re.sub(r"\s+", "", text).encode())
+    return h.hexdigest()
 
 
 def cpu_baseline(prob, seconds):

@@ -9,10 +9,10 @@
 //   * One workgroup of eight waves per CU owns one 64-element group and a
 //     run of consecutive slices of it, and walks them one after another.
 //     The group's geometry is read once per workgroup, not once per item:
-//     the four metric planes stay in LDS, the mass weights, face factors
-//     and neighbour offsets stay in the registers of the waves that use
-//     them.
-//   * Wave 7 is a loader: while an item is computed it streams the next
+//     the four metric planes and the two mass-weight planes stay in LDS,
+//     the face factors and neighbour offsets in the registers of the face
+//     waves.
+//   * Wave 4 is a loader: while an item is computed it streams the next
 //     slice's input tile into the other half of an LDS double buffer with
 //     gfx950's direct-to-LDS buffer loads (no registers involved), so the
 //     HBM latency of the tile is off the item's critical path.
@@ -22,19 +22,22 @@
 //     this one's, each a full item ahead of its use.
 //
 // Roles per item (two barriers):
-//   phase F  wave 0  pressure volume term        (Section 4.1, weak form)
-//            wave 1  velocity volume terms, b_v handed to wave 6 in LDS
-//            waves 2..5  traces, flux and lift of face 0..3 (all fields)
-//            wave 7  tile of the next slice -> LDS
-//   -- barrier: face terms and b_v in LDS
-//   phase B  waves 0, 1, 6  face terms added in face order 0..3, mass
-//            inverse and stage update of p, u, v
-//            wave 7  waits for its tile
-//   -- barrier: the current tile, face terms and b_v are free again
+//   phase F  wave 0     pressure volume term (Section 4.1, weak form)
+//            waves 1, 2 the u and v components of the velocity volume term
+//                       (one SIMD each, so the pressure wave has its own)
+//            waves 3, 5, 6, 7  traces, flux and lift of faces 0..3
+//            wave 4     tile of the next slice -> LDS
+//   -- barrier: face terms in LDS
+//   phase B  waves 0..2  face terms added in face order 0..3, mass inverse
+//                        and stage update of p, u, v
+//            wave 4      waits for its tile
+//   -- barrier: the current tile and the face terms are free again
 //
-// LDS at N = 3, FP64: two input tiles (48 KB), the metric planes (50 KB),
-// face terms (24 KB) and b_v (8 KB): 130 KB, one workgroup per CU with two
-// waves per SIMD.  Instantiated where this fits in the CU's 160 KB.
+// The update waves keep the element's nodal values in registers for all
+// quadrature columns.  LDS at N = 3, FP64: two input tiles (48 KB), the
+// metric planes (50 KB), face terms (24 KB) and mass weights (25 KB):
+// 147 KB, one workgroup per CU with two waves per SIMD.  Instantiated where
+// this fits in the CU's 160 KB.
 
 #include <hip/hip_runtime.h>
 

@@ -28,17 +28,19 @@ def test_stage_bytes_by_hand():
 
 def test_traffic_record_follows_the_sources(tmp_path, monkeypatch):
     src = tmp_path / "k.hip"
-    src.write_text("kernel v1\n")
+    src.write_text("x = a * b;  // kernel v1\n")
     (tmp_path / "profiles").mkdir()
     rec = {"kernel": "k<double>", "workload": "w", "fetch_bytes_per_launch": 300,
            "write_bytes_per_launch": 200, "sources": ["k.hip"],
-           "sources_sha1": hashlib.sha1(b"kernel v1\n").hexdigest()}
+           "sources_sha1": hashlib.sha1(b"x=a*b;").hexdigest()}   # code, no comments or blanks
     (tmp_path / "profiles" / "hbm_traffic.json").write_text(json.dumps({"records": [rec]}))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.measured_traffic("k<double>", "w") == 500
     assert bench.measured_traffic("k<double>", "other") is None
     assert bench.measured_traffic("other", "w") is None
-    src.write_text("kernel v2\n")               # the kernel changed since the counters
+    src.write_text("/* the product */\nx = a * b;   // reworded comment\n")
+    assert bench.measured_traffic("k<double>", "w") == 500      # comments only: still valid
+    src.write_text("x = a * c;  // kernel v1\n")    # the code changed since the counters
     assert bench.measured_traffic("k<double>", "w") is None
 
 
