@@ -231,7 +231,9 @@ def run_fp32(args):
 
 
 def run_batch(args):
-    """The 1000-problem batch: one 4-step sweep of every problem per step."""
+    """The 1000-problem batch: one 4-step sweep of every problem per step,
+    as a replay of the HIP graph the library captured for the sweep, on the
+    schedule its autotuner chose."""
     import numpy as np
     import torch
     import paper_1608_03836_amd as W
@@ -245,17 +247,24 @@ def run_batch(args):
     stream = torch.cuda.current_stream()
     Q = batch.upload([p.Q0 for p in probs])
     work = batch.workspace()
+    wg, order, runs, tuned_us = batch.tune(Q, dts, work=work, reps=3, stream=stream)
+    batch.capture(Q, work, dts, nsteps)
     calibrate(args, torch)
-    elapsed, ev = timed(args, torch, stream,
-                        lambda: batch.integrate(Q, dts, nsteps, work=work, stream=stream))
+    elapsed, ev = timed(args, torch, stream, lambda: batch.replay(stream=stream))
+    batch.release_graph()
     N, nq1 = batch.N, batch.nq1
     gps = sum(p.S * p.mesh.K * (N + 1) ** 2 for p in probs) * nsteps
     line = common(args, gps / (elapsed / args.steps), 1e3 * elapsed / args.steps, "f64",
                   {"workload": "batch1000", "problems": len(probs),
                    "elements": int(sum(p.mesh.K for p in probs)),
                    "slices": int(sum(p.S for p in probs)), "degree": N, "nq1": nq1,
-                   "lsrk_steps_per_slice": nsteps, "parallelism": "single-gpu"})
-    kname = f"batch_split_kernel<{N},{nq1}>"
+                   "lsrk_steps_per_slice": nsteps, "launch": "hip-graph replay",
+                   "schedule": {"run_slices": runs, "wg_per_cu": wg, "order": order,
+                                "tuned_stage_us": tuned_us},
+                   "parallelism": "single-gpu"})
+    kind = ("batch_pipe_kernel" if runs > 0 else
+            "batch_split_kernel" if wg == 0 else "batch_stage_kernel")
+    kname = f"{kind}<{N},{nq1}>"
     line["roofline"] = roofline(kname, sum(stage_bytes(p.mesh.K, p.S, N, nq1) for p in probs),
                                 sum(ev) / (args.steps * 5 * nsteps),
                                 measured_traffic(kname, "batch1000"))

@@ -281,25 +281,38 @@ int wadg_adjoint(wadg_ctx ctx, const double* chk, const double* seed, double* gr
  * wadg_batch_integrate: every problem advanced by nsteps LSRK steps of its
  *   own dt[i] (host array, finite > 0), all slices at once.  Q (device):
  *   the batch state, in/out; work: device workspace.  Asynchronous.
- * wadg_batch_set_schedule: workgroups and work-list order.  wg_per_cu 0:
- *   one four-wave workgroup per work item (the split-work kernel, as
+ * wadg_batch_set_runs: run_slices >= 1 selects the pipelined kernel (as
+ *   WADG_KERNEL_PIPE): for every problem and element group of its virtual
+ *   mesh, the virtual slices in which the group holds a real slice are cut
+ *   into runs of at most run_slices (nearly equal lengths), one 512-thread
+ *   workgroup per run with the group's geometry on chip; elements of unused
+ *   copies in a last virtual slice are neither computed into the state nor
+ *   written (their values in Q are unspecified).  0 returns to the item
+ *   schedule of wadg_batch_set_schedule.  Default 16 where the kernel's LDS
+ *   plan fits (N <= 3 with nq1 <= N + 2), else 0.  Returns
+ *   WADG_E_UNSUPPORTED for run_slices > 0 where it does not fit.
+ * wadg_batch_set_schedule: item schedule (and run_slices = 0).  wg_per_cu
+ *   0: one four-wave workgroup per work item (the split-work kernel, as
  *   WADG_KERNEL_SPLIT); 1..64: that many persistent two-wave workgroups per
  *   CU looping over the list (the streamed kernel).  order: 0 problem-major,
- *   1 round-robin over problems.  Results are bitwise independent of it.
- *   Defaults 0, 0 (the fastest measured on the 1000-problem workload).
- * wadg_batch_tune: the autotuner -- times one stage of every schedule
- *   candidate (1, 2, 4, 8 workgroups per CU or one per item, both orders)
- *   reps times on the device, keeps the fastest and returns it (host out:
- *   wg_per_cu, order, best_us per stage).  Q is read only; work is scratch.
- *   Synchronises `stream`.
+ *   1 round-robin over problems.
+ * Results are bitwise independent of the schedule and of the runs.
+ * wadg_batch_tune: the autotuner -- times one stage of every candidate
+ *   (runs of 4, 8, 16, 32, 128 slices where the pipelined kernel fits; 1, 2,
+ *   4, 8 persistent workgroups per CU or one per item, both orders) reps
+ *   times on the device, keeps the fastest and returns it (host out:
+ *   wg_per_cu, order, run_slices -- 0 unless the pipelined kernel won --
+ *   and best_us per stage).  Q is read only; work is scratch.  Synchronises
+ *   `stream`.
  * wadg_batch_capture: records the whole nsteps sweep of wadg_batch_integrate
  *   for these Q, work and dt into a HIP graph (on a stream of its own); the
  *   graph reads its own copy of the per-problem dt, so later integrate calls
  *   with other dt do not change what it computes.  wadg_batch_replay
  *   launches it on `stream` (each replay advances Q by nsteps steps again).
- *   wadg_batch_release_graph frees it; set_schedule and tune refuse while a
- *   graph is held.
- * A call that changes the device-side work list (set_schedule, tune) or
+ *   wadg_batch_release_graph frees it; set_schedule, set_runs and tune
+ *   refuse while a graph is held.
+ * A call that changes the device-side work list (set_schedule, set_runs,
+ * tune) or
  * the per-problem dt (integrate, tune, capture with dt other than the last)
  * first waits for the device to drain, so that no queued launch of the
  * batch reads a table while it is rewritten. */
@@ -311,8 +324,10 @@ int wadg_batch_workspace_bytes(wadg_batch b, size_t* bytes);
 int wadg_batch_integrate(wadg_batch b, double* Q, double* work, const double* dt, int32_t nsteps,
                          void* stream);
 int wadg_batch_set_schedule(wadg_batch b, int32_t wg_per_cu, int32_t order);
+int wadg_batch_set_runs(wadg_batch b, int32_t run_slices);
 int wadg_batch_tune(wadg_batch b, const double* Q, double* work, const double* dt, int32_t reps,
-                    int32_t* wg_per_cu, int32_t* order, double* best_us, void* stream);
+                    int32_t* wg_per_cu, int32_t* order, int32_t* run_slices, double* best_us,
+                    void* stream);
 int wadg_batch_capture(wadg_batch b, double* Q, double* work, const double* dt, int32_t nsteps);
 int wadg_batch_replay(wadg_batch b, void* stream);
 int wadg_batch_release_graph(wadg_batch b);

@@ -106,8 +106,9 @@ def _load():
         "wadg_batch_workspace_bytes": (ctypes.c_int, [vp, ctypes.POINTER(sz)]),
         "wadg_batch_integrate": (ctypes.c_int, [vp, vp, vp, _c_double_p, ctypes.c_int32, vp]),
         "wadg_batch_set_schedule": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32]),
+        "wadg_batch_set_runs": (ctypes.c_int, [vp, ctypes.c_int32]),
         "wadg_batch_tune": (ctypes.c_int, [vp, vp, vp, _c_double_p, ctypes.c_int32, _c_int32_p,
-                                           _c_int32_p, _c_double_p, vp]),
+                                           _c_int32_p, _c_int32_p, _c_double_p, vp]),
         "wadg_batch_capture": (ctypes.c_int, [vp, vp, vp, _c_double_p, ctypes.c_int32]),
         "wadg_batch_replay": (ctypes.c_int, [vp, vp]),
         "wadg_batch_release_graph": (ctypes.c_int, [vp]),
@@ -139,6 +140,7 @@ EXPORTED = ("wadg_quadrature_points", "wadg_geometry", "wadg_cfl_number", "wadg_
             "wadg_set_c2_scale", "wadg_adjoint_workspace_bytes", "wadg_forward_checkpoints",
             "wadg_adjoint", "wadg_batch_create", "wadg_batch_destroy", "wadg_batch_layout",
             "wadg_batch_workspace_bytes", "wadg_batch_integrate", "wadg_batch_set_schedule",
+            "wadg_batch_set_runs",
             "wadg_batch_tune", "wadg_batch_capture", "wadg_batch_replay",
             "wadg_batch_release_graph",
             "wadg_status_string", "wadg_last_error")
@@ -507,13 +509,18 @@ def wadg_batch_set_schedule(b, wg_per_cu, order):
     _check(LIB.wadg_batch_set_schedule(b, int(wg_per_cu), int(order)))
 
 
+def wadg_batch_set_runs(b, run_slices):
+    _check(LIB.wadg_batch_set_runs(b, int(run_slices)))
+
+
 def wadg_batch_tune(b, Q, work, dt, reps=3, stream=None):
+    """(wg_per_cu, order, run_slices, best_us) of the fastest candidate."""
     d, dp = _batch_dt(b, dt)
     q, w = _batch_state(b, Q, work)
-    wg, order, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
-    _check(LIB.wadg_batch_tune(b, q, w, dp, int(reps), ctypes.byref(wg),
-                               ctypes.byref(order), ctypes.byref(us), _stream(stream)))
-    return wg.value, order.value, us.value
+    wg, order, runs, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    _check(LIB.wadg_batch_tune(b, q, w, dp, int(reps), ctypes.byref(wg), ctypes.byref(order),
+                               ctypes.byref(runs), ctypes.byref(us), _stream(stream)))
+    return wg.value, order.value, runs.value, us.value
 
 
 def wadg_batch_capture(b, Q, work, dt, nsteps):

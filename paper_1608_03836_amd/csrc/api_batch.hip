@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -29,8 +30,11 @@ struct wadg_batch_s {
   wadg::BatchProb* d_prob = nullptr;           // descriptors of eager sweeps
   wadg::BatchProb* d_prob_graph = nullptr;     // descriptors the captured graph reads
   int32_t* d_items = nullptr;
+  int32_t* d_runs = nullptr;                   // pipelined kernel's runs [nruns][4]
+  int64_t nruns = 0;
   int grid_mult = 0;                           // persistent workgroups per CU (0: one per item)
   int order = 0;                               // 0 problem-major, 1 interleaved
+  int run_slices = 0;                          // > 0: pipelined kernel, runs of this many slices
   hipStream_t capture_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -38,13 +42,16 @@ struct wadg_batch_s {
 
 namespace {
 
+// Default slices per run of the pipelined batch kernel.
+constexpr int kBatchRunSlices = 16;
+
 void free_batch(wadg_batch b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
   for (void* ptr : {(void*)b->d_vol, (void*)b->d_face, (void*)b->d_nbr, (void*)b->d_prob,
-                    (void*)b->d_prob_graph, (void*)b->d_items})
+                    (void*)b->d_prob_graph, (void*)b->d_items, (void*)b->d_runs})
     if (ptr) (void)hipFree(ptr);
   delete b;
 }
@@ -87,6 +94,49 @@ int batch_upload_items(wadg_batch b) {
   return WADG_OK;
 }
 
+// Elements of problem i's virtual mesh that hold real slices in its last
+// virtual slice (the first copies; a packed last slice may have unused ones).
+int32_t last_slice_elements(const wadg_batch b, int i) {
+  return (b->S[i] - (b->Sv[i] - 1) * b->pack[i]) * b->K[i];
+}
+
+// Runs of the pipelined kernel: for every problem and element group of its
+// virtual mesh, the virtual slices in which the group holds a real element
+// (all but, possibly, the last), cut into ceil(n / run_slices) runs of
+// nearly equal length.  Order: longest first, dealt round-robin into the
+// eight contiguous ranges that the kernel's XCD remap gives the XCDs, so
+// every XCD gets the same mix and ends on its shortest runs (runs of equal
+// length stay problem-major).  Uploaded like the work list.
+int batch_upload_runs(wadg_batch b) {
+  std::vector<std::array<int32_t, 4>> list;
+  for (int i = 0; i < b->nprob; ++i)
+    for (int g = 0; g < b->nEG[i]; ++g) {
+      const int n = b->Sv[i] - (g * wadg::kWave >= last_slice_elements(b, i) ? 1 : 0);
+      const int c = (n + b->run_slices - 1) / b->run_slices;
+      for (int j = 0; j < c; ++j) {
+        const int s0 = (int)((int64_t)j * n / c), s1 = (int)((int64_t)(j + 1) * n / c);
+        list.push_back({i, g, s0, s1 - s0});
+      }
+    }
+  std::stable_sort(list.begin(), list.end(),
+                   [](const std::array<int32_t, 4>& x, const std::array<int32_t, 4>& y) {
+                     return x[3] > y[3];
+                   });
+  std::vector<int32_t> r;
+  r.reserve(list.size() * 4);
+  for (int x = 0; x < 8; ++x)
+    for (size_t k = (size_t)x; k < list.size(); k += 8) r.insert(r.end(), list[k].begin(), list[k].end());
+  if (r.size() / 4 >= (size_t)1 << 31) return fail(WADG_E_INVALID, "too many runs");
+  WADG_HIP(hipDeviceSynchronize());
+  if (b->d_runs) WADG_HIP(hipFree(b->d_runs));
+  b->d_runs = nullptr;
+  b->nruns = (int64_t)(r.size() / 4);
+  if (b->nruns == 0) return WADG_OK;
+  WADG_HIP(hipMalloc(&b->d_runs, r.size() * sizeof(int32_t)));
+  WADG_HIP(hipMemcpy(b->d_runs, r.data(), r.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  return WADG_OK;
+}
+
 int check_dt(const wadg_batch b, const double* dt) {
   for (int i = 0; i < b->nprob; ++i)
     if (!(dt[i] > 0.0) || !std::isfinite(dt[i]))
@@ -97,7 +147,8 @@ int check_dt(const wadg_batch b, const double* dt) {
 int write_descriptors(const wadg_batch b, const double* dt, wadg::BatchProb* dst) {
   std::vector<wadg::BatchProb> pr(b->nprob);
   for (int i = 0; i < b->nprob; ++i)
-    pr[i] = wadg::BatchProb{b->offset[i], b->nEG[i], b->Sv[i], b->Kv[i], b->g0[i], dt[i]};
+    pr[i] = wadg::BatchProb{b->offset[i], b->nEG[i], b->Sv[i], b->Kv[i], b->g0[i],
+                            last_slice_elements(b, i), dt[i]};
   WADG_HIP(hipDeviceSynchronize());
   WADG_HIP(hipMemcpy(dst, pr.data(), pr.size() * sizeof(wadg::BatchProb),
                      hipMemcpyHostToDevice));
@@ -138,10 +189,14 @@ int batch_stage(wadg_batch b, const wadg::BatchProb* prob, const double* qin, do
   p.tau_u = b->tau_u;
   p.rkA = kRkA[i];
   p.rkB = kRkB[i];
-  // one workgroup per item: the split-work kernel; persistent workgroups:
-  // the streamed kernel (wadg_batch_set_schedule)
-  int e = b->grid_mult == 0 ? wadg::launch_batch_split(b->N, b->nq1, p, stream)
-                            : wadg::launch_batch_stage(b->N, b->nq1, p, batch_grid(b), stream);
+  // runs of slices: the pipelined kernel (wadg_batch_set_runs); one
+  // workgroup per item: the split-work kernel; persistent workgroups: the
+  // streamed kernel (wadg_batch_set_schedule)
+  int e = b->run_slices > 0
+              ? wadg::launch_batch_pipe(b->N, b->nq1, p, b->d_runs, (int32_t)b->nruns, stream)
+          : b->grid_mult == 0
+              ? wadg::launch_batch_split(b->N, b->nq1, p, stream)
+              : wadg::launch_batch_stage(b->N, b->nq1, p, batch_grid(b), stream);
   if (e) return hip_fail((hipError_t)e, "batch stage kernel launch");
   return WADG_OK;
 }
@@ -317,6 +372,10 @@ int wadg_batch_create(const wadg_mesh* meshes, int32_t nprob, const int32_t* S, 
     return hip_fail(e, "wadg_batch_create device setup");
   }
   int st = batch_upload_items(b);
+  if (!st && wadg::batch_pipe_supported(N, nq)) {   // the default schedule
+    b->run_slices = kBatchRunSlices;
+    st = batch_upload_runs(b);
+  }
   if (st) {
     free_batch(b);
     return st;
@@ -369,6 +428,7 @@ int wadg_batch_set_schedule(wadg_batch b, int32_t wg_per_cu, int32_t order) {
   DeviceGuard guard(b->device);
   if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select the batch's device");
   b->grid_mult = wg_per_cu;
+  b->run_slices = 0;
   if (order != b->order) {
     b->order = order;
     int st = batch_upload_items(b);
@@ -377,10 +437,24 @@ int wadg_batch_set_schedule(wadg_batch b, int32_t wg_per_cu, int32_t order) {
   return WADG_OK;
 }
 
-int wadg_batch_tune(wadg_batch b, const double* Q, double* work, const double* dt, int32_t reps,
-                    int32_t* wg_per_cu, int32_t* order, double* best_us, void* stream) {
+int wadg_batch_set_runs(wadg_batch b, int32_t run_slices) {
   if (!b) return fail(WADG_E_INVALID, "batch is NULL");
-  if (!Q || !work || !dt || !wg_per_cu || !order || !best_us)
+  if (run_slices < 0) return fail(WADG_E_INVALID, "run_slices must be >= 0");
+  if (b->exec) return fail(WADG_E_INVALID, "release the captured graph first");
+  if (run_slices > 0 && !wadg::batch_pipe_supported(b->N, b->nq1))
+    return fail(WADG_E_UNSUPPORTED, "the pipelined kernel's tiles do not fit in LDS");
+  DeviceGuard guard(b->device);
+  if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select the batch's device");
+  if (run_slices == b->run_slices) return WADG_OK;
+  b->run_slices = run_slices;
+  return run_slices > 0 ? batch_upload_runs(b) : WADG_OK;
+}
+
+int wadg_batch_tune(wadg_batch b, const double* Q, double* work, const double* dt, int32_t reps,
+                    int32_t* wg_per_cu, int32_t* order, int32_t* run_slices, double* best_us,
+                    void* stream) {
+  if (!b) return fail(WADG_E_INVALID, "batch is NULL");
+  if (!Q || !work || !dt || !wg_per_cu || !order || !run_slices || !best_us)
     return fail(WADG_E_INVALID, "Q, work, dt and the outputs must not be NULL");
   if (reps < 1) return fail(WADG_E_INVALID, "reps must be >= 1");
   if (b->exec) return fail(WADG_E_INVALID, "release the captured graph first");
@@ -397,45 +471,54 @@ int wadg_batch_tune(wadg_batch b, const double* Q, double* work, const double* d
     if (e0) (void)hipEventDestroy(e0);
     return hip_fail(hipErrorUnknown, "hipEventCreate");
   }
-  // candidates: persistent grids of 1, 2, 4, 8 two-wave workgroups per CU
-  // (streamed kernel) or one four-wave workgroup per item (split kernel), in
-  // both item orders; each timed on a stage with a residual read (Q is only
-  // read, the workspace is scratch)
-  const int mults[] = {1, 2, 4, 8, 0};
+  // candidates: the pipelined kernel with runs of 4..128 slices per
+  // workgroup (tile = one element group x a run of slices); persistent grids
+  // of 1, 2, 4, 8 two-wave workgroups per CU (streamed kernel) or one
+  // four-wave workgroup per item (split kernel), in both item orders; each
+  // timed on a stage with a residual read (Q is only read, the workspace is
+  // scratch)
+  struct Cand { int m, o, r; };
+  std::vector<Cand> cands;
+  if (wadg::batch_pipe_supported(b->N, b->nq1))
+    for (int r : {4, 8, 16, 32, 128}) cands.push_back({0, 0, r});
+  for (int o = 0; o < 2; ++o)
+    for (int m : {1, 2, 4, 8, 0}) cands.push_back({m, o, 0});
   double best = 1e300;
-  const int m0 = b->grid_mult, o0 = b->order;
-  int bm = m0, bo = o0;
-  for (int o = 0; o < 2 && !st; ++o) {
-    for (int m : mults) {
-      if ((st = wadg_batch_set_schedule(b, m, o))) break;
-      if ((st = batch_stage(b, b->d_prob, Q, work, work + n, 1, stream))) break;
-      if (hipEventRecord(e0, hs) != hipSuccess) { st = hip_fail(hipErrorUnknown, "event"); break; }
-      for (int r = 0; r < reps && !st; ++r)
-        st = batch_stage(b, b->d_prob, Q, work, work + n, 1, stream);
-      if (st) break;
-      float ms = 0.f;
-      if (hipEventRecord(e1, hs) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-        st = hip_fail(hipErrorUnknown, "event timing");
-        break;
-      }
-      const double us = 1e3 * ms / reps;
-      if (us < best) {
-        best = us;
-        bm = m;
-        bo = o;
-      }
+  const Cand c0{b->grid_mult, b->order, b->run_slices};
+  Cand bc = c0;
+  auto apply = [&](const Cand& c) {
+    int s = wadg_batch_set_schedule(b, c.m, c.o);
+    return s ? s : wadg_batch_set_runs(b, c.r);
+  };
+  for (const Cand& c : cands) {
+    if ((st = apply(c))) break;
+    if ((st = batch_stage(b, b->d_prob, Q, work, work + n, 1, stream))) break;
+    if (hipEventRecord(e0, hs) != hipSuccess) { st = hip_fail(hipErrorUnknown, "event"); break; }
+    for (int r = 0; r < reps && !st; ++r)
+      st = batch_stage(b, b->d_prob, Q, work, work + n, 1, stream);
+    if (st) break;
+    float ms = 0.f;
+    if (hipEventRecord(e1, hs) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      st = hip_fail(hipErrorUnknown, "event timing");
+      break;
+    }
+    const double us = 1e3 * ms / reps;
+    if (us < best) {
+      best = us;
+      bc = c;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st) {
-    (void)wadg_batch_set_schedule(b, m0, o0);   // leave the schedule as it was
+    (void)apply(c0);   // leave the schedule as it was
     return st;
   }
-  if ((st = wadg_batch_set_schedule(b, bm, bo))) return st;
-  *wg_per_cu = bm;
-  *order = bo;
+  if ((st = apply(bc))) return st;
+  *wg_per_cu = bc.m;
+  *order = bc.o;
+  *run_slices = bc.r;
   *best_us = best;
   return WADG_OK;
 }

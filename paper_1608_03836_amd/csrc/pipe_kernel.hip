@@ -182,29 +182,52 @@ __device__ __forceinline__ void wadg_inverse_wide(const R (&b)[(N + 1) * (N + 1)
       for (int a = 0; a < NP1; ++a) dq[a + NP1 * bb] = mad(T.P[a][i], c[i][bb], dq[a + NP1 * bb]);
 }
 
+// One workgroup's work: element group g of a state whose slice s starts at
+// qin + s slice_vals (likewise qout, res, resw), slices [s0, s0 + nit); the
+// group's geometry resources; the elements of the group's lanes that are
+// real: e = 64 g + lane is updated iff e < kfull, or e < klast in slice
+// slast (the last virtual slice of a packed batch problem, whose unused
+// copies are skipped; slast = -1 otherwise).
+template <typename R>
+struct PipeRun {
+  const R* qin;
+  R* qout;
+  const R* res;
+  R* resw;
+  size_t slice_vals;
+  int g, s0, nit;
+  rsrc_t vol, face, nbr;
+  int kfull, slast, klast;
+  size_t goff;   // g times the values of one tile
+  // offset (in values) of the group's tile in slice s
+  __device__ __forceinline__ size_t grp(int s) const { return (size_t)s * slice_vals + goff; }
+};
+
 // Face wave of face F: its factors and neighbour offsets held for the
 // whole run, its traces gathered one slice ahead.  Barriers as the other
 // roles: one after the prologue, two per item.
 template <typename R, int N, int NQ, int F>
-__device__ __forceinline__ void pipe_face_role(const StageParams& p, const StageScalars<R>& k,
-                                               int g, int s0, int nit, int lane, unsigned kb,
-                                               rsrc_t face, R (*tq)[Pipe<R, N, NQ>::tile_alloc],
-                                               R* xf) {
+__device__ __forceinline__ void pipe_face_role(const PipeRun<R>& run, const StageScalars<R>& k,
+                                               int lane, unsigned kb,
+                                               R (*tq)[Pipe<R, N, NQ>::tile_alloc], R* xf) {
   using L = Pipe<R, N, NQ>;
   constexpr int NP1 = L::NP1, NP = L::NP;
   constexpr unsigned KP = kWave * sizeof(R);
-  const R* Qin = static_cast<const R*>(p.Qin);
-  const size_t slice_vals = (size_t)p.nEG * L::tile;
+  const int nit = run.nit;
+  auto slice = [&](int s) {
+    return make_rsrc(run.qin + (size_t)s * run.slice_vals,
+                     (unsigned)(run.slice_vals * sizeof(R)));
+  };
   R gf[3][NQ];
 #pragma unroll
   for (int cc = 0; cc < 3; ++cc)
 #pragma unroll
-    for (int jj = 0; jj < NQ; ++jj) gf[cc][jj] = ldr<R>(face, kb, (cc * 4 * NQ + F * NQ + jj) * KP);
+    for (int jj = 0; jj < NQ; ++jj)
+      gf[cc][jj] = ldr<R>(run.face, kb, (cc * 4 * NQ + F * NQ + jj) * KP);
   NbrOffsets nbo;
-  load_nbr(make_rsrc(p.nbr + (size_t)g * 8 * kWave, 8u * kWave * 4u), lane, nbo);
+  load_nbr(run.nbr, lane, nbo);
   Trace<R, N> tr;
-  gather_trace<R, N>(make_rsrc(Qin + (size_t)s0 * slice_vals, (unsigned)(slice_vals * sizeof(R))),
-                     nbo, F, tr);
+  gather_trace<R, N>(slice(run.s0), nbo, F, tr);
   __syncthreads();                                           // prologue done
   for (int it = 0; it < nit; ++it) {
     const R* t = tq[it & 1];
@@ -219,10 +242,7 @@ __device__ __forceinline__ void pipe_face_role(const StageParams& p, const Stage
       xf[((F * 3 + 1) * NP1 + m) * kWave + lane] = su[m];
       xf[((F * 3 + 2) * NP1 + m) * kWave + lane] = sv[m];
     }
-    if (it + 1 < nit)
-      gather_trace<R, N>(
-          make_rsrc(Qin + (size_t)(s0 + it + 1) * slice_vals, (unsigned)(slice_vals * sizeof(R))),
-          nbo, F, tr);
+    if (it + 1 < nit) gather_trace<R, N>(slice(run.s0 + it + 1), nbo, F, tr);
     __syncthreads();                                         // face terms ready
     __syncthreads();                                         // item done
   }
@@ -235,20 +255,18 @@ __device__ __forceinline__ void pipe_face_role(const StageParams& p, const Stage
 // c^2 scale) or 1/J held for the whole run; the residual requested one
 // slice ahead.  Barriers: one after the prologue, two per item.
 template <typename R, int N, int NQ, int C>
-__device__ __forceinline__ void pipe_update_role(const StageParams& p, const StageScalars<R>& k,
-                                                 int g, int s0, int nit, int lane, unsigned kb,
-                                                 bool active, rsrc_t vol,
+__device__ __forceinline__ void pipe_update_role(const PipeRun<R>& run, const StageScalars<R>& k,
+                                                 int lane, unsigned kb,
                                                  R (*tq)[Pipe<R, N, NQ>::tile_alloc],
                                                  const R* xm, const R* xf, R* xw) {
   using L = Pipe<R, N, NQ>;
   constexpr int NP1 = L::NP1, NP = L::NP, NQ2 = L::NQ2;
   constexpr unsigned tile = L::tile;
   constexpr unsigned KP = kWave * sizeof(R);
-  R* Qout = static_cast<R*>(p.Qout);
-  R* res = static_cast<R*>(p.res);
-  R* resw = static_cast<R*>(p.res_out ? p.res_out : p.res);
-  const size_t slice_vals = (size_t)p.nEG * tile;
-  auto grp = [&](int s) { return (size_t)s * slice_vals + (size_t)g * tile; };
+  const int s0 = run.s0, nit = run.nit;
+  const rsrc_t vol = run.vol;
+  const int e = run.g * kWave + lane;
+  auto grp = [&](int s) { return run.grp(s); };
   constexpr bool kLdsW = L::weights_in_lds;
   // mass weights: c^2/J times the c^2 scale (p) or 1/J (u, v); in LDS the
   // pressure wave writes plane 0 and the u wave plane 1
@@ -271,7 +289,7 @@ __device__ __forceinline__ void pipe_update_role(const StageParams& p, const Sta
     }
   }
   R resv[NP];
-  load_res<R, NP, kStage>(k, make_rsrc(res + grp(s0), tile * sizeof(R)), C, kb, resv);
+  load_res<R, NP, kStage>(k, make_rsrc(run.res + grp(s0), tile * sizeof(R)), C, kb, resv);
   __syncthreads();                                           // prologue done
   for (int it = 0; it < nit; ++it) {
     const int s = s0 + it;
@@ -325,23 +343,70 @@ __device__ __forceinline__ void pipe_update_role(const StageParams& p, const Sta
     } else {
       wadg_inverse_wide<R, N, NQ>(b, wq, dq);
     }
-    const rsrc_t qo = make_rsrc(Qout + grp(s), tile * sizeof(R));
-    const rsrc_t rw = make_rsrc(resw + grp(s), tile * sizeof(R));
+    const rsrc_t qo = make_rsrc(run.qout + grp(s), tile * sizeof(R));
+    const rsrc_t rw = make_rsrc(run.resw + grp(s), tile * sizeof(R));
+    const bool active = e < (s == run.slast ? run.klast : run.kfull);
     finish_field<R, NP, kStage>(k, qo, rw, Pt, C, kb, active, resv, dq);
     if (it + 1 < nit)
-      load_res<R, NP, kStage>(k, make_rsrc(res + grp(s + 1), tile * sizeof(R)), C, kb, resv);
+      load_res<R, NP, kStage>(k, make_rsrc(run.res + grp(s + 1), tile * sizeof(R)), C, kb, resv);
     __syncthreads();                                         // item done
+  }
+}
+
+// One run over the eight waves of the workgroup, on the workgroup's LDS
+// arrays (Pipe<>).  Waves 0..2 (one per SIMD) carry the volume terms and
+// the updates of p, u, v; wave 4 shares SIMD 0 with the pressure wave as the
+// loader; waves 3, 5, 6, 7 the faces 0..3.
+template <typename R, int N, int NQ>
+__device__ __forceinline__ void pipe_run(const PipeRun<R>& run, const StageScalars<R>& k,
+                                         R (*tq)[Pipe<R, N, NQ>::tile_alloc], R* xm, R* xf,
+                                         R* xw) {
+  using L = Pipe<R, N, NQ>;
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & (kWave - 1);
+  const unsigned kb = (unsigned)lane * sizeof(R);
+  constexpr int kLoader = 4;
+  auto tile_src = [&](int s) { return make_rsrc(run.qin + run.grp(s), L::tile_bytes); };
+
+  // prologue: metric planes 0..3 of the group into LDS (every wave but the
+  // loader), the first tile by the loader
+  if (wave != kLoader)
+    copy_to_lds(run.vol, xm, L::metric * sizeof(R) / 16u,
+                (wave < kLoader ? wave : wave - 1) * kWave + lane, 7 * kWave);
+  if (wave == 0) {
+    pipe_update_role<R, N, NQ, 0>(run, k, lane, kb, tq, xm, xf, xw);
+  } else if (wave == 1) {
+    pipe_update_role<R, N, NQ, 1>(run, k, lane, kb, tq, xm, xf, xw);
+  } else if (wave == 2) {
+    pipe_update_role<R, N, NQ, 2>(run, k, lane, kb, tq, xm, xf, xw);
+  } else if (wave == kLoader) {
+    // the next slice's tile while this one is computed
+    tile_to_lds<L::rows>(tile_src(run.s0), tq[0], lane);
+    wait_vm_all();
+    __syncthreads();                                         // prologue done
+    for (int it = 0; it < run.nit; ++it) {
+      if (it + 1 < run.nit) tile_to_lds<L::rows>(tile_src(run.s0 + it + 1), tq[(it + 1) & 1], lane);
+      __syncthreads();                                       // face terms ready
+      wait_vm_all();                                         // next tile in LDS
+      __syncthreads();                                       // item done
+    }
+  } else if (wave == 3) {
+    pipe_face_role<R, N, NQ, 0>(run, k, lane, kb, tq, xf);
+  } else if (wave == 5) {
+    pipe_face_role<R, N, NQ, 1>(run, k, lane, kb, tq, xf);
+  } else if (wave == 6) {
+    pipe_face_role<R, N, NQ, 2>(run, k, lane, kb, tq, xf);
+  } else {
+    pipe_face_role<R, N, NQ, 3>(run, k, lane, kb, tq, xf);
   }
 }
 
 }  // namespace
 
-// Workgroup b: element group g and slices [s0, s1) (see launch below);
+// Workgroup b: element group g and slices [s0, s1) of one problem;
 // grid = nEG * chunks, chunk j of group g holds slices
-// [j S / chunks, (j + 1) S / chunks).  LSRK stage mode only.  Waves 0..2
-// (one per SIMD) carry the volume terms and the updates of p, u, v; wave 4
-// shares SIMD 0 with the pressure wave as the loader; waves 3, 5, 6, 7 the
-// faces 0..3.
+// [j S / chunks, (j + 1) S / chunks).  LSRK stage mode only.
 template <typename R, int N, int NQ>
 __global__ __launch_bounds__(8 * kWave) void pipe_kernel(const StageParams p, int chunks) {
   using L = Pipe<R, N, NQ>;
@@ -352,11 +417,6 @@ __global__ __launch_bounds__(8 * kWave) void pipe_kernel(const StageParams p, in
   __shared__ __attribute__((aligned(16))) R xf[L::xf];
   __shared__ __attribute__((aligned(16))) R xw[L::weights_in_lds ? L::wts : 1];
 
-  const int tid = threadIdx.x;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int lane = tid & (kWave - 1);
-  const unsigned kb = (unsigned)lane * sizeof(R);
-
   // workgroup -> (group, slice run), XCD-aware: each XCD takes a
   // contiguous range of groups, so most neighbour traces are read by
   // workgroups of the same XCD
@@ -365,53 +425,72 @@ __global__ __launch_bounds__(8 * kWave) void pipe_kernel(const StageParams p, in
   if (g >= p.nEG) return;                 // whole workgroup: no barrier reached
   const int s0 = (int)((int64_t)j * p.S / chunks);
   const int s1 = (int)((int64_t)(j + 1) * p.S / chunks);
-  const int nit = s1 - s0;
-  if (nit <= 0) return;
-  const bool active = g * kWave + lane < p.K;
-  const StageScalars<R> k = stage_scalars<R>(p);
-  const R* Qin = static_cast<const R*>(p.Qin);
-  const size_t slice_vals = (size_t)p.nEG * L::tile;
-  const rsrc_t vol = make_rsrc(static_cast<const R*>(p.vol) + (size_t)g * 6 * NQ2 * kWave,
-                               6u * NQ2 * KP);
-  const rsrc_t face = make_rsrc(static_cast<const R*>(p.face) + (size_t)g * 12 * NQ * kWave,
-                                12u * NQ * KP);
-  constexpr int kLoader = 4;
+  if (s1 <= s0) return;
+  PipeRun<R> run;
+  run.qin = static_cast<const R*>(p.Qin);
+  run.qout = static_cast<R*>(p.Qout);
+  run.res = static_cast<const R*>(p.res);
+  run.resw = static_cast<R*>(p.res_out ? p.res_out : p.res);
+  run.slice_vals = (size_t)p.nEG * L::tile;
+  run.g = g;
+  run.goff = (size_t)g * L::tile;
+  run.s0 = s0;
+  run.nit = s1 - s0;
+  run.vol = make_rsrc(static_cast<const R*>(p.vol) + (size_t)g * 6 * NQ2 * kWave, 6u * NQ2 * KP);
+  run.face = make_rsrc(static_cast<const R*>(p.face) + (size_t)g * 12 * NQ * kWave, 12u * NQ * KP);
+  run.nbr = make_rsrc(p.nbr + (size_t)g * 8 * kWave, 8u * kWave * 4u);
+  run.kfull = p.K;
+  run.slast = -1;
+  run.klast = p.K;
+  pipe_run<R, N, NQ>(run, stage_scalars<R>(p), tq, xm, xf, xw);
+}
 
-  // prologue: metric planes 0..3 of the group into LDS (every wave but the
-  // loader), the first tile by the loader
-  if (wave != kLoader)
-    copy_to_lds(vol, xm, L::metric * sizeof(R) / 16u, (wave < kLoader ? wave : wave - 1) * kWave + lane,
-                7 * kWave);
-  if (wave == 0) {
-    pipe_update_role<R, N, NQ, 0>(p, k, g, s0, nit, lane, kb, active, vol, tq, xm, xf, xw);
-  } else if (wave == 1) {
-    pipe_update_role<R, N, NQ, 1>(p, k, g, s0, nit, lane, kb, active, vol, tq, xm, xf, xw);
-  } else if (wave == 2) {
-    pipe_update_role<R, N, NQ, 2>(p, k, g, s0, nit, lane, kb, active, vol, tq, xm, xf, xw);
-  } else if (wave == kLoader) {
-    // the next slice's tile while this one is computed
-    tile_to_lds<L::rows>(make_rsrc(Qin + (size_t)s0 * slice_vals + (size_t)g * L::tile,
-                                   L::tile_bytes), tq[0], lane);
-    wait_vm_all();
-    __syncthreads();                                         // prologue done
-    for (int it = 0; it < nit; ++it) {
-      if (it + 1 < nit)
-        tile_to_lds<L::rows>(make_rsrc(Qin + (size_t)(s0 + it + 1) * slice_vals +
-                                           (size_t)g * L::tile, L::tile_bytes),
-                             tq[(it + 1) & 1], lane);
-      __syncthreads();                                       // face terms ready
-      wait_vm_all();                                         // next tile in LDS
-      __syncthreads();                                       // item done
-    }
-  } else if (wave == 3) {
-    pipe_face_role<R, N, NQ, 0>(p, k, g, s0, nit, lane, kb, face, tq, xf);
-  } else if (wave == 5) {
-    pipe_face_role<R, N, NQ, 1>(p, k, g, s0, nit, lane, kb, face, tq, xf);
-  } else if (wave == 6) {
-    pipe_face_role<R, N, NQ, 2>(p, k, g, s0, nit, lane, kb, face, tq, xf);
-  } else {
-    pipe_face_role<R, N, NQ, 3>(p, k, g, s0, nit, lane, kb, face, tq, xf);
-  }
+// Batched LSRK stage (FP64) over a list of runs of many independent
+// problems: run r = (problem, element group of its virtual mesh, first
+// virtual slice, slice count), one workgroup each.  The problem's
+// descriptor supplies the state offset, geometry groups and dt, and the
+// real element count of every virtual slice (unused copies of a packed
+// last slice are not written).
+template <int N, int NQ>
+__global__ __launch_bounds__(8 * kWave) void batch_pipe_kernel(const BatchParams bp,
+                                                               const int32_t* runs, int nruns) {
+  using R = double;
+  using L = Pipe<R, N, NQ>;
+  constexpr int NQ2 = L::NQ2;
+  constexpr unsigned KP = kWave * sizeof(R);
+  __shared__ __attribute__((aligned(1024))) R tq[2][L::tile_alloc];
+  __shared__ __attribute__((aligned(16))) R xm[L::metric];
+  __shared__ __attribute__((aligned(16))) R xf[L::xf];
+  __shared__ __attribute__((aligned(16))) R xw[L::weights_in_lds ? L::wts : 1];
+  const int r = xcd_remap(blockIdx.x, gridDim.x);
+  if (r >= nruns) return;
+  const int pi = runs[4 * r], g = runs[4 * r + 1];
+  const BatchProb pr = bp.prob[pi];
+  PipeRun<R> run;
+  run.qin = bp.Qin + pr.qoff;
+  run.qout = bp.Qout + pr.qoff;
+  run.res = bp.res + pr.qoff;
+  run.resw = bp.res + pr.qoff;
+  run.slice_vals = (size_t)pr.nEG * L::tile;
+  run.g = g;
+  run.goff = (size_t)g * L::tile;
+  run.s0 = runs[4 * r + 2];
+  run.nit = runs[4 * r + 3];
+  const size_t gg = (size_t)pr.g0 + g;
+  run.vol = make_rsrc(bp.vol + gg * 6 * NQ2 * kWave, 6u * NQ2 * KP);
+  run.face = make_rsrc(bp.face + gg * 12 * NQ * kWave, 12u * NQ * KP);
+  run.nbr = make_rsrc(bp.nbr + gg * 8 * kWave, 8u * kWave * 4u);
+  run.kfull = pr.K;
+  run.slast = pr.S - 1;
+  run.klast = pr.klast;
+  StageScalars<R> k;
+  k.tau_p = bp.tau_p;
+  k.tau_u = bp.tau_u;
+  k.A = bp.rkA;
+  k.B = bp.rkB;
+  k.dt = pr.dt;
+  k.c2s = 1.0;
+  pipe_run<R, N, NQ>(run, k, tq, xm, xf, xw);
 }
 
 namespace {
@@ -481,6 +560,46 @@ bool pipe_supported(int N, int nq, bool fp32) {
     case 3: return fp32 ? fits_n<float, 3>(nq) : fits_n<double, 3>(nq);
     case 4: return fp32 ? fits_n<float, 4>(nq) : fits_n<double, 4>(nq);
     default: return false;
+  }
+}
+
+namespace {
+
+template <int N, int NQ>
+int launch_batch_nq(const BatchParams& p, const int32_t* runs, int32_t nruns, void* stream) {
+  if constexpr (!Pipe<double, N, NQ>::fits) {
+    return (int)hipErrorInvalidValue;
+  } else {
+    hipLaunchKernelGGL((batch_pipe_kernel<N, NQ>), dim3(nruns), dim3(8 * kWave), 0,
+                       static_cast<hipStream_t>(stream), p, runs, nruns);
+    return (int)hipGetLastError();
+  }
+}
+
+template <int N>
+int launch_batch_n(int nq, const BatchParams& p, const int32_t* runs, int32_t nruns,
+                   void* stream) {
+  switch (nq - N) {
+    case 1: return launch_batch_nq<N, N + 1>(p, runs, nruns, stream);
+    case 2: return launch_batch_nq<N, N + 2>(p, runs, nruns, stream);
+    case 3: return launch_batch_nq<N, N + 3>(p, runs, nruns, stream);
+    default: return (int)hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+bool batch_pipe_supported(int N, int nq) { return pipe_supported(N, nq, false); }
+
+int launch_batch_pipe(int N, int nq, const BatchParams& p, const int32_t* runs, int32_t nruns,
+                      void* stream) {
+  if (nruns <= 0) return 0;
+  switch (N) {
+    case 1: return launch_batch_n<1>(nq, p, runs, nruns, stream);
+    case 2: return launch_batch_n<2>(nq, p, runs, nruns, stream);
+    case 3: return launch_batch_n<3>(nq, p, runs, nruns, stream);
+    case 4: return launch_batch_n<4>(nq, p, runs, nruns, stream);
+    default: return (int)hipErrorInvalidValue;
   }
 }
 

@@ -151,6 +151,7 @@ struct BatchProb {
   int64_t qoff;          // first value of the problem in the batch state arrays
   int32_t nEG, S, K;     // element groups per slice, slices, elements (lanes in use)
   int32_t g0;            // first element group of the problem in the geometry arrays
+  int32_t klast;         // elements holding real slices in the last (virtual) slice
   double dt;
 };
 struct BatchParams {
@@ -171,6 +172,12 @@ struct BatchParams {
 int launch_batch_stage(int N, int nq, const BatchParams& p, int grid, void* stream);
 // Split-work kernel, one four-wave workgroup per item.
 int launch_batch_split(int N, int nq, const BatchParams& p, void* stream);
+// Pipelined kernel (FP64), one eight-wave workgroup per run: runs[4 r ..] =
+// (problem, element group, first virtual slice, slice count); items are not
+// read from p.items.  Only where batch_pipe_supported(N, nq).
+bool batch_pipe_supported(int N, int nq);
+int launch_batch_pipe(int N, int nq, const BatchParams& p, const int32_t* runs, int32_t nruns,
+                      void* stream);
 
 // Per-slice norms over the tiled layout (padding skipped): partial sums into
 // `partials` [S][nblk][4] then a fixed-order reduction into `out` [S][4].

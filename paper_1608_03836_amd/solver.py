@@ -232,6 +232,11 @@ class Batch:
     def set_schedule(self, wg_per_cu, order=0):
         B.wadg_batch_set_schedule(self.b, wg_per_cu, order)
 
+    def set_runs(self, run_slices):
+        """Pipelined kernel with runs of at most run_slices slices per
+        workgroup (0: the item schedule of set_schedule)."""
+        B.wadg_batch_set_runs(self.b, run_slices)
+
     def tune(self, Q, dt, work=None, reps=3, stream=None):
         work = self.workspace() if work is None else work
         return B.wadg_batch_tune(self.b, Q, work, dt, reps, stream)

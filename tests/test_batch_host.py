@@ -67,4 +67,5 @@ def test_batch_create_validates_before_device_work():
         == W.WADG_E_INVALID
     assert W.LIB.wadg_batch_integrate(None, None, None, None, 1, None) == W.WADG_E_INVALID
     assert W.LIB.wadg_batch_replay(None, None) == W.WADG_E_INVALID
+    assert W.LIB.wadg_batch_set_runs(None, 4) == W.WADG_E_INVALID
     W.LIB.wadg_batch_destroy(None)

@@ -94,25 +94,32 @@ def test_batch_matches_oracle(W, small):
 
 
 def test_schedules_and_tuner_bitwise_invariant(W, small):
+    """Item schedules (split and persistent kernels, both orders), runs of
+    the pipelined kernel (one slice each, three, and the default sixteen:
+    runs of one slice have no prefetch, sixteen cover whole problems) and the
+    tuner's choice all give the same bits."""
     _print_case(test="batch-schedules")
     probs, batch = small
     dts = [p.dt for p in probs]
     outs = []
-    for wg, order in ((2, 0), (0, 0), (1, 1), (8, 1), (4, 0)):
+    for wg, order, runs in ((2, 0, 0), (0, 0, 0), (1, 1, 0), (8, 1, 0), (4, 0, 0), (0, 0, 1),
+                            (0, 0, 3), (0, 0, 16)):
         batch.set_schedule(wg, order)
+        batch.set_runs(runs)
         Q = batch.upload([p.Q0 for p in probs])
         batch.integrate(Q, dts, 3)
         outs.append(batch.download(Q))
     Q0 = batch.upload([p.Q0 for p in probs])
-    wg, order, us = batch.tune(Q0, dts, reps=2)
-    assert wg in (0, 1, 2, 4, 8) and order in (0, 1) and us > 0
+    wg, order, runs, us = batch.tune(Q0, dts, reps=2)
+    assert wg in (0, 1, 2, 4, 8) and order in (0, 1) and runs in (0, 4, 8, 16, 32, 128)
+    assert us > 0
     assert np.array_equal(Q0.cpu().numpy(), batch.upload([p.Q0 for p in probs]).cpu().numpy())
     batch.integrate(Q0, dts, 3)
     outs.append(batch.download(Q0))
     for o in outs[1:]:
         for a, b in zip(o, outs[0]):
             assert np.array_equal(a, b)
-    batch.set_schedule(0, 0)   # the default
+    batch.set_runs(16)         # the default
 
 
 def test_graph_replays_equal_eager(W, small):
@@ -188,11 +195,12 @@ def test_full_batch_sampled_problems(W):
 
 
 @pytest.mark.parametrize("N,nq1", [(1, 2), (2, 4), (4, 6)])
-def test_other_degrees_both_batch_kernels(W, N, nq1):
+def test_other_degrees_all_batch_kernels(W, N, nq1):
     """Batches of other degrees and quadratures, mixing packed (4 and 9
     elements) and multi-group (100 elements) meshes with c^2 varying: every
     problem equals the single-problem path bitwise, with the split-work
-    kernel (one workgroup per item) and with persistent workgroups."""
+    kernel (one workgroup per item), with persistent workgroups and, where
+    it fits, with the pipelined kernel (refused with UNSUPPORTED at N = 4)."""
     from workloads import periodic_quad_mesh, c2_layered
     _print_case(test="batch-degrees", N=N, nq1=nq1)
     meshes = [periodic_quad_mesh(k, N, eps=0.05, warp="skew", rotate_seed=k) for k in (2, 3, 10)]
@@ -208,7 +216,15 @@ def test_other_degrees_both_batch_kernels(W, N, nq1):
         Q = batch.upload(Q0)
         batch.integrate(Q, dts, 2)
         outs.append(batch.download(Q))
-    batch.set_schedule(0, 0)
+    if N <= 2:      # the pipelined kernel's LDS plan fits
+        batch.set_runs(2)
+        Q = batch.upload(Q0)
+        batch.integrate(Q, dts, 2)
+        outs.append(batch.download(Q))
+    else:
+        with pytest.raises(W.WadgError) as e:
+            batch.set_runs(2)
+        assert e.value.status == W.binding.WADG_E_UNSUPPORTED
     for i, (m, s) in enumerate(zip(meshes, S)):
         sol = W.Solver(m, nq1=nq1, c2=c2_layered)
         q = sol.upload(Q0[i])
@@ -217,3 +233,5 @@ def test_other_degrees_both_batch_kernels(W, N, nq1):
         assert np.all(np.isfinite(want))
         assert np.array_equal(outs[0][i], want), (i, "split")
         assert np.array_equal(outs[1][i], want), (i, "persistent")
+        if N <= 2:
+            assert np.array_equal(outs[2][i], want), (i, "pipelined")
