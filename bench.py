@@ -63,12 +63,13 @@ def kernel_choice(W, name):
 
 def stage_bytes(K, S, N, nq1, word=8):
     """Algorithmic HBM bytes of one stage launch, averaged over the 5 stages:
-    per element and slice, read Q_in and write Q_out and res (3 (N+1)^2
-    values each) and read res in 4 of the 5 stages; per element, read the
-    geometry once (6 nq1^2 volume + 12 nq1 face values, 8 int32 offsets).
-    word: bytes per value (8 FP64, 4 FP32-bulk)."""
+    per element and slice, read Q_in and write Q_out (3 (N+1)^2 values
+    each), read the residual in stages 2-5 (stage 1 has A = 0) and write it
+    in stages 1-4 (stage 5's is never read: the next step starts with A =
+    0); per element, read the geometry once (6 nq1^2 volume + 12 nq1 face
+    values, 8 int32 offsets).  word: bytes per value (8 FP64, 4 FP32-bulk)."""
     Np = (N + 1) ** 2
-    per_elem_slice = 3 * Np * word * (3 + 4 / 5)
+    per_elem_slice = 3 * Np * word * (2 + 8 / 5)
     per_elem = (6 * nq1 * nq1 + 12 * nq1) * word + 8 * 4
     return K * (S * per_elem_slice + per_elem)
 

@@ -172,7 +172,9 @@ int wadg_rhs(wadg_ctx ctx, const double* Q, double* dQdt, int32_t S, void* strea
  *   Q     device, S slices in the tiled state layout; in: start states,
  *         out: end states.
  *   work  device workspace of wadg_workspace_bytes(S) bytes, 256-B aligned,
- *         not aliasing Q; its contents on entry are ignored.
+ *         not aliasing Q; its contents on entry are ignored and on return
+ *         unspecified (the residual of each step's last stage, which the
+ *         2N-storage scheme never reads, is not stored).
  *   dt > 0 and finite, nsteps >= 0.  Asynchronous on `stream`. */
 int wadg_integrate(wadg_ctx ctx, double* Q, double* work, int32_t S, double dt,
                    int32_t nsteps, void* stream);

@@ -345,6 +345,7 @@ int wadg_integrate(wadg_ctx ctx, double* Q, double* work, int32_t S, double dt, 
       p.Qout = (cur == Q) ? other : Q;
       p.rkA = kRkA[i];
       p.rkB = kRkB[i];
+      p.res_dead = i == 4;
       int e = launch_stage(ctx, wadg::kStage, false, p, stream);
       if (e) return hip_fail((hipError_t)e, "stage kernel launch");
       cur = static_cast<double*>(p.Qout);
@@ -394,6 +395,7 @@ int wadg_integrate_fp32(wadg_ctx ctx, double* Q, void* work, int32_t S, double d
       p.Qout = (cur == q0) ? q1 : q0;
       p.rkA = kRkA[i];
       p.rkB = kRkB[i];
+      p.res_dead = i == 4;
       e = launch_stage(ctx, wadg::kStage, true, p, stream);
       if (e) return hip_fail((hipError_t)e, "stage kernel launch");
       cur = static_cast<float*>(p.Qout);

@@ -62,6 +62,7 @@ int one_step(wadg_ctx ctx, const double* in, double* out, double* t0, double* t1
     p.Qout = i == 4 ? out : (i % 2 == 0 ? t0 : t1);
     p.rkA = kRkA[i];
     p.rkB = kRkB[i];
+    p.res_dead = i == 4;
     int e = launch_stage(ctx, wadg::kStage, false, p, stream);
     if (e) return hip_fail((hipError_t)e, "stage kernel launch");
     cur = static_cast<const double*>(p.Qout);

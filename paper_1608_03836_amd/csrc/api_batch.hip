@@ -189,6 +189,7 @@ int batch_stage(wadg_batch b, const wadg::BatchProb* prob, const double* qin, do
   p.tau_u = b->tau_u;
   p.rkA = kRkA[i];
   p.rkB = kRkB[i];
+  p.res_dead = i == 4;
   // runs of slices: the pipelined kernel (wadg_batch_set_runs); one
   // workgroup per item: the split-work kernel; persistent workgroups: the
   // streamed kernel (wadg_batch_set_schedule)

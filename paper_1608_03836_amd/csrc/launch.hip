@@ -89,6 +89,7 @@ wadg::StageParams base_params(wadg_ctx c, int32_t S) {
   p.tau_u = c->tau_u;
   p.c2_scale = c->c2_scale;
   p.res_out = nullptr;
+  p.res_dead = 0;
   return p;
 }
 

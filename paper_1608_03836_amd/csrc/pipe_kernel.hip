@@ -58,6 +58,8 @@ struct Pipe {
   static constexpr unsigned rows = (tile_bytes + 1023u) / 1024u;
   static constexpr unsigned tile_alloc = rows * 1024u / sizeof(R);
   static constexpr unsigned metric = 4u * NQ2 * kWave;         // planes 0..3 of the geometry
+  static constexpr unsigned metric_rows = metric * sizeof(R) / 1024u;   // whole 1 KB rows
+  static_assert(metric * sizeof(R) % 1024u == 0, "the metric planes are whole 1 KB rows");
   static constexpr unsigned xf = 4u * 3 * NP1 * kWave;         // face terms [4][3][NP1][64]
   static constexpr unsigned wts = 2u * NQ2 * kWave;            // mass weights [2][NQ2][64]
   static constexpr size_t lds_base = (2 * tile_alloc + metric + xf) * sizeof(R);
@@ -70,12 +72,17 @@ struct Pipe {
   static constexpr bool fits = weights_in_lds;
 };
 
-// Lane-parallel copy of `n16` 16-byte chunks from global memory into LDS by
-// the waves [w0, w0 + nw) of the workgroup (prologue only).
-__device__ __forceinline__ void copy_to_lds(rsrc_t src, void* dst, unsigned n16, int tid0,
-                                            int nthreads) {
-  for (unsigned c = (unsigned)tid0; c < n16; c += (unsigned)nthreads)
-    *reinterpret_cast<u32x4*>(static_cast<char*>(dst) + c * 16u) = ld128(src, c * 16u);
+// Rows r = w, w + nw, ... < ROWS of 1 KB (64 lanes x 16 B) from global
+// memory into LDS (row r at dst + 1 KB r) with direct-to-LDS loads, by wave
+// w of nw sharing the copy: the loads are issued back to back and land
+// without registers; the caller waits (vmcnt) before the barrier that
+// publishes them.
+template <unsigned ROWS>
+__device__ __forceinline__ void rows_to_lds(rsrc_t src, void* dst, int w, int nw, int lane) {
+  for (unsigned r = (unsigned)w; r < ROWS; r += (unsigned)nw)
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+        src, (__attribute__((address_space(3))) void*)(static_cast<char*>(dst) + r * 1024u), 16,
+        (r * 64u + (unsigned)lane) * 16u, 0, 0, 0);
 }
 
 // The loader wave's request of one input tile: `rows` direct-to-LDS loads of
@@ -198,6 +205,7 @@ struct PipeRun {
   int g, s0, nit;
   rsrc_t vol, face, nbr;
   int kfull, slast, klast;
+  unsigned res_bytes;   // bytes of a residual tile written: 0 drops the stores
   size_t goff;   // g times the values of one tile
   // offset (in values) of the group's tile in slice s
   __device__ __forceinline__ size_t grp(int s) const { return (size_t)s * slice_vals + goff; }
@@ -290,6 +298,7 @@ __device__ __forceinline__ void pipe_update_role(const PipeRun<R>& run, const St
   }
   R resv[NP];
   load_res<R, NP, kStage>(k, make_rsrc(run.res + grp(s0), tile * sizeof(R)), C, kb, resv);
+  wait_vm_all();                                             // metric rows in LDS
   __syncthreads();                                           // prologue done
   for (int it = 0; it < nit; ++it) {
     const int s = s0 + it;
@@ -344,7 +353,7 @@ __device__ __forceinline__ void pipe_update_role(const PipeRun<R>& run, const St
       wadg_inverse_wide<R, N, NQ>(b, wq, dq);
     }
     const rsrc_t qo = make_rsrc(run.qout + grp(s), tile * sizeof(R));
-    const rsrc_t rw = make_rsrc(run.resw + grp(s), tile * sizeof(R));
+    const rsrc_t rw = make_rsrc(run.resw + grp(s), run.res_bytes);
     const bool active = e < (s == run.slast ? run.klast : run.kfull);
     finish_field<R, NP, kStage>(k, qo, rw, Pt, C, kb, active, resv, dq);
     if (it + 1 < nit)
@@ -369,11 +378,11 @@ __device__ __forceinline__ void pipe_run(const PipeRun<R>& run, const StageScala
   constexpr int kLoader = 4;
   auto tile_src = [&](int s) { return make_rsrc(run.qin + run.grp(s), L::tile_bytes); };
 
-  // prologue: metric planes 0..3 of the group into LDS (every wave but the
-  // loader), the first tile by the loader
-  if (wave != kLoader)
-    copy_to_lds(run.vol, xm, L::metric * sizeof(R) / 16u,
-                (wave < kLoader ? wave : wave - 1) * kWave + lane, 7 * kWave);
+  // prologue: metric planes 0..3 of the group into LDS by the update waves
+  // and the loader (the face waves gather their first traces meanwhile),
+  // the first tile by the loader
+  if (wave <= 2 || wave == kLoader)
+    rows_to_lds<L::metric_rows>(run.vol, xm, wave == kLoader ? 3 : wave, 4, lane);
   if (wave == 0) {
     pipe_update_role<R, N, NQ, 0>(run, k, lane, kb, tq, xm, xf, xw);
   } else if (wave == 1) {
@@ -442,6 +451,7 @@ __global__ __launch_bounds__(8 * kWave) void pipe_kernel(const StageParams p, in
   run.kfull = p.K;
   run.slast = -1;
   run.klast = p.K;
+  run.res_bytes = p.res_dead ? 0u : L::tile * sizeof(R);
   pipe_run<R, N, NQ>(run, stage_scalars<R>(p), tq, xm, xf, xw);
 }
 
@@ -483,6 +493,7 @@ __global__ __launch_bounds__(8 * kWave) void batch_pipe_kernel(const BatchParams
   run.kfull = pr.K;
   run.slast = pr.S - 1;
   run.klast = pr.klast;
+  run.res_bytes = bp.res_dead ? 0u : L::tile * sizeof(R);
   StageScalars<R> k;
   k.tau_p = bp.tau_p;
   k.tau_u = bp.tau_u;

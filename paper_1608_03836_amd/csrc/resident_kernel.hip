@@ -237,7 +237,7 @@ __global__ __launch_bounds__(kResidentWaves * kWave) void resident_kernel(const 
       const rsrc_t qo = tile_rsrc(Qout, s);
       const size_t toff = (size_t)s * slice_vals + goff;
       const rsrc_t rr = make_rsrc(Res + toff, (RHS || k.A == R(0)) ? 0u : tile_bytes);
-      const rsrc_t rw = make_rsrc(ResW + toff, RHS ? 0u : tile_bytes);
+      const rsrc_t rw = make_rsrc(ResW + toff, RHS || p.res_dead ? 0u : tile_bytes);
       const rsrc_t qn = tile_rsrc(Qin, s + 2);
       if (pressure)
         resident_item<R, N, NQ, MODE, true>(k, qs, qo, rr, rw, qn, tq, gv, gf, nbo, lane,

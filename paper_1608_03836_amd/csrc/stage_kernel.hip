@@ -233,7 +233,7 @@ __global__ __launch_bounds__(2 * kWave) void stage_kernel(const StageParams p) {
   B.qout = make_rsrc(static_cast<R*>(p.Qout) + grp, tile * sizeof(R));
   B.res = make_rsrc(static_cast<R*>(MODE == kRhs ? p.Qout : p.res) + grp, tile * sizeof(R));
   B.resw = make_rsrc(static_cast<R*>(p.res_out ? p.res_out : p.res) + grp,
-                     MODE == kStage ? tile * sizeof(R) : 0u);
+                     MODE == kStage && !p.res_dead ? tile * sizeof(R) : 0u);
   B.qslice = make_rsrc(Qin + slice, (unsigned)p.nEG * tile * sizeof(R));
   B.vol = make_rsrc(static_cast<const R*>(p.vol) + (size_t)eg * 6 * NQ2 * kWave, 6u * NQ2 * KP);
   B.face = make_rsrc(static_cast<const R*>(p.face) + (size_t)eg * 12 * NQ * kWave,
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(2 * kWave) void batch_stage_kernel(const BatchParam
     B.qin = make_rsrc(bp.Qin + grp, tile * sizeof(R));
     B.qout = make_rsrc(bp.Qout + grp, tile * sizeof(R));
     B.res = make_rsrc(bp.res + grp, tile * sizeof(R));
-    B.resw = B.res;
+    B.resw = make_rsrc(bp.res + grp, bp.res_dead ? 0u : tile * sizeof(R));
     B.qslice = make_rsrc(bp.Qin + slice, (unsigned)pr.nEG * tile * sizeof(R));
     B.vol = make_rsrc(bp.vol + gg * 6 * NQ2 * kWave, 6u * NQ2 * KP);
     B.face = make_rsrc(bp.face + gg * 12 * NQ * kWave, 12u * NQ * KP);

@@ -87,6 +87,9 @@ struct StageParams {
   double rkA, rkB, dt;
   double c2_scale;       // c^2 multiplier (pressure mass weights)
   int32_t reverse;       // nonzero: the work items in reverse order
+  int32_t res_dead;      // nonzero (stage mode): the residual this stage writes is never
+                         // read -- the last stage of a step, the next step starting with
+                         // A = 0 -- so the kernel may drop its store
   AdjMassParams adj;     // kApplyAMass only
 };
 
@@ -165,6 +168,7 @@ struct BatchParams {
   const double* face;    // [all groups][3][4][nq][64]
   const int32_t* nbr;    // [all groups][2][4][64]
   double tau_p, tau_u, rkA, rkB;
+  int32_t res_dead;      // as StageParams::res_dead
 };
 // Streamed kernel, persistent two-wave workgroups: grid = number of
 // workgroups (each loops over items with stride grid), or nitems for one
