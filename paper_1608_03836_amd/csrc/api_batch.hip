@@ -103,29 +103,53 @@ int32_t last_slice_elements(const wadg_batch b, int i) {
 // Runs of the pipelined kernel: for every problem and element group of its
 // virtual mesh, the virtual slices in which the group holds a real element
 // (all but, possibly, the last), cut into ceil(n / run_slices) runs of
-// nearly equal length.  Order: longest first, dealt round-robin into the
-// eight contiguous ranges that the kernel's XCD remap gives the XCDs, so
-// every XCD gets the same mix and ends on its shortest runs (runs of equal
-// length stay problem-major).  Uploaded like the work list.
+// nearly equal length.  Placement: workgroups are dealt to the eight XCDs
+// round-robin (block b on XCD b % 8), so the list is laid out per block.
+// Whole problems go to one XCD each (largest first, to the XCD with the
+// least work so far), so that the neighbour traces a group reads come from
+// tiles its own XCD has just loaded; each XCD then takes its runs longest
+// first (runs of equal length problem-major).  Blocks past the end of
+// their XCD's list get an empty run (problem -1).  Uploaded like the work
+// list.
 int batch_upload_runs(wadg_batch b) {
-  std::vector<std::array<int32_t, 4>> list;
+  using Run = std::array<int32_t, 4>;
+  std::vector<std::vector<Run>> per(b->nprob);
+  std::vector<int64_t> work(b->nprob, 0);
   for (int i = 0; i < b->nprob; ++i)
     for (int g = 0; g < b->nEG[i]; ++g) {
       const int n = b->Sv[i] - (g * wadg::kWave >= last_slice_elements(b, i) ? 1 : 0);
       const int c = (n + b->run_slices - 1) / b->run_slices;
       for (int j = 0; j < c; ++j) {
         const int s0 = (int)((int64_t)j * n / c), s1 = (int)((int64_t)(j + 1) * n / c);
-        list.push_back({i, g, s0, s1 - s0});
+        per[i].push_back({i, g, s0, s1 - s0});
       }
+      work[i] += n;
     }
-  std::stable_sort(list.begin(), list.end(),
-                   [](const std::array<int32_t, 4>& x, const std::array<int32_t, 4>& y) {
-                     return x[3] > y[3];
-                   });
+  std::vector<int> order(b->nprob);
+  for (int i = 0; i < b->nprob; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
+  constexpr int kXcds = 8;
+  std::vector<std::vector<Run>> xcd(kXcds);
+  int64_t load[kXcds] = {};
+  for (int i : order) {
+    int x = 0;
+    for (int y = 1; y < kXcds; ++y)
+      if (load[y] < load[x]) x = y;
+    load[x] += work[i];
+    xcd[x].insert(xcd[x].end(), per[i].begin(), per[i].end());
+  }
+  size_t longest = 0;
+  for (auto& l : xcd) {
+    std::stable_sort(l.begin(), l.end(), [](const Run& u, const Run& v) { return u[3] > v[3]; });
+    longest = std::max(longest, l.size());
+  }
   std::vector<int32_t> r;
-  r.reserve(list.size() * 4);
-  for (int x = 0; x < 8; ++x)
-    for (size_t k = (size_t)x; k < list.size(); k += 8) r.insert(r.end(), list[k].begin(), list[k].end());
+  r.reserve(longest * kXcds * 4);
+  for (size_t j = 0; j < longest; ++j)
+    for (int x = 0; x < kXcds; ++x) {
+      const Run e = j < xcd[x].size() ? xcd[x][j] : Run{-1, 0, 0, 0};
+      r.insert(r.end(), e.begin(), e.end());
+    }
   if (r.size() / 4 >= (size_t)1 << 31) return fail(WADG_E_INVALID, "too many runs");
   WADG_HIP(hipDeviceSynchronize());
   if (b->d_runs) WADG_HIP(hipFree(b->d_runs));

@@ -457,7 +457,8 @@ __global__ __launch_bounds__(8 * kWave) void pipe_kernel(const StageParams p, in
 
 // Batched LSRK stage (FP64) over a list of runs of many independent
 // problems: run r = (problem, element group of its virtual mesh, first
-// virtual slice, slice count), one workgroup each.  The problem's
+// virtual slice, slice count) for workgroup r (problem -1: nothing to do;
+// the list is laid out for the XCD each workgroup lands on).  The problem's
 // descriptor supplies the state offset, geometry groups and dt, and the
 // real element count of every virtual slice (unused copies of a packed
 // last slice are not written).
@@ -472,8 +473,8 @@ __global__ __launch_bounds__(8 * kWave) void batch_pipe_kernel(const BatchParams
   __shared__ __attribute__((aligned(16))) R xm[L::metric];
   __shared__ __attribute__((aligned(16))) R xf[L::xf];
   __shared__ __attribute__((aligned(16))) R xw[L::weights_in_lds ? L::wts : 1];
-  const int r = xcd_remap(blockIdx.x, gridDim.x);
-  if (r >= nruns) return;
+  const int r = blockIdx.x;
+  if (r >= nruns || runs[4 * r] < 0) return;   // whole workgroup: no barrier reached
   const int pi = runs[4 * r], g = runs[4 * r + 1];
   const BatchProb pr = bp.prob[pi];
   PipeRun<R> run;
