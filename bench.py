@@ -220,7 +220,7 @@ def run_fp32(args):
     k = KERNEL_NAMES[sol.kernel_in_use(fp32=True)]
     # the events bracket the whole call: 5 nsteps stage launches plus the two
     # FP64<->FP32 conversions at the ends of the sweep
-    kname = f"{k}<float,{N},{prob.nq1},false>"
+    kname = f"{k}<float,{N},{prob.nq1}>"
     line["roofline"] = roofline(kname, stage_bytes(K, S, N, prob.nq1, word=4),
                                 sum(ev) / (args.steps * 5 * prob.nsteps),
                                 measured_traffic(kname, prob.name))
@@ -468,7 +468,7 @@ def main():
         sol.set_schedule(args.tile_groups, args.tile_slices)
     sol.set_kernel(kernel_choice(W, args.kernel))
     kname = KERNEL_NAMES[sol.kernel_in_use()]
-    kname += f"<double,{prob.N},{prob.nq1},false>"
+    kname += f"<double,{prob.N},{prob.nq1}>"
     S, K, N = prob.S, prob.K, prob.N
     Q = sol.upload(prob.Q0)
     work = sol.workspace(S)

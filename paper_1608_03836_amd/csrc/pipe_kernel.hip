@@ -261,8 +261,9 @@ __device__ __forceinline__ void pipe_face_role(const PipeRun<R>& run, const Stag
 // face terms are in LDS -- the face terms in face order 0..3, the mass
 // inverse and the stage update of its field.  Mass weights c^2/J (times the
 // c^2 scale) or 1/J held for the whole run; the residual requested one
-// slice ahead.  Barriers: one after the prologue, two per item.
-template <typename R, int N, int NQ, int C>
+// slice ahead.  RD: the residual is not stored (the last stage of a
+// step).  Barriers: one after the prologue, two per item.
+template <typename R, int N, int NQ, int C, bool RD>
 __device__ __forceinline__ void pipe_update_role(const PipeRun<R>& run, const StageScalars<R>& k,
                                                  int lane, unsigned kb,
                                                  R (*tq)[Pipe<R, N, NQ>::tile_alloc],
@@ -355,9 +356,24 @@ __device__ __forceinline__ void pipe_update_role(const PipeRun<R>& run, const St
     const rsrc_t qo = make_rsrc(run.qout + grp(s), tile * sizeof(R));
     const rsrc_t rw = make_rsrc(run.resw + grp(s), run.res_bytes);
     const bool active = e < (s == run.slast ? run.klast : run.kfull);
-    finish_field<R, NP, kStage>(k, qo, rw, Pt, C, kb, active, resv, dq);
-    if (it + 1 < nit)
-      load_res<R, NP, kStage>(k, make_rsrc(run.res + grp(s + 1), tile * sizeof(R)), C, kb, resv);
+    if constexpr (!RD) {
+      finish_field<R, NP, kStage>(k, qo, rw, Pt, C, kb, active, resv, dq);
+    } else if (active) {
+      // finish_field's arithmetic without the residual's stores
+#pragma unroll
+      for (int n = 0; n < NP; ++n) {
+        const R r = mad(k.A, resv[n], k.dt * dq[n]);
+        st(qo, kb, (C * NP + n) * KP, mad(k.B, r, Pt(C * NP + n)));
+      }
+    }
+    // the next slice's residual; in a first stage (A = 0) resv keeps the
+    // zeros the prologue gave it -- rewriting them would wait for this
+    // item's stores, whose registers the compiler cannot tell apart
+    if (it + 1 < nit && k.A != R(0)) {
+      const rsrc_t rn = make_rsrc(run.res + grp(s + 1), tile * sizeof(R));
+#pragma unroll
+      for (int n = 0; n < NP; ++n) resv[n] = ldr<R>(rn, kb, (C * NP + n) * KP);
+    }
     __syncthreads();                                         // item done
   }
 }
@@ -366,7 +382,7 @@ __device__ __forceinline__ void pipe_update_role(const PipeRun<R>& run, const St
 // arrays (Pipe<>).  Waves 0..2 (one per SIMD) carry the volume terms and
 // the updates of p, u, v; wave 4 shares SIMD 0 with the pressure wave as the
 // loader; waves 3, 5, 6, 7 the faces 0..3.
-template <typename R, int N, int NQ>
+template <typename R, int N, int NQ, bool RD>
 __device__ __forceinline__ void pipe_run(const PipeRun<R>& run, const StageScalars<R>& k,
                                          R (*tq)[Pipe<R, N, NQ>::tile_alloc], R* xm, R* xf,
                                          R* xw) {
@@ -384,11 +400,11 @@ __device__ __forceinline__ void pipe_run(const PipeRun<R>& run, const StageScala
   if (wave <= 2 || wave == kLoader)
     rows_to_lds<L::metric_rows>(run.vol, xm, wave == kLoader ? 3 : wave, 4, lane);
   if (wave == 0) {
-    pipe_update_role<R, N, NQ, 0>(run, k, lane, kb, tq, xm, xf, xw);
+    pipe_update_role<R, N, NQ, 0, RD>(run, k, lane, kb, tq, xm, xf, xw);
   } else if (wave == 1) {
-    pipe_update_role<R, N, NQ, 1>(run, k, lane, kb, tq, xm, xf, xw);
+    pipe_update_role<R, N, NQ, 1, RD>(run, k, lane, kb, tq, xm, xf, xw);
   } else if (wave == 2) {
-    pipe_update_role<R, N, NQ, 2>(run, k, lane, kb, tq, xm, xf, xw);
+    pipe_update_role<R, N, NQ, 2, RD>(run, k, lane, kb, tq, xm, xf, xw);
   } else if (wave == kLoader) {
     // the next slice's tile while this one is computed
     tile_to_lds<L::rows>(tile_src(run.s0), tq[0], lane);
@@ -415,8 +431,10 @@ __device__ __forceinline__ void pipe_run(const PipeRun<R>& run, const StageScala
 
 // Workgroup b: element group g and slices [s0, s1) of one problem;
 // grid = nEG * chunks, chunk j of group g holds slices
-// [j S / chunks, (j + 1) S / chunks).  LSRK stage mode only.
-template <typename R, int N, int NQ>
+// [j S / chunks, (j + 1) S / chunks).  LSRK stage mode only; RD = p.res_dead
+// (the last stage of a step, a kernel of its own so that the other stages'
+// code is not shaped by the branch).
+template <typename R, int N, int NQ, bool RD>
 __global__ __launch_bounds__(8 * kWave) void pipe_kernel(const StageParams p, int chunks) {
   using L = Pipe<R, N, NQ>;
   constexpr int NQ2 = L::NQ2;
@@ -451,8 +469,8 @@ __global__ __launch_bounds__(8 * kWave) void pipe_kernel(const StageParams p, in
   run.kfull = p.K;
   run.slast = -1;
   run.klast = p.K;
-  run.res_bytes = p.res_dead ? 0u : L::tile * sizeof(R);
-  pipe_run<R, N, NQ>(run, stage_scalars<R>(p), tq, xm, xf, xw);
+  run.res_bytes = RD ? 0u : L::tile * sizeof(R);
+  pipe_run<R, N, NQ, RD>(run, stage_scalars<R>(p), tq, xm, xf, xw);
 }
 
 // Batched LSRK stage (FP64) over a list of runs of many independent
@@ -461,8 +479,8 @@ __global__ __launch_bounds__(8 * kWave) void pipe_kernel(const StageParams p, in
 // the list is laid out for the XCD each workgroup lands on).  The problem's
 // descriptor supplies the state offset, geometry groups and dt, and the
 // real element count of every virtual slice (unused copies of a packed
-// last slice are not written).
-template <int N, int NQ>
+// last slice are not written).  RD = bp.res_dead, as for pipe_kernel.
+template <int N, int NQ, bool RD>
 __global__ __launch_bounds__(8 * kWave) void batch_pipe_kernel(const BatchParams bp,
                                                                const int32_t* runs, int nruns) {
   using R = double;
@@ -494,7 +512,7 @@ __global__ __launch_bounds__(8 * kWave) void batch_pipe_kernel(const BatchParams
   run.kfull = pr.K;
   run.slast = pr.S - 1;
   run.klast = pr.klast;
-  run.res_bytes = bp.res_dead ? 0u : L::tile * sizeof(R);
+  run.res_bytes = RD ? 0u : L::tile * sizeof(R);
   StageScalars<R> k;
   k.tau_p = bp.tau_p;
   k.tau_u = bp.tau_u;
@@ -502,7 +520,7 @@ __global__ __launch_bounds__(8 * kWave) void batch_pipe_kernel(const BatchParams
   k.B = bp.rkB;
   k.dt = pr.dt;
   k.c2s = 1.0;
-  pipe_run<R, N, NQ>(run, k, tq, xm, xf, xw);
+  pipe_run<R, N, NQ, RD>(run, k, tq, xm, xf, xw);
 }
 
 namespace {
@@ -526,8 +544,12 @@ int launch_nq(const StageParams& p, int cus, void* stream) {
     const int per_cu = Pipe<R, N, NQ>::lds_bytes <= 80u * 1024u ? 2 : 1;
     const int chunks = pipe_chunks(p.nEG, p.S, cus * per_cu);
     if ((int64_t)p.nEG * chunks >= (1LL << 31)) return (int)hipErrorInvalidValue;
-    hipLaunchKernelGGL((pipe_kernel<R, N, NQ>), dim3(p.nEG * chunks), dim3(8 * kWave), 0,
-                       static_cast<hipStream_t>(stream), p, chunks);
+    if (p.res_dead)
+      hipLaunchKernelGGL((pipe_kernel<R, N, NQ, true>), dim3(p.nEG * chunks), dim3(8 * kWave), 0,
+                         static_cast<hipStream_t>(stream), p, chunks);
+    else
+      hipLaunchKernelGGL((pipe_kernel<R, N, NQ, false>), dim3(p.nEG * chunks), dim3(8 * kWave),
+                         0, static_cast<hipStream_t>(stream), p, chunks);
     return (int)hipGetLastError();
   }
 }
@@ -582,8 +604,12 @@ int launch_batch_nq(const BatchParams& p, const int32_t* runs, int32_t nruns, vo
   if constexpr (!Pipe<double, N, NQ>::fits) {
     return (int)hipErrorInvalidValue;
   } else {
-    hipLaunchKernelGGL((batch_pipe_kernel<N, NQ>), dim3(nruns), dim3(8 * kWave), 0,
-                       static_cast<hipStream_t>(stream), p, runs, nruns);
+    if (p.res_dead)
+      hipLaunchKernelGGL((batch_pipe_kernel<N, NQ, true>), dim3(nruns), dim3(8 * kWave), 0,
+                         static_cast<hipStream_t>(stream), p, runs, nruns);
+    else
+      hipLaunchKernelGGL((batch_pipe_kernel<N, NQ, false>), dim3(nruns), dim3(8 * kWave), 0,
+                         static_cast<hipStream_t>(stream), p, runs, nruns);
     return (int)hipGetLastError();
   }
 }
