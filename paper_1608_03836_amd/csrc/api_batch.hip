@@ -172,7 +172,9 @@ int write_descriptors(const wadg_batch b, const double* dt, wadg::BatchProb* dst
   std::vector<wadg::BatchProb> pr(b->nprob);
   for (int i = 0; i < b->nprob; ++i)
     pr[i] = wadg::BatchProb{b->offset[i], b->nEG[i], b->Sv[i], b->Kv[i], b->g0[i],
-                            last_slice_elements(b, i), dt[i]};
+                            last_slice_elements(b, i),
+                            b->pack[i] > 1 || b->K[i] < wadg::kWave ? b->K[i] : 0,
+                            dt[i]};
   WADG_HIP(hipDeviceSynchronize());
   WADG_HIP(hipMemcpy(dst, pr.data(), pr.size() * sizeof(wadg::BatchProb),
                      hipMemcpyHostToDevice));

@@ -85,6 +85,14 @@ __device__ __forceinline__ void rows_to_lds(rsrc_t src, void* dst, int w, int nw
         (r * 64u + (unsigned)lane) * 16u, 0, 0, 0);
 }
 
+// Lane L of a direct-to-LDS row load moves values 2 (L mod 32) and the next
+// of a 64-value (512 B) plane row: whether they include one of the first
+// `elems` lanes' values.  Batches skip the rest (padding, or values that
+// every group reads from its problem's first group).
+__device__ __forceinline__ bool row_lane_needed(int lane, int elems) {
+  return 2 * (lane & 31) < elems;
+}
+
 // The loader wave's request of one input tile: `rows` direct-to-LDS loads of
 // 64 lanes x 16 B, row r landing at dst + 1 KB r.
 template <unsigned ROWS>
@@ -205,16 +213,34 @@ struct PipeRun {
   int g, s0, nit;
   rsrc_t vol, face, nbr;
   int kfull, slast, klast;
+  // Batches: where this lane's geometry is.  A problem packed as copies of
+  // a K-element mesh has the same geometry in every copy, so element
+  // 64 g + lane reads that of copy 0's element e = (64 g + lane) mod K:
+  //   K < 64:  in the first group at lane e; the metric rows of that group
+  //            are copied whole for lanes < gelems = K, and the volume
+  //            terms read them at glane = e;
+  //   K >= 64: in group e / 64 at lane e % 64 (gelems = 0): this lane's
+  //            values are loaded one by one into its own LDS lane
+  //            (glane = lane);
+  // otherwise its own group and lane (glane = lane, gelems = 64).
+  // gvoff, gfoff: byte offsets of this lane's values in `vol` and `face`.
+  int glane, gelems;
+  unsigned gvoff, gfoff;
   unsigned res_bytes;   // bytes of a residual tile written: 0 drops the stores
   size_t goff;   // g times the values of one tile
   // offset (in values) of the group's tile in slice s
   __device__ __forceinline__ size_t grp(int s) const { return (size_t)s * slice_vals + goff; }
+  // real elements of the group in slice s
+  __device__ __forceinline__ int kact(int s) const {
+    const int k = (s == slast ? klast : kfull) - g * kWave;
+    return k < 0 ? 0 : k > kWave ? kWave : k;
+  }
 };
 
 // Face wave of face F: its factors and neighbour offsets held for the
 // whole run, its traces gathered one slice ahead.  Barriers as the other
 // roles: one after the prologue, two per item.
-template <typename R, int N, int NQ, int F>
+template <typename R, int N, int NQ, int F, bool BATCH>
 __device__ __forceinline__ void pipe_face_role(const PipeRun<R>& run, const StageScalars<R>& k,
                                                int lane, unsigned kb,
                                                R (*tq)[Pipe<R, N, NQ>::tile_alloc], R* xf) {
@@ -231,7 +257,8 @@ __device__ __forceinline__ void pipe_face_role(const PipeRun<R>& run, const Stag
   for (int cc = 0; cc < 3; ++cc)
 #pragma unroll
     for (int jj = 0; jj < NQ; ++jj)
-      gf[cc][jj] = ldr<R>(run.face, kb, (cc * 4 * NQ + F * NQ + jj) * KP);
+      gf[cc][jj] = ldr<R>(run.face, BATCH ? run.gfoff : kb,
+                          (cc * 4 * NQ + F * NQ + jj) * KP);
   NbrOffsets nbo;
   load_nbr(run.nbr, lane, nbo);
   Trace<R, N> tr;
@@ -263,7 +290,7 @@ __device__ __forceinline__ void pipe_face_role(const PipeRun<R>& run, const Stag
 // c^2 scale) or 1/J held for the whole run; the residual requested one
 // slice ahead.  RD: the residual is not stored (the last stage of a
 // step).  Barriers: one after the prologue, two per item.
-template <typename R, int N, int NQ, int C, bool RD>
+template <typename R, int N, int NQ, int C, bool RD, bool BATCH>
 __device__ __forceinline__ void pipe_update_role(const PipeRun<R>& run, const StageScalars<R>& k,
                                                  int lane, unsigned kb,
                                                  R (*tq)[Pipe<R, N, NQ>::tile_alloc],
@@ -284,14 +311,17 @@ __device__ __forceinline__ void pipe_update_role(const PipeRun<R>& run, const St
     if constexpr (C != 2) {
 #pragma unroll
       for (int q = 0; q < NQ2; ++q) {
-        R x = ldr<R>(vol, kb, ((C == 0 ? 4 : 5) * NQ2 + q) * KP);
+        R x = ldr<R>(vol, BATCH ? run.gvoff : kb,
+                     ((C == 0 ? 4 : 5) * NQ2 + q) * KP);
         if constexpr (C == 0) x *= k.c2s;
         xw[(C * NQ2 + q) * kWave + lane] = x;
       }
     }
   } else {
 #pragma unroll
-    for (int q = 0; q < NQ2; ++q) wq[q] = ldr<R>(vol, kb, ((C == 0 ? 4 : 5) * NQ2 + q) * KP);
+    for (int q = 0; q < NQ2; ++q)
+      wq[q] = ldr<R>(vol, BATCH ? run.gvoff : kb,
+                     ((C == 0 ? 4 : 5) * NQ2 + q) * KP);
     if constexpr (C == 0) {
 #pragma unroll
       for (int q = 0; q < NQ2; ++q) wq[q] *= k.c2s;
@@ -329,7 +359,7 @@ __device__ __forceinline__ void pipe_update_role(const PipeRun<R>& run, const St
 #pragma unroll
         for (int jj = 0; jj < NQ; ++jj)
           if (C == 0 || q == C - 1 || q == C + 1)
-            gc[q][jj] = xm[(q * NQ2 + i + NQ * jj) * kWave + lane];
+            gc[q][jj] = xm[(q * NQ2 + i + NQ * jj) * kWave + (BATCH ? run.glane : lane)];
           else
             gc[q][jj] = R(0);
       if constexpr (C == 0)
@@ -369,7 +399,8 @@ __device__ __forceinline__ void pipe_update_role(const PipeRun<R>& run, const St
     // the next slice's residual; in a first stage (A = 0) resv keeps the
     // zeros the prologue gave it -- rewriting them would wait for this
     // item's stores, whose registers the compiler cannot tell apart
-    if (it + 1 < nit && k.A != R(0)) {
+    // (batches: only for the next slice's real elements)
+    if (it + 1 < nit && k.A != R(0) && (!BATCH || lane < run.kact(s + 1))) {
       const rsrc_t rn = make_rsrc(run.res + grp(s + 1), tile * sizeof(R));
 #pragma unroll
       for (int n = 0; n < NP; ++n) resv[n] = ldr<R>(rn, kb, (C * NP + n) * KP);
@@ -382,7 +413,7 @@ __device__ __forceinline__ void pipe_update_role(const PipeRun<R>& run, const St
 // arrays (Pipe<>).  Waves 0..2 (one per SIMD) carry the volume terms and
 // the updates of p, u, v; wave 4 shares SIMD 0 with the pressure wave as the
 // loader; waves 3, 5, 6, 7 the faces 0..3.
-template <typename R, int N, int NQ, bool RD>
+template <typename R, int N, int NQ, bool RD, bool BATCH>
 __device__ __forceinline__ void pipe_run(const PipeRun<R>& run, const StageScalars<R>& k,
                                          R (*tq)[Pipe<R, N, NQ>::tile_alloc], R* xm, R* xf,
                                          R* xw) {
@@ -397,33 +428,47 @@ __device__ __forceinline__ void pipe_run(const PipeRun<R>& run, const StageScala
   // prologue: metric planes 0..3 of the group into LDS by the update waves
   // and the loader (the face waves gather their first traces meanwhile),
   // the first tile by the loader
-  if (wave <= 2 || wave == kLoader)
-    rows_to_lds<L::metric_rows>(run.vol, xm, wave == kLoader ? 3 : wave, 4, lane);
+  if (wave <= 2 || wave == kLoader) {
+    const int w = wave == kLoader ? 3 : wave;
+    if (!BATCH || run.gelems > 0) {
+      if (!BATCH || row_lane_needed(lane, run.gelems))
+        rows_to_lds<L::metric_rows>(run.vol, xm, w, 4, lane);
+    } else {
+      constexpr unsigned KP = kWave * sizeof(R);
+      for (int pp = w; pp < 4 * L::NQ2; pp += 4)
+        xm[pp * kWave + lane] = ldr<R>(run.vol, run.gvoff, (unsigned)pp * KP);
+    }
+  }
   if (wave == 0) {
-    pipe_update_role<R, N, NQ, 0, RD>(run, k, lane, kb, tq, xm, xf, xw);
+    pipe_update_role<R, N, NQ, 0, RD, BATCH>(run, k, lane, kb, tq, xm, xf, xw);
   } else if (wave == 1) {
-    pipe_update_role<R, N, NQ, 1, RD>(run, k, lane, kb, tq, xm, xf, xw);
+    pipe_update_role<R, N, NQ, 1, RD, BATCH>(run, k, lane, kb, tq, xm, xf, xw);
   } else if (wave == 2) {
-    pipe_update_role<R, N, NQ, 2, RD>(run, k, lane, kb, tq, xm, xf, xw);
+    pipe_update_role<R, N, NQ, 2, RD, BATCH>(run, k, lane, kb, tq, xm, xf, xw);
   } else if (wave == kLoader) {
     // the next slice's tile while this one is computed
-    tile_to_lds<L::rows>(tile_src(run.s0), tq[0], lane);
+    // (batches: only the rows' values of the slice's real elements)
+    auto tile_in = [&](int s, R* dst) {
+      if (!BATCH || row_lane_needed(lane, run.kact(s)))
+        tile_to_lds<L::rows>(tile_src(s), dst, lane);
+    };
+    tile_in(run.s0, tq[0]);
     wait_vm_all();
     __syncthreads();                                         // prologue done
     for (int it = 0; it < run.nit; ++it) {
-      if (it + 1 < run.nit) tile_to_lds<L::rows>(tile_src(run.s0 + it + 1), tq[(it + 1) & 1], lane);
+      if (it + 1 < run.nit) tile_in(run.s0 + it + 1, tq[(it + 1) & 1]);
       __syncthreads();                                       // face terms ready
       wait_vm_all();                                         // next tile in LDS
       __syncthreads();                                       // item done
     }
   } else if (wave == 3) {
-    pipe_face_role<R, N, NQ, 0>(run, k, lane, kb, tq, xf);
+    pipe_face_role<R, N, NQ, 0, BATCH>(run, k, lane, kb, tq, xf);
   } else if (wave == 5) {
-    pipe_face_role<R, N, NQ, 1>(run, k, lane, kb, tq, xf);
+    pipe_face_role<R, N, NQ, 1, BATCH>(run, k, lane, kb, tq, xf);
   } else if (wave == 6) {
-    pipe_face_role<R, N, NQ, 2>(run, k, lane, kb, tq, xf);
+    pipe_face_role<R, N, NQ, 2, BATCH>(run, k, lane, kb, tq, xf);
   } else {
-    pipe_face_role<R, N, NQ, 3>(run, k, lane, kb, tq, xf);
+    pipe_face_role<R, N, NQ, 3, BATCH>(run, k, lane, kb, tq, xf);
   }
 }
 
@@ -469,8 +514,11 @@ __global__ __launch_bounds__(8 * kWave) void pipe_kernel(const StageParams p, in
   run.kfull = p.K;
   run.slast = -1;
   run.klast = p.K;
+  run.glane = 0;                          // (batches only)
+  run.gelems = kWave;
+  run.gvoff = run.gfoff = 0;
   run.res_bytes = RD ? 0u : L::tile * sizeof(R);
-  pipe_run<R, N, NQ, RD>(run, stage_scalars<R>(p), tq, xm, xf, xw);
+  pipe_run<R, N, NQ, RD, false>(run, stage_scalars<R>(p), tq, xm, xf, xw);
 }
 
 // Batched LSRK stage (FP64) over a list of runs of many independent
@@ -506,8 +554,26 @@ __global__ __launch_bounds__(8 * kWave) void batch_pipe_kernel(const BatchParams
   run.s0 = runs[4 * r + 2];
   run.nit = runs[4 * r + 3];
   const size_t gg = (size_t)pr.g0 + g;
-  run.vol = make_rsrc(bp.vol + gg * 6 * NQ2 * kWave, 6u * NQ2 * KP);
-  run.face = make_rsrc(bp.face + gg * 12 * NQ * kWave, 12u * NQ * KP);
+  // a problem of fewer than 64 elements has the same geometry in every
+  // copy: every group reads its first group's (which holds copy 0 in lanes
+  // 0..K-1) at lane (64 g + lane) mod K, shared through the cache
+  const int lane = threadIdx.x & (kWave - 1);
+  const int ec = pr.kc ? (g * kWave + lane) % pr.kc : lane;   // copy 0's element
+  const unsigned gvs = 6u * NQ2 * KP, gfs = 12u * NQ * KP;     // bytes per group
+  const size_t gv = pr.kc ? (size_t)pr.g0 : gg;
+  const unsigned ngv = pr.kc ? (unsigned)(pr.kc + kWave - 1) / kWave : 1u;
+  if (pr.kc == 0 || pr.kc >= kWave) {
+    run.glane = lane;
+    run.gelems = pr.kc ? 0 : kWave;
+    run.gvoff = (unsigned)(ec / kWave) * gvs + (unsigned)(ec % kWave) * sizeof(R);
+    run.gfoff = (unsigned)(ec / kWave) * gfs + (unsigned)(ec % kWave) * sizeof(R);
+  } else {
+    run.glane = ec;
+    run.gelems = pr.kc;
+    run.gvoff = run.gfoff = (unsigned)ec * sizeof(R);
+  }
+  run.vol = make_rsrc(bp.vol + gv * 6 * NQ2 * kWave, ngv * gvs);
+  run.face = make_rsrc(bp.face + gv * 12 * NQ * kWave, ngv * gfs);
   run.nbr = make_rsrc(bp.nbr + gg * 8 * kWave, 8u * kWave * 4u);
   run.kfull = pr.K;
   run.slast = pr.S - 1;
@@ -520,7 +586,7 @@ __global__ __launch_bounds__(8 * kWave) void batch_pipe_kernel(const BatchParams
   k.B = bp.rkB;
   k.dt = pr.dt;
   k.c2s = 1.0;
-  pipe_run<R, N, NQ, RD>(run, k, tq, xm, xf, xw);
+  pipe_run<R, N, NQ, RD, true>(run, k, tq, xm, xf, xw);
 }
 
 namespace {

@@ -155,6 +155,8 @@ struct BatchProb {
   int32_t nEG, S, K;     // element groups per slice, slices, elements (lanes in use)
   int32_t g0;            // first element group of the problem in the geometry arrays
   int32_t klast;         // elements holding real slices in the last (virtual) slice
+  int32_t kc;            // copies of a K-element mesh (or K < 64): K, and every group
+                         // reads copy 0's geometry (the first groups); else 0
   double dt;
 };
 struct BatchParams {
