@@ -46,6 +46,16 @@ def test_traffic_record_follows_the_sources(tmp_path, monkeypatch):
     assert bench.measured_traffic("k<double>", "w") is None
 
 
+def test_four_array_count_by_hand():
+    # the scope table's count for the 128x128 workload: 4 x 48 values x 8 B per
+    # element and slice, (6 x 25 + 12 x 5) x 8 B of geometry per element
+    assert bench.stage_bytes_4(16384, 256, 3, 5) == 16384 * (256 * 1536 + 1680)
+    assert bench.stage_bytes_4(16384, 256, 3, 5) == pytest.approx(6.47e9, rel=1e-3)
+    r = bench.roofline("k", 8e9, 1.0, bytes_4=4e9)
+    assert r["frac_4_state_arrays"] == pytest.approx(0.5)
+    assert "frac_4_state_arrays" not in bench.roofline("k", 8e9, 1.0)
+
+
 def test_roofline_fields():
     r = bench.roofline("k", 8e9, 1.0, traffic=4e9)
     assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
