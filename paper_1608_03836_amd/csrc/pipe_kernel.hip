@@ -33,6 +33,12 @@
 //            wave 4      waits for its tile
 //   -- barrier: the current tile and the face terms are free again
 //
+// A first stage (A = 0) requests no residual; the last stage of a step,
+// whose residual is never read again, is a kernel instance of its own that
+// stores none.  The batched kernel runs the same roles over a list of runs
+// of many problems, and lets the copies of a packed mesh share one copy's
+// geometry.
+//
 // The update waves keep the element's nodal values in registers for all
 // quadrature columns.  LDS at N = 3, FP64: two input tiles (48 KB), the
 // metric planes (50 KB), face terms (24 KB) and mass weights (25 KB):
