@@ -110,6 +110,34 @@ __device__ __forceinline__ void tile_to_lds(rsrc_t src, void* dst, int lane) {
         (r * 64u + (unsigned)lane) * 16u, 0, 0, 0);
 }
 
+// Buffer stores with the non-temporal hint, for launches whose state is far
+// larger than the caches: nothing they write is read again before the
+// whole launch has streamed through.
+__device__ __forceinline__ void st_nt(rsrc_t r, unsigned voff, unsigned soff, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 2);
+}
+__device__ __forceinline__ void st_nt(rsrc_t r, unsigned voff, unsigned soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 2);
+}
+
+// a5 of the LSRK stage for field c (finish_field's stage mode, the same
+// operations in the same order) with non-temporal stores.
+template <typename R, int NP, typename FQ>
+__device__ __forceinline__ void finish_field_nt(const StageScalars<R>& k, rsrc_t qout,
+                                                rsrc_t resw, const FQ& qin, int c, unsigned kb,
+                                                bool active, const R (&resv)[NP],
+                                                const R (&dq)[NP]) {
+  constexpr unsigned KP = kWave * sizeof(R);
+  if (!active) return;
+#pragma unroll
+  for (int n = 0; n < NP; ++n) {
+    const unsigned so = (c * NP + n) * KP;
+    const R r = mad(k.A, resv[n], k.dt * dq[n]);
+    st_nt(resw, kb, so, r);
+    st_nt(qout, kb, so, mad(k.B, r, qin(c * NP + n)));
+  }
+}
+
 // Wait until every vector memory operation of this wave has completed
 // (vmcnt = 0; the other counters left at their maxima).
 __device__ __forceinline__ void wait_vm_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
@@ -295,8 +323,9 @@ __device__ __forceinline__ void pipe_face_role(const PipeRun<R>& run, const Stag
 // inverse and the stage update of its field.  Mass weights c^2/J (times the
 // c^2 scale) or 1/J held for the whole run; the residual requested one
 // slice ahead.  RD: the residual is not stored (the last stage of a
-// step).  Barriers: one after the prologue, two per item.
-template <typename R, int N, int NQ, int C, bool RD, bool BATCH>
+// step); NT: the outputs are stored with the non-temporal hint.  Barriers:
+// one after the prologue, two per item.
+template <typename R, int N, int NQ, int C, bool RD, bool NT, bool BATCH>
 __device__ __forceinline__ void pipe_update_role(const PipeRun<R>& run, const StageScalars<R>& k,
                                                  int lane, unsigned kb,
                                                  R (*tq)[Pipe<R, N, NQ>::tile_alloc],
@@ -393,13 +422,20 @@ __device__ __forceinline__ void pipe_update_role(const PipeRun<R>& run, const St
     const rsrc_t rw = make_rsrc(run.resw + grp(s), run.res_bytes);
     const bool active = e < (s == run.slast ? run.klast : run.kfull);
     if constexpr (!RD) {
-      finish_field<R, NP, kStage>(k, qo, rw, Pt, C, kb, active, resv, dq);
+      if constexpr (NT)
+        finish_field_nt<R, NP>(k, qo, rw, Pt, C, kb, active, resv, dq);
+      else
+        finish_field<R, NP, kStage>(k, qo, rw, Pt, C, kb, active, resv, dq);
     } else if (active) {
       // finish_field's arithmetic without the residual's stores
 #pragma unroll
       for (int n = 0; n < NP; ++n) {
         const R r = mad(k.A, resv[n], k.dt * dq[n]);
-        st(qo, kb, (C * NP + n) * KP, mad(k.B, r, Pt(C * NP + n)));
+        const R q = mad(k.B, r, Pt(C * NP + n));
+        if constexpr (NT)
+          st_nt(qo, kb, (C * NP + n) * KP, q);
+        else
+          st(qo, kb, (C * NP + n) * KP, q);
       }
     }
     // the next slice's residual; in a first stage (A = 0) resv keeps the
@@ -419,7 +455,7 @@ __device__ __forceinline__ void pipe_update_role(const PipeRun<R>& run, const St
 // arrays (Pipe<>).  Waves 0..2 (one per SIMD) carry the volume terms and
 // the updates of p, u, v; wave 4 shares SIMD 0 with the pressure wave as the
 // loader; waves 3, 5, 6, 7 the faces 0..3.
-template <typename R, int N, int NQ, bool RD, bool BATCH>
+template <typename R, int N, int NQ, bool RD, bool NT, bool BATCH>
 __device__ __forceinline__ void pipe_run(const PipeRun<R>& run, const StageScalars<R>& k,
                                          R (*tq)[Pipe<R, N, NQ>::tile_alloc], R* xm, R* xf,
                                          R* xw) {
@@ -446,11 +482,11 @@ __device__ __forceinline__ void pipe_run(const PipeRun<R>& run, const StageScala
     }
   }
   if (wave == 0) {
-    pipe_update_role<R, N, NQ, 0, RD, BATCH>(run, k, lane, kb, tq, xm, xf, xw);
+    pipe_update_role<R, N, NQ, 0, RD, NT, BATCH>(run, k, lane, kb, tq, xm, xf, xw);
   } else if (wave == 1) {
-    pipe_update_role<R, N, NQ, 1, RD, BATCH>(run, k, lane, kb, tq, xm, xf, xw);
+    pipe_update_role<R, N, NQ, 1, RD, NT, BATCH>(run, k, lane, kb, tq, xm, xf, xw);
   } else if (wave == 2) {
-    pipe_update_role<R, N, NQ, 2, RD, BATCH>(run, k, lane, kb, tq, xm, xf, xw);
+    pipe_update_role<R, N, NQ, 2, RD, NT, BATCH>(run, k, lane, kb, tq, xm, xf, xw);
   } else if (wave == kLoader) {
     // the next slice's tile while this one is computed
     // (batches: only the rows' values of the slice's real elements)
@@ -484,8 +520,9 @@ __device__ __forceinline__ void pipe_run(const PipeRun<R>& run, const StageScala
 // grid = nEG * chunks, chunk j of group g holds slices
 // [j S / chunks, (j + 1) S / chunks).  LSRK stage mode only; RD = p.res_dead
 // (the last stage of a step, a kernel of its own so that the other stages'
-// code is not shaped by the branch).
-template <typename R, int N, int NQ, bool RD>
+// code is not shaped by the branch); NT: non-temporal stores (launches
+// whose state is far larger than the caches).
+template <typename R, int N, int NQ, bool RD, bool NT>
 __global__ __launch_bounds__(8 * kWave) void pipe_kernel(const StageParams p, int chunks) {
   using L = Pipe<R, N, NQ>;
   constexpr int NQ2 = L::NQ2;
@@ -524,7 +561,7 @@ __global__ __launch_bounds__(8 * kWave) void pipe_kernel(const StageParams p, in
   run.gelems = kWave;
   run.gvoff = run.gfoff = 0;
   run.res_bytes = RD ? 0u : L::tile * sizeof(R);
-  pipe_run<R, N, NQ, RD, false>(run, stage_scalars<R>(p), tq, xm, xf, xw);
+  pipe_run<R, N, NQ, RD, NT, false>(run, stage_scalars<R>(p), tq, xm, xf, xw);
 }
 
 // Batched LSRK stage (FP64) over a list of runs of many independent
@@ -533,8 +570,8 @@ __global__ __launch_bounds__(8 * kWave) void pipe_kernel(const StageParams p, in
 // the list is laid out for the XCD each workgroup lands on).  The problem's
 // descriptor supplies the state offset, geometry groups and dt, and the
 // real element count of every virtual slice (unused copies of a packed
-// last slice are not written).  RD = bp.res_dead, as for pipe_kernel.
-template <int N, int NQ, bool RD>
+// last slice are not written).  RD, NT as for pipe_kernel.
+template <int N, int NQ, bool RD, bool NT>
 __global__ __launch_bounds__(8 * kWave) void batch_pipe_kernel(const BatchParams bp,
                                                                const int32_t* runs, int nruns) {
   using R = double;
@@ -592,10 +629,17 @@ __global__ __launch_bounds__(8 * kWave) void batch_pipe_kernel(const BatchParams
   k.B = bp.rkB;
   k.dt = pr.dt;
   k.c2s = 1.0;
-  pipe_run<R, N, NQ, RD, true>(run, k, tq, xm, xf, xw);
+  pipe_run<R, N, NQ, RD, NT, true>(run, k, tq, xm, xf, xw);
 }
 
 namespace {
+
+// Non-temporal stores where a launch's state (Q_in, Q_out and the residual:
+// three times `bytes`, one array) is well beyond the 256 MB memory-side
+// cache; below that the next launch may still find what this one wrote.
+// Measured on MI355X, 128x128 elements x 256 slices (4.8 GB): about 1 %
+// faster per launch in FP64 and FP32, results unchanged.
+bool nt_stores(int64_t bytes) { return 3 * bytes > (int64_t)512 << 20; }
 
 // Slice runs per element group: enough workgroups to give every CU one
 // (grid = nEG * chunks), at most one per slice.
@@ -616,12 +660,19 @@ int launch_nq(const StageParams& p, int cus, void* stream) {
     const int per_cu = Pipe<R, N, NQ>::lds_bytes <= 80u * 1024u ? 2 : 1;
     const int chunks = pipe_chunks(p.nEG, p.S, cus * per_cu);
     if ((int64_t)p.nEG * chunks >= (1LL << 31)) return (int)hipErrorInvalidValue;
-    if (p.res_dead)
-      hipLaunchKernelGGL((pipe_kernel<R, N, NQ, true>), dim3(p.nEG * chunks), dim3(8 * kWave), 0,
-                         static_cast<hipStream_t>(stream), p, chunks);
-    else
-      hipLaunchKernelGGL((pipe_kernel<R, N, NQ, false>), dim3(p.nEG * chunks), dim3(8 * kWave),
-                         0, static_cast<hipStream_t>(stream), p, chunks);
+    const dim3 grid(p.nEG * chunks), block(8 * kWave);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (nt_stores((int64_t)p.S * p.nEG * Pipe<R, N, NQ>::tile_bytes)) {
+      if (p.res_dead)
+        hipLaunchKernelGGL((pipe_kernel<R, N, NQ, true, true>), grid, block, 0, st, p, chunks);
+      else
+        hipLaunchKernelGGL((pipe_kernel<R, N, NQ, false, true>), grid, block, 0, st, p, chunks);
+    } else {
+      if (p.res_dead)
+        hipLaunchKernelGGL((pipe_kernel<R, N, NQ, true, false>), grid, block, 0, st, p, chunks);
+      else
+        hipLaunchKernelGGL((pipe_kernel<R, N, NQ, false, false>), grid, block, 0, st, p, chunks);
+    }
     return (int)hipGetLastError();
   }
 }
@@ -676,12 +727,22 @@ int launch_batch_nq(const BatchParams& p, const int32_t* runs, int32_t nruns, vo
   if constexpr (!Pipe<double, N, NQ>::fits) {
     return (int)hipErrorInvalidValue;
   } else {
-    if (p.res_dead)
-      hipLaunchKernelGGL((batch_pipe_kernel<N, NQ, true>), dim3(nruns), dim3(8 * kWave), 0,
-                         static_cast<hipStream_t>(stream), p, runs, nruns);
-    else
-      hipLaunchKernelGGL((batch_pipe_kernel<N, NQ, false>), dim3(nruns), dim3(8 * kWave), 0,
-                         static_cast<hipStream_t>(stream), p, runs, nruns);
+    const dim3 grid(nruns), block(8 * kWave);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (nt_stores((int64_t)p.nitems * Pipe<double, N, NQ>::tile_bytes)) {
+      if (p.res_dead)
+        hipLaunchKernelGGL((batch_pipe_kernel<N, NQ, true, true>), grid, block, 0, st, p, runs, nruns);
+      else
+        hipLaunchKernelGGL((batch_pipe_kernel<N, NQ, false, true>), grid, block, 0, st, p, runs,
+                           nruns);
+    } else {
+      if (p.res_dead)
+        hipLaunchKernelGGL((batch_pipe_kernel<N, NQ, true, false>), grid, block, 0, st, p, runs,
+                           nruns);
+      else
+        hipLaunchKernelGGL((batch_pipe_kernel<N, NQ, false, false>), grid, block, 0, st, p, runs,
+                           nruns);
+    }
     return (int)hipGetLastError();
   }
 }
