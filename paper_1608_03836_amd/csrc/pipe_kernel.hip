@@ -112,7 +112,9 @@ __device__ __forceinline__ void tile_to_lds(rsrc_t src, void* dst, int lane) {
 
 // Buffer stores with the non-temporal hint, for launches whose state is far
 // larger than the caches: nothing they write is read again before the
-// whole launch has streamed through.
+// whole launch has streamed through.  The residual is loaded with it too
+// (only its own item reads it); the input tile is not (its lines are also
+// the neighbours' traces).
 __device__ __forceinline__ void st_nt(rsrc_t r, unsigned voff, unsigned soff, double v) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 2);
 }
@@ -122,6 +124,14 @@ __device__ __forceinline__ void st_nt(rsrc_t r, unsigned voff, unsigned soff, fl
 
 // a5 of the LSRK stage for field c (finish_field's stage mode, the same
 // operations in the same order) with non-temporal stores.
+template <typename R>
+__device__ __forceinline__ R ldr_nt(rsrc_t r, unsigned voff, unsigned soff) {
+  if constexpr (sizeof(R) == 8)
+    return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 2));
+  else
+    return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 2));
+}
+
 template <typename R, int NP, typename FQ>
 __device__ __forceinline__ void finish_field_nt(const StageScalars<R>& k, rsrc_t qout,
                                                 rsrc_t resw, const FQ& qin, int c, unsigned kb,
@@ -445,7 +455,8 @@ __device__ __forceinline__ void pipe_update_role(const PipeRun<R>& run, const St
     if (it + 1 < nit && k.A != R(0) && (!BATCH || lane < run.kact(s + 1))) {
       const rsrc_t rn = make_rsrc(run.res + grp(s + 1), tile * sizeof(R));
 #pragma unroll
-      for (int n = 0; n < NP; ++n) resv[n] = ldr<R>(rn, kb, (C * NP + n) * KP);
+      for (int n = 0; n < NP; ++n)
+        resv[n] = NT ? ldr_nt<R>(rn, kb, (C * NP + n) * KP) : ldr<R>(rn, kb, (C * NP + n) * KP);
     }
     __syncthreads();                                         // item done
   }
