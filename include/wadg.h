@@ -418,10 +418,11 @@ int wadg_set_schedule(wadg_ctx ctx, int32_t groups_per_tile, int32_t slices_per_
  *     its slices, keeps the group's geometry on chip for the whole run and
  *     streams the next slice's input tile into LDS while computing the
  *     current one; ignores wadg_set_schedule.  Needs two input tiles, the
- *     metric planes, the face terms and one field of the load vector in
- *     LDS (N <= 3 in FP64, every N in FP32); launches of fewer than two
- *     slices, right-hand sides and the adjoint's launches take the split
- *     kernel.
+ *     metric planes, the face terms and the two mass-weight planes in LDS
+ *     (N <= 3 in FP64, every N in FP32); launches of fewer than two slices,
+ *     right-hand sides and the adjoint's launches take the split kernel.
+ *     Launches whose state (Q in, Q out and the residual) exceeds 512 MB
+ *     store their outputs with the non-temporal cache hint.
  *   WADG_KERNEL_AUTO (default): LSRK stages (FP64 and FP32) of two or more
  *     slices take the pipelined kernel where it fits, else the split
  *     kernel; right-hand-side launches the resident kernel where it fits,
