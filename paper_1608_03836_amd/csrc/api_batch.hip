@@ -168,13 +168,22 @@ int check_dt(const wadg_batch b, const double* dt) {
   return WADG_OK;
 }
 
+// Elements of one copy whose geometry every group of problem i reads
+// (wadg::BatchProb::kc), or 0: a packed mesh, or one of fewer than 64
+// elements, whose first groups' geometry a 32-bit buffer range can hold.
+int32_t copy_elements(const wadg_batch b, int i) {
+  if (b->pack[i] == 1 && b->K[i] >= wadg::kWave) return 0;
+  const int64_t groups = (b->K[i] + wadg::kWave - 1) / wadg::kWave;
+  const int64_t vol = 6LL * b->nq1 * b->nq1 * wadg::kWave * (int64_t)sizeof(double);
+  const int64_t face = 12LL * b->nq1 * wadg::kWave * (int64_t)sizeof(double);
+  return groups * (vol > face ? vol : face) < (1LL << 31) ? b->K[i] : 0;
+}
+
 int write_descriptors(const wadg_batch b, const double* dt, wadg::BatchProb* dst) {
   std::vector<wadg::BatchProb> pr(b->nprob);
   for (int i = 0; i < b->nprob; ++i)
     pr[i] = wadg::BatchProb{b->offset[i], b->nEG[i], b->Sv[i], b->Kv[i], b->g0[i],
-                            last_slice_elements(b, i),
-                            b->pack[i] > 1 || b->K[i] < wadg::kWave ? b->K[i] : 0,
-                            dt[i]};
+                            last_slice_elements(b, i), copy_elements(b, i), dt[i]};
   WADG_HIP(hipDeviceSynchronize());
   WADG_HIP(hipMemcpy(dst, pr.data(), pr.size() * sizeof(wadg::BatchProb),
                      hipMemcpyHostToDevice));
