@@ -9,29 +9,31 @@
 //   * One workgroup of eight waves per CU owns one 64-element group and a
 //     run of consecutive slices of it, and walks them one after another.
 //     The group's geometry is read once per workgroup, not once per item:
-//     the four metric planes and the two mass-weight planes stay in LDS,
-//     the face factors and neighbour offsets in the registers of the face
-//     waves.
-//   * Wave 4 is a loader: while an item is computed it streams the next
-//     slice's input tile into the other half of an LDS double buffer with
-//     gfx950's direct-to-LDS buffer loads (no registers involved), so the
-//     HBM latency of the tile is off the item's critical path.
-//   * The face waves gather the next slice's neighbour traces into
-//     registers as soon as their face terms are written, and the update
-//     waves request the next slice's residual as soon as they have stored
-//     this one's, each a full item ahead of its use.
+//     the four metric planes and the pressure mass weights stay in LDS, the
+//     velocity mass weights in the registers of their waves, the face
+//     factors and neighbour offsets in the registers of the face waves.
+//   * The items go through a two-stage pipeline: in step j the volume and
+//     face waves build item j's load vector (volume term, then the face
+//     terms in face order 0..3) and hand it over through LDS, while the
+//     inverse waves apply the mass inverse and the stage update to item
+//     j - 1.  The two halves of an item's work run on different waves, so
+//     all four SIMDs compute in every phase.
+//   * The v volume wave also loads the tiles: while an item is computed it
+//     streams the next slice's input tile into the other half of an LDS
+//     double buffer with gfx950's direct-to-LDS buffer loads (no registers
+//     involved).  The face waves gather the next slice's neighbour traces
+//     into registers as soon as their face terms are written, and the
+//     inverse waves request the next residual as soon as they have used
+//     this one, each a full item ahead of its use.
 //
-// Roles per item (two barriers):
-//   phase F  wave 0     pressure volume term (Section 4.1, weak form)
-//            waves 1, 2 the u and v components of the velocity volume term
-//                       (one SIMD each, so the pressure wave has its own)
-//            waves 3, 5, 6, 7  traces, flux and lift of faces 0..3
-//            wave 4     tile of the next slice -> LDS
-//   -- barrier: face terms in LDS
-//   phase B  waves 0..2  face terms added in face order 0..3, mass inverse
-//                        and stage update of p, u, v
-//            wave 4      waits for its tile
-//   -- barrier: the current tile and the face terms are free again
+// Waves (wave w runs on SIMD w mod 4), two barriers per step:
+//   wave 0  pressure volume term (Section 4.1, weak form)
+//   waves 1, 2  the u and v components of the velocity volume term
+//   wave 3  pressure mass inverse and update      wave 4  faces 0, 1
+//   waves 5, 6  u, v mass inverses and updates    wave 7  faces 2, 3
+//   -- barrier: face terms of item j in LDS
+//   waves 0..2 add them in face order and hand the load vectors over
+//   -- barrier: load vectors handed over, the next tile in LDS
 //
 // A first stage (A = 0) requests no residual; the last stage of a step,
 // whose residual is never read again, is a kernel instance of its own that
@@ -39,11 +41,10 @@
 // of many problems, and lets the copies of a packed mesh share one copy's
 // geometry.
 //
-// The update waves keep the element's nodal values in registers for all
-// quadrature columns.  LDS at N = 3, FP64: two input tiles (48 KB), the
-// metric planes (50 KB), face terms (24 KB) and mass weights (25 KB):
-// 147 KB, one workgroup per CU with two waves per SIMD.  Instantiated where
-// this fits in the CU's 160 KB.
+// LDS at N = 3, FP64: two input tiles (48 KB), the metric planes (50 KB),
+// face terms (24 KB), the handed-over load vectors (24 KB) and the pressure
+// mass weights (12.5 KB): 158.5 KB, one workgroup per CU with two waves per
+// SIMD.  Instantiated where this fits in the CU's 160 KB.
 
 #include <hip/hip_runtime.h>
 
@@ -67,15 +68,10 @@ struct Pipe {
   static constexpr unsigned metric_rows = metric * sizeof(R) / 1024u;   // whole 1 KB rows
   static_assert(metric * sizeof(R) % 1024u == 0, "the metric planes are whole 1 KB rows");
   static constexpr unsigned xf = 4u * 3 * NP1 * kWave;         // face terms [4][3][NP1][64]
-  static constexpr unsigned wts = 2u * NQ2 * kWave;            // mass weights [2][NQ2][64]
-  static constexpr size_t lds_base = (2 * tile_alloc + metric + xf) * sizeof(R);
-  // the mass weights (c^2/J scaled, 1/J) live in LDS where they fit, else
-  // in the registers of the update waves
-  static constexpr bool weights_in_lds = lds_base + wts * sizeof(R) <= 160u * 1024u;
-  static constexpr size_t lds_bytes = lds_base + (weights_in_lds ? wts * sizeof(R) : 0);
-  // instantiated only with the weights in LDS: the update waves' registers
-  // are needed for the nodal values
-  static constexpr bool fits = weights_in_lds;
+  static constexpr unsigned xb = 3u * NP * kWave;              // load vectors handed over [3][NP][64]
+  static constexpr unsigned wp = NQ2 * kWave;                  // pressure mass weights [NQ2][64]
+  static constexpr size_t lds_bytes = (2 * tile_alloc + metric + xf + xb + wp) * sizeof(R);
+  static constexpr bool fits = lds_bytes <= 160u * 1024u;
 };
 
 // Rows r = w, w + nw, ... < ROWS of 1 KB (64 lanes x 16 B) from global
@@ -281,10 +277,16 @@ struct PipeRun {
   }
 };
 
-// Face wave of face F: its factors and neighbour offsets held for the
-// whole run, its traces gathered one slice ahead.  Barriers as the other
-// roles: one after the prologue, two per item.
-template <typename R, int N, int NQ, int F, bool BATCH>
+// The run is a two-stage pipeline over its items: in step j the volume and
+// face waves compute item j's load vector (volume term plus the face terms
+// in face order 0..3, Section 6.4) and hand it over through LDS, while the
+// inverse waves apply the mass inverse and the stage update to item j - 1.
+// Steps j = 0..nit, two barriers each (face terms ready; load vectors
+// handed over), one barrier after the prologue.
+
+// Face wave of faces F0 and F1: their factors and neighbour offsets held
+// for the whole run, their traces gathered one item ahead.
+template <typename R, int N, int NQ, int F0, int F1, bool BATCH>
 __device__ __forceinline__ void pipe_face_role(const PipeRun<R>& run, const StageScalars<R>& k,
                                                int lane, unsigned kb,
                                                R (*tq)[Pipe<R, N, NQ>::tile_alloc], R* xf) {
@@ -296,193 +298,229 @@ __device__ __forceinline__ void pipe_face_role(const PipeRun<R>& run, const Stag
     return make_rsrc(run.qin + (size_t)s * run.slice_vals,
                      (unsigned)(run.slice_vals * sizeof(R)));
   };
-  R gf[3][NQ];
+  R gf0[3][NQ], gf1[3][NQ];
 #pragma unroll
   for (int cc = 0; cc < 3; ++cc)
 #pragma unroll
-    for (int jj = 0; jj < NQ; ++jj)
-      gf[cc][jj] = ldr<R>(run.face, BATCH ? run.gfoff : kb,
-                          (cc * 4 * NQ + F * NQ + jj) * KP);
+    for (int jj = 0; jj < NQ; ++jj) {
+      gf0[cc][jj] = ldr<R>(run.face, BATCH ? run.gfoff : kb, (cc * 4 * NQ + F0 * NQ + jj) * KP);
+      gf1[cc][jj] = ldr<R>(run.face, BATCH ? run.gfoff : kb, (cc * 4 * NQ + F1 * NQ + jj) * KP);
+    }
   NbrOffsets nbo;
   load_nbr(run.nbr, lane, nbo);
-  Trace<R, N> tr;
-  gather_trace<R, N>(slice(run.s0), nbo, F, tr);
+  Trace<R, N> tr0, tr1;
+  gather_trace<R, N>(slice(run.s0), nbo, F0, tr0);
+  gather_trace<R, N>(slice(run.s0), nbo, F1, tr1);
   __syncthreads();                                           // prologue done
-  for (int it = 0; it < nit; ++it) {
-    const R* t = tq[it & 1];
-    auto Pt = [&](int n) { return t[n * kWave + lane]; };
-    auto Ut = [&](int n) { return t[(NP + n) * kWave + lane]; };
-    auto Vt = [&](int n) { return t[(2 * NP + n) * kWave + lane]; };
-    R sp[NP1], su[NP1], sv[NP1];
-    face_terms<R, N, NQ, true, true>(F, Pt, Ut, Vt, tr, gf, k.tau_p, k.tau_u, sp, su, sv);
+  for (int it = 0; it <= nit; ++it) {
+    if (it < nit) {
+      const R* t = tq[it & 1];
+      auto Pt = [&](int n) { return t[n * kWave + lane]; };
+      auto Ut = [&](int n) { return t[(NP + n) * kWave + lane]; };
+      auto Vt = [&](int n) { return t[(2 * NP + n) * kWave + lane]; };
+      auto face = [&](int F, const Trace<R, N>& tr, const R (&gf)[3][NQ]) {
+        R sp[NP1], su[NP1], sv[NP1];
+        face_terms<R, N, NQ, true, true>(F, Pt, Ut, Vt, tr, gf, k.tau_p, k.tau_u, sp, su, sv);
 #pragma unroll
-    for (int m = 0; m < NP1; ++m) {
-      xf[((F * 3 + 0) * NP1 + m) * kWave + lane] = sp[m];
-      xf[((F * 3 + 1) * NP1 + m) * kWave + lane] = su[m];
-      xf[((F * 3 + 2) * NP1 + m) * kWave + lane] = sv[m];
+        for (int m = 0; m < NP1; ++m) {
+          xf[((F * 3 + 0) * NP1 + m) * kWave + lane] = sp[m];
+          xf[((F * 3 + 1) * NP1 + m) * kWave + lane] = su[m];
+          xf[((F * 3 + 2) * NP1 + m) * kWave + lane] = sv[m];
+        }
+      };
+      face(F0, tr0, gf0);
+      face(F1, tr1, gf1);
+      if (it + 1 < nit) {
+        gather_trace<R, N>(slice(run.s0 + it + 1), nbo, F0, tr0);
+        gather_trace<R, N>(slice(run.s0 + it + 1), nbo, F1, tr1);
+      }
     }
-    if (it + 1 < nit) gather_trace<R, N>(slice(run.s0 + it + 1), nbo, F, tr);
     __syncthreads();                                         // face terms ready
-    __syncthreads();                                         // item done
+    __syncthreads();                                         // load vectors handed over
   }
 }
 
-// Update wave of field C (0: p, 1: u, 2: v): its volume term (the
-// pressure term, or one component of the velocity term), then -- once the
-// face terms are in LDS -- the face terms in face order 0..3, the mass
-// inverse and the stage update of its field.  Mass weights c^2/J (times the
-// c^2 scale) or 1/J held for the whole run; the residual requested one
-// slice ahead.  RD: the residual is not stored (the last stage of a
-// step); NT: the outputs are stored with the non-temporal hint.  Barriers:
-// one after the prologue, two per item.
-template <typename R, int N, int NQ, int C, bool RD, bool NT, bool BATCH>
-__device__ __forceinline__ void pipe_update_role(const PipeRun<R>& run, const StageScalars<R>& k,
-                                                 int lane, unsigned kb,
+// Volume wave of field C (0: p, 1: u, 2: v): the pressure term, or one
+// component of the velocity term, of item j; once the face terms are in
+// LDS it adds them in face order 0..3 and hands the load vector over (xb).
+// The v wave also loads the next item's tile (LOADER).
+template <typename R, int N, int NQ, int C, bool LOADER, bool BATCH>
+__device__ __forceinline__ void pipe_volume_role(const PipeRun<R>& run, int lane,
                                                  R (*tq)[Pipe<R, N, NQ>::tile_alloc],
-                                                 const R* xm, const R* xf, R* xw) {
+                                                 const R* xm, const R* xf, R* xb) {
   using L = Pipe<R, N, NQ>;
   constexpr int NP1 = L::NP1, NP = L::NP, NQ2 = L::NQ2;
+  const int nit = run.nit;
+  auto tile_src = [&](int s) { return make_rsrc(run.qin + run.grp(s), L::tile_bytes); };
+  // (batches: only the rows' values of the slice's real elements)
+  auto tile_in = [&](int s, R* dst) {
+    if (!BATCH || row_lane_needed(lane, run.kact(s))) tile_to_lds<L::rows>(tile_src(s), dst, lane);
+  };
+  if constexpr (LOADER) tile_in(run.s0, tq[0]);
+  wait_vm_all();                                             // metric rows (and tile) in LDS
+  __syncthreads();                                           // prologue done
+  for (int it = 0; it <= nit; ++it) {
+    R b[NP];
+    if (it < nit) {
+      if constexpr (LOADER) {
+        if (it + 1 < nit) tile_in(run.s0 + it + 1, tq[(it + 1) & 1]);
+      }
+      const R* t = tq[it & 1];
+      // the nodal values the volume term reads, in registers for all of its
+      // columns: u and v (pressure), p (velocity)
+      R x0[NP], x1[C == 0 ? NP : 1];
+#pragma unroll
+      for (int n = 0; n < NP; ++n) {
+        x0[n] = t[((C == 0 ? NP : 0) + n) * kWave + lane];
+        if constexpr (C == 0) x1[n] = t[(2 * NP + n) * kWave + lane];
+      }
+      auto X0 = [&](int n) { return x0[n]; };
+      auto X1 = [&](int n) { return x1[n]; };
+#pragma unroll
+      for (int n = 0; n < NP; ++n) b[n] = R(0);
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) {
+        // this column's metric terms, requested before its first products
+        // (which need only the nodal values) so that they arrive meanwhile
+        R gc[4][NQ];
+        order();
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int jj = 0; jj < NQ; ++jj)
+            if (C == 0 || q == C - 1 || q == C + 1)
+              gc[q][jj] = xm[(q * NQ2 + i + NQ * jj) * kWave + (BATCH ? run.glane : lane)];
+            else
+              gc[q][jj] = R(0);
+        if constexpr (C == 0)
+          pressure_volume_column<R, N, NQ>(i, X0, X1, gc, b);
+        else
+          velocity_component_column<R, N, NQ, C>(i, X0, gc, b);
+        pin(b);
+      }
+    }
+    __syncthreads();                                         // face terms ready
+    if (it < nit) {
+#pragma unroll
+      for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int m = 0; m < NP1; ++m)
+          b[fnode<N>(f, m)] += xf[((f * 3 + C) * NP1 + m) * kWave + lane];
+#pragma unroll
+      for (int n = 0; n < NP; ++n) xb[(C * NP + n) * kWave + lane] = b[n];
+    }
+    if constexpr (LOADER) wait_vm_all();                     // next tile in LDS
+    __syncthreads();                                         // load vectors handed over
+  }
+}
+
+// Inverse wave of field C: in step j the mass inverse and the stage update
+// of item j - 1 from the handed-over load vector, with mass weights c^2/J
+// (times the c^2 scale; LDS) or 1/J (registers), the residual requested one
+// item ahead, and the item's input values of the field kept in registers
+// from the step before (the tile buffer is refilled meanwhile).  RD: the
+// residual is not stored (the last stage of a step); NT: the outputs are
+// stored with the non-temporal hint.
+template <typename R, int N, int NQ, int C, bool RD, bool NT, bool BATCH>
+__device__ __forceinline__ void pipe_inverse_role(const PipeRun<R>& run, const StageScalars<R>& k,
+                                                  int lane, unsigned kb,
+                                                  R (*tq)[Pipe<R, N, NQ>::tile_alloc],
+                                                  const R* xb, R* xw) {
+  using L = Pipe<R, N, NQ>;
+  constexpr int NP = L::NP, NQ2 = L::NQ2;
   constexpr unsigned tile = L::tile;
   constexpr unsigned KP = kWave * sizeof(R);
   const int s0 = run.s0, nit = run.nit;
   const rsrc_t vol = run.vol;
   const int e = run.g * kWave + lane;
   auto grp = [&](int s) { return run.grp(s); };
-  constexpr bool kLdsW = L::weights_in_lds;
-  // mass weights: c^2/J times the c^2 scale (p) or 1/J (u, v); in LDS the
-  // pressure wave writes plane 0 and the u wave plane 1
-  R wq[kLdsW ? 1 : NQ2];
-  if constexpr (kLdsW) {
-    if constexpr (C != 2) {
-#pragma unroll
-      for (int q = 0; q < NQ2; ++q) {
-        R x = ldr<R>(vol, BATCH ? run.gvoff : kb,
-                     ((C == 0 ? 4 : 5) * NQ2 + q) * KP);
-        if constexpr (C == 0) x *= k.c2s;
-        xw[(C * NQ2 + q) * kWave + lane] = x;
-      }
-    }
-  } else {
+  R wq[C == 0 ? 1 : NQ2];
+  if constexpr (C == 0) {
 #pragma unroll
     for (int q = 0; q < NQ2; ++q)
-      wq[q] = ldr<R>(vol, BATCH ? run.gvoff : kb,
-                     ((C == 0 ? 4 : 5) * NQ2 + q) * KP);
-    if constexpr (C == 0) {
+      xw[q * kWave + lane] = ldr<R>(vol, BATCH ? run.gvoff : kb, (4 * NQ2 + q) * KP) * k.c2s;
+  } else {
 #pragma unroll
-      for (int q = 0; q < NQ2; ++q) wq[q] *= k.c2s;
-    }
+    for (int q = 0; q < NQ2; ++q) wq[q] = ldr<R>(vol, BATCH ? run.gvoff : kb, (5 * NQ2 + q) * KP);
   }
-  R resv[NP];
+  R resv[NP], qv[NP];
   load_res<R, NP, kStage>(k, make_rsrc(run.res + grp(s0), tile * sizeof(R)), C, kb, resv);
-  wait_vm_all();                                             // metric rows in LDS
+  if constexpr (C == 0) wait_vm_all();                       // metric rows in LDS
   __syncthreads();                                           // prologue done
-  for (int it = 0; it < nit; ++it) {
-    const int s = s0 + it;
-    const R* t = tq[it & 1];
-    auto Pt = [&](int n) { return t[n * kWave + lane]; };
-    // the nodal values the volume term reads, in registers for all of its
-    // columns: u and v (pressure), p (velocity)
-    R x0[NP], x1[C == 0 ? NP : 1];
+  for (int it = 0; it <= nit; ++it) {
+    if (it > 0) {
+      const int s = s0 + it - 1;
+      R b[NP];
 #pragma unroll
-    for (int n = 0; n < NP; ++n) {
-      x0[n] = t[((C == 0 ? NP : 0) + n) * kWave + lane];
-      if constexpr (C == 0) x1[n] = t[(2 * NP + n) * kWave + lane];
-    }
-    auto X0 = [&](int n) { return x0[n]; };
-    auto X1 = [&](int n) { return x1[n]; };
-    R b[NP];
+      for (int n = 0; n < NP; ++n) b[n] = xb[(C * NP + n) * kWave + lane];
+      R dq[NP];
+      if constexpr (C == 0) {
+        R wl[NQ2];
 #pragma unroll
-    for (int n = 0; n < NP; ++n) b[n] = R(0);
-#pragma unroll
-    for (int i = 0; i < NQ; ++i) {
-      // this column's metric terms, requested before its first products
-      // (which need only the nodal values) so that they arrive meanwhile
-      R gc[4][NQ];
-      order();
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int jj = 0; jj < NQ; ++jj)
-          if (C == 0 || q == C - 1 || q == C + 1)
-            gc[q][jj] = xm[(q * NQ2 + i + NQ * jj) * kWave + (BATCH ? run.glane : lane)];
-          else
-            gc[q][jj] = R(0);
-      if constexpr (C == 0)
-        pressure_volume_column<R, N, NQ>(i, X0, X1, gc, b);
-      else
-        velocity_component_column<R, N, NQ, C>(i, X0, gc, b);
-      pin(b);
-    }
-    __syncthreads();                                         // face terms ready
-#pragma unroll
-    for (int f = 0; f < 4; ++f)
-#pragma unroll
-      for (int m = 0; m < NP1; ++m)
-        b[fnode<N>(f, m)] += xf[((f * 3 + C) * NP1 + m) * kWave + lane];
-    R dq[NP];
-    if constexpr (kLdsW) {
-      R wl[NQ2];
-#pragma unroll
-      for (int q = 0; q < NQ2; ++q) wl[q] = xw[((C == 0 ? 0 : 1) * NQ2 + q) * kWave + lane];
-      wadg_inverse_wide<R, N, NQ>(b, wl, dq);
-    } else {
-      wadg_inverse_wide<R, N, NQ>(b, wq, dq);
-    }
-    const rsrc_t qo = make_rsrc(run.qout + grp(s), tile * sizeof(R));
-    const rsrc_t rw = make_rsrc(run.resw + grp(s), run.res_bytes);
-    const bool active = e < (s == run.slast ? run.klast : run.kfull);
-    if constexpr (!RD) {
-      if constexpr (NT)
-        finish_field_nt<R, NP>(k, qo, rw, Pt, C, kb, active, resv, dq);
-      else
-        finish_field<R, NP, kStage>(k, qo, rw, Pt, C, kb, active, resv, dq);
-    } else if (active) {
-      // finish_field's arithmetic without the residual's stores
-#pragma unroll
-      for (int n = 0; n < NP; ++n) {
-        const R r = mad(k.A, resv[n], k.dt * dq[n]);
-        const R q = mad(k.B, r, Pt(C * NP + n));
+        for (int q = 0; q < NQ2; ++q) wl[q] = xw[q * kWave + lane];
+        wadg_inverse_wide<R, N, NQ>(b, wl, dq);
+      } else {
+        wadg_inverse_wide<R, N, NQ>(b, wq, dq);
+      }
+      const rsrc_t qo = make_rsrc(run.qout + grp(s), tile * sizeof(R));
+      const rsrc_t rw = make_rsrc(run.resw + grp(s), run.res_bytes);
+      const bool active = e < (s == run.slast ? run.klast : run.kfull);
+      auto Qv = [&](int n) { return qv[n - C * NP]; };
+      if constexpr (!RD) {
         if constexpr (NT)
-          st_nt(qo, kb, (C * NP + n) * KP, q);
+          finish_field_nt<R, NP>(k, qo, rw, Qv, C, kb, active, resv, dq);
         else
-          st(qo, kb, (C * NP + n) * KP, q);
+          finish_field<R, NP, kStage>(k, qo, rw, Qv, C, kb, active, resv, dq);
+      } else if (active) {
+        // finish_field's arithmetic without the residual's stores
+#pragma unroll
+        for (int n = 0; n < NP; ++n) {
+          const R r = mad(k.A, resv[n], k.dt * dq[n]);
+          const R q = mad(k.B, r, qv[n]);
+          if constexpr (NT)
+            st_nt(qo, kb, (C * NP + n) * KP, q);
+          else
+            st(qo, kb, (C * NP + n) * KP, q);
+        }
+      }
+      // the next item's residual; in a first stage (A = 0) resv keeps the
+      // zeros the prologue gave it (batches: only for real elements)
+      if (it < nit && k.A != R(0) && (!BATCH || lane < run.kact(s + 1))) {
+        const rsrc_t rn = make_rsrc(run.res + grp(s + 1), tile * sizeof(R));
+#pragma unroll
+        for (int n = 0; n < NP; ++n)
+          resv[n] = NT ? ldr_nt<R>(rn, kb, (C * NP + n) * KP) : ldr<R>(rn, kb, (C * NP + n) * KP);
       }
     }
-    // the next slice's residual; in a first stage (A = 0) resv keeps the
-    // zeros the prologue gave it -- rewriting them would wait for this
-    // item's stores, whose registers the compiler cannot tell apart
-    // (batches: only for the next slice's real elements)
-    if (it + 1 < nit && k.A != R(0) && (!BATCH || lane < run.kact(s + 1))) {
-      const rsrc_t rn = make_rsrc(run.res + grp(s + 1), tile * sizeof(R));
+    if (it < nit) {
+      // item it's input values of this field, before its buffer is refilled
+      const R* t = tq[it & 1];
 #pragma unroll
-      for (int n = 0; n < NP; ++n)
-        resv[n] = NT ? ldr_nt<R>(rn, kb, (C * NP + n) * KP) : ldr<R>(rn, kb, (C * NP + n) * KP);
+      for (int n = 0; n < NP; ++n) qv[n] = t[(C * NP + n) * kWave + lane];
     }
-    __syncthreads();                                         // item done
+    __syncthreads();                                         // face terms ready
+    __syncthreads();                                         // load vectors handed over
   }
 }
 
 // One run over the eight waves of the workgroup, on the workgroup's LDS
-// arrays (Pipe<>).  Waves 0..2 (one per SIMD) carry the volume terms and
-// the updates of p, u, v; wave 4 shares SIMD 0 with the pressure wave as the
-// loader; waves 3, 5, 6, 7 the faces 0..3.
+// arrays (Pipe<>).  SIMD s (wave w on SIMD w mod 4): waves 0..2 the volume
+// terms of p, u, v (wave 2 also loads the tiles), waves 4..6 the mass
+// inverses and updates of p, u, v, waves 3 and 7 the faces 0, 1 and 2, 3.
 template <typename R, int N, int NQ, bool RD, bool NT, bool BATCH>
 __device__ __forceinline__ void pipe_run(const PipeRun<R>& run, const StageScalars<R>& k,
                                          R (*tq)[Pipe<R, N, NQ>::tile_alloc], R* xm, R* xf,
-                                         R* xw) {
+                                         R* xb, R* xw) {
   using L = Pipe<R, N, NQ>;
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & (kWave - 1);
   const unsigned kb = (unsigned)lane * sizeof(R);
-  constexpr int kLoader = 4;
-  auto tile_src = [&](int s) { return make_rsrc(run.qin + run.grp(s), L::tile_bytes); };
 
-  // prologue: metric planes 0..3 of the group into LDS by the update waves
-  // and the loader (the face waves gather their first traces meanwhile),
-  // the first tile by the loader
-  if (wave <= 2 || wave == kLoader) {
-    const int w = wave == kLoader ? 3 : wave;
+  // prologue: metric planes 0..3 of the group into LDS by waves 0..3 (the
+  // face waves gather their first traces meanwhile)
+  if (wave <= 3) {
+    const int w = wave;
     if (!BATCH || run.gelems > 0) {
       if (!BATCH || row_lane_needed(lane, run.gelems))
         rows_to_lds<L::metric_rows>(run.vol, xm, w, 4, lane);
@@ -493,35 +531,21 @@ __device__ __forceinline__ void pipe_run(const PipeRun<R>& run, const StageScala
     }
   }
   if (wave == 0) {
-    pipe_update_role<R, N, NQ, 0, RD, NT, BATCH>(run, k, lane, kb, tq, xm, xf, xw);
+    pipe_volume_role<R, N, NQ, 0, false, BATCH>(run, lane, tq, xm, xf, xb);
   } else if (wave == 1) {
-    pipe_update_role<R, N, NQ, 1, RD, NT, BATCH>(run, k, lane, kb, tq, xm, xf, xw);
+    pipe_volume_role<R, N, NQ, 1, false, BATCH>(run, lane, tq, xm, xf, xb);
   } else if (wave == 2) {
-    pipe_update_role<R, N, NQ, 2, RD, NT, BATCH>(run, k, lane, kb, tq, xm, xf, xw);
-  } else if (wave == kLoader) {
-    // the next slice's tile while this one is computed
-    // (batches: only the rows' values of the slice's real elements)
-    auto tile_in = [&](int s, R* dst) {
-      if (!BATCH || row_lane_needed(lane, run.kact(s)))
-        tile_to_lds<L::rows>(tile_src(s), dst, lane);
-    };
-    tile_in(run.s0, tq[0]);
-    wait_vm_all();
-    __syncthreads();                                         // prologue done
-    for (int it = 0; it < run.nit; ++it) {
-      if (it + 1 < run.nit) tile_in(run.s0 + it + 1, tq[(it + 1) & 1]);
-      __syncthreads();                                       // face terms ready
-      wait_vm_all();                                         // next tile in LDS
-      __syncthreads();                                       // item done
-    }
+    pipe_volume_role<R, N, NQ, 2, true, BATCH>(run, lane, tq, xm, xf, xb);
   } else if (wave == 3) {
-    pipe_face_role<R, N, NQ, 0, BATCH>(run, k, lane, kb, tq, xf);
+    pipe_inverse_role<R, N, NQ, 0, RD, NT, BATCH>(run, k, lane, kb, tq, xb, xw);
   } else if (wave == 5) {
-    pipe_face_role<R, N, NQ, 1, BATCH>(run, k, lane, kb, tq, xf);
+    pipe_inverse_role<R, N, NQ, 1, RD, NT, BATCH>(run, k, lane, kb, tq, xb, xw);
   } else if (wave == 6) {
-    pipe_face_role<R, N, NQ, 2, BATCH>(run, k, lane, kb, tq, xf);
+    pipe_inverse_role<R, N, NQ, 2, RD, NT, BATCH>(run, k, lane, kb, tq, xb, xw);
+  } else if (wave == 4) {
+    pipe_face_role<R, N, NQ, 0, 1, BATCH>(run, k, lane, kb, tq, xf);
   } else {
-    pipe_face_role<R, N, NQ, 3, BATCH>(run, k, lane, kb, tq, xf);
+    pipe_face_role<R, N, NQ, 2, 3, BATCH>(run, k, lane, kb, tq, xf);
   }
 }
 
@@ -541,7 +565,8 @@ __global__ __launch_bounds__(8 * kWave) void pipe_kernel(const StageParams p, in
   __shared__ __attribute__((aligned(1024))) R tq[2][L::tile_alloc];
   __shared__ __attribute__((aligned(16))) R xm[L::metric];
   __shared__ __attribute__((aligned(16))) R xf[L::xf];
-  __shared__ __attribute__((aligned(16))) R xw[L::weights_in_lds ? L::wts : 1];
+  __shared__ __attribute__((aligned(16))) R xb[L::xb];
+  __shared__ __attribute__((aligned(16))) R xw[L::wp];
 
   // workgroup -> (group, slice run), XCD-aware: each XCD takes a
   // contiguous range of groups, so most neighbour traces are read by
@@ -572,7 +597,7 @@ __global__ __launch_bounds__(8 * kWave) void pipe_kernel(const StageParams p, in
   run.gelems = kWave;
   run.gvoff = run.gfoff = 0;
   run.res_bytes = RD ? 0u : L::tile * sizeof(R);
-  pipe_run<R, N, NQ, RD, NT, false>(run, stage_scalars<R>(p), tq, xm, xf, xw);
+  pipe_run<R, N, NQ, RD, NT, false>(run, stage_scalars<R>(p), tq, xm, xf, xb, xw);
 }
 
 // Batched LSRK stage (FP64) over a list of runs of many independent
@@ -592,7 +617,8 @@ __global__ __launch_bounds__(8 * kWave) void batch_pipe_kernel(const BatchParams
   __shared__ __attribute__((aligned(1024))) R tq[2][L::tile_alloc];
   __shared__ __attribute__((aligned(16))) R xm[L::metric];
   __shared__ __attribute__((aligned(16))) R xf[L::xf];
-  __shared__ __attribute__((aligned(16))) R xw[L::weights_in_lds ? L::wts : 1];
+  __shared__ __attribute__((aligned(16))) R xb[L::xb];
+  __shared__ __attribute__((aligned(16))) R xw[L::wp];
   const int r = blockIdx.x;
   if (r >= nruns || runs[4 * r] < 0) return;   // whole workgroup: no barrier reached
   const int pi = runs[4 * r], g = runs[4 * r + 1];
@@ -640,7 +666,7 @@ __global__ __launch_bounds__(8 * kWave) void batch_pipe_kernel(const BatchParams
   k.B = bp.rkB;
   k.dt = pr.dt;
   k.c2s = 1.0;
-  pipe_run<R, N, NQ, RD, NT, true>(run, k, tq, xm, xf, xw);
+  pipe_run<R, N, NQ, RD, NT, true>(run, k, tq, xm, xf, xb, xw);
 }
 
 namespace {
