@@ -95,7 +95,7 @@ __device__ __forceinline__ bool row_lane_needed(int lane, int elems) {
   return 2 * (lane & 31) < elems;
 }
 
-// The loader wave's request of one input tile: `rows` direct-to-LDS loads of
+// The tile loader's request of one input tile: `rows` direct-to-LDS loads of
 // 64 lanes x 16 B, row r landing at dst + 1 KB r.
 template <unsigned ROWS>
 __device__ __forceinline__ void tile_to_lds(rsrc_t src, void* dst, int lane) {
