@@ -148,6 +148,23 @@ def common(args, value, ms_per_step, dtype, config):
             "data": "synthetic", "config": config}
 
 
+# Floating-point operations per element and LSRK stage, sum-factorised, at
+# N = 3 with 5 Gauss points per direction: volume 3,180, mass inverse
+# 2,235, surface 2,224, update 192 (the volume and inverse parts follow
+# from the operation counts of the kernels' contractions; FMA = 2).
+FLOPS_PER_ELEMENT_STAGE = {(3, 5): 7831}
+PEAK_FP32_TFLOPS = 157.3
+
+
+def roofline_alu(flops_launch, stage_ms, peak_tflops):
+    """The FP32 path's arithmetic roofline: its kernels issue no packed
+    (two-wide) FP32 instructions, so half the peak is their ceiling."""
+    achieved = flops_launch / (stage_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": peak_tflops, "unit": "TFLOP/s",
+            "frac": achieved / peak_tflops, "flops_per_launch": flops_launch,
+            "frac_of_unpacked_rate": achieved / (peak_tflops / 2)}
+
+
 def roofline(kname, bytes_launch, stage_ms, traffic=None, bytes_4=None):
     achieved = bytes_launch / (stage_ms * 1e-3) / 1e9
     r = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -234,10 +251,14 @@ def run_fp32(args):
     # the events bracket the whole call: 5 nsteps stage launches plus the two
     # FP64<->FP32 conversions at the ends of the sweep
     kname = f"{k}<float,{N},{prob.nq1}>"
-    line["roofline"] = roofline(kname, stage_bytes(K, S, N, prob.nq1, word=4),
-                                sum(ev) / (args.steps * 5 * prob.nsteps),
+    stage_ms = sum(ev) / (args.steps * 5 * prob.nsteps)
+    line["roofline"] = roofline(kname, stage_bytes(K, S, N, prob.nq1, word=4), stage_ms,
                                 measured_traffic(kname, prob.name),
                                 stage_bytes_4(K, S, N, prob.nq1, word=4))
+    fl = FLOPS_PER_ELEMENT_STAGE.get((N, prob.nq1))
+    if fl is not None:
+        # the arithmetic bound of this path (the HBM one above is not reached)
+        line["roofline_alu"] = roofline_alu(fl * K * S, stage_ms, PEAK_FP32_TFLOPS)
     line["max_rel_err_vs_fp64_sweep"] = rel
     line["max_rel_l2_err_vs_fp64_sweep"] = rel_l2
     if args.cpu_baseline_seconds > 0:

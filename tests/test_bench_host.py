@@ -56,6 +56,20 @@ def test_four_array_count_by_hand():
     assert "frac_4_state_arrays" not in bench.roofline("k", 8e9, 1.0)
 
 
+def test_alu_roofline_by_hand():
+    # the scope table's flop count at N = 3, nq1 = 5: volume 3,180 + mass
+    # inverse 2,235 + surface 2,224 + update 192; the volume part by hand:
+    # per column and field group 4 (N+1)^2 + nq1 (4 (N+1) + 2) FMAs and 2 nq1
+    # products, 5 columns, 2 groups
+    vol = 2 * 5 * (2 * (4 * 16 + 5 * (4 * 4 + 2)) + 2 * 5)
+    inv = 3 * (2 * (2 * 5 * 16 + 2 * 25 * 4) + 25)
+    assert (vol, inv) == (3180, 2235)
+    assert bench.FLOPS_PER_ELEMENT_STAGE[(3, 5)] == vol + inv + 2224 + 192
+    r = bench.roofline_alu(157.3e9, 1.0, 157.3)
+    assert r["bound"] == "alu" and r["frac"] == pytest.approx(1.0)
+    assert r["frac_of_unpacked_rate"] == pytest.approx(2.0)
+
+
 def test_roofline_fields():
     r = bench.roofline("k", 8e9, 1.0, traffic=4e9)
     assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
