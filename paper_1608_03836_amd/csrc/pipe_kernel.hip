@@ -504,9 +504,9 @@ __device__ __forceinline__ void pipe_inverse_role(const PipeRun<R>& run, const S
 }
 
 // One run over the eight waves of the workgroup, on the workgroup's LDS
-// arrays (Pipe<>).  SIMD s (wave w on SIMD w mod 4): waves 0..2 the volume
-// terms of p, u, v (wave 2 also loads the tiles), waves 4..6 the mass
-// inverses and updates of p, u, v, waves 3 and 7 the faces 0, 1 and 2, 3.
+// arrays (Pipe<>).  Wave w runs on SIMD w mod 4: waves 0..2 the volume
+// terms of p, u, v (wave 2 also loads the tiles), waves 3, 5, 6 the mass
+// inverses and updates of p, u, v, waves 4 and 7 the faces 0, 1 and 2, 3.
 template <typename R, int N, int NQ, bool RD, bool NT, bool BATCH>
 __device__ __forceinline__ void pipe_run(const PipeRun<R>& run, const StageScalars<R>& k,
                                          R (*tq)[Pipe<R, N, NQ>::tile_alloc], R* xm, R* xf,
