@@ -311,8 +311,10 @@ int wadg_adjoint(wadg_ctx ctx, const double* chk, const double* seed, double* gr
  *   graph reads its own copy of the per-problem dt, so later integrate calls
  *   with other dt do not change what it computes.  wadg_batch_replay
  *   launches it on `stream` (each replay advances Q by nsteps steps again).
- *   wadg_batch_release_graph frees it; set_schedule, set_runs and tune
- *   refuse while a graph is held.
+ *   wadg_batch_release_graph frees it (after the device has drained, so
+ *   replays still queued finish first; so does a new capture, which replaces
+ *   the graph); set_schedule, set_runs and tune refuse while a graph is
+ *   held.
  * A call that changes the device-side work list (set_schedule, set_runs,
  * tune) or
  * the per-problem dt (integrate, tune, capture with dt other than the last)

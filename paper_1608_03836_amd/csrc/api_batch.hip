@@ -47,6 +47,7 @@ constexpr int kBatchRunSlices = 16;
 
 void free_batch(wadg_batch b) {
   if (!b) return;
+  if (b->exec || b->graph) (void)hipDeviceSynchronize();   // replays still queued
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
@@ -200,6 +201,18 @@ int batch_upload_dt(wadg_batch b, const double* dt) {
   if (same) return WADG_OK;
   if ((st = write_descriptors(b, dt, b->d_prob))) return st;
   b->dt.assign(dt, dt + b->nprob);
+  return WADG_OK;
+}
+
+// Frees the captured graph, if any, once the device has drained, so that
+// no replay still queued on any stream runs from a destroyed graph.
+int drop_graph(wadg_batch b) {
+  if (!b->exec && !b->graph) return WADG_OK;
+  WADG_HIP(hipDeviceSynchronize());
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
   return WADG_OK;
 }
 
@@ -570,10 +583,7 @@ int wadg_batch_capture(wadg_batch b, double* Q, double* work, const double* dt, 
   if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select the batch's device");
   int st = check_dt(b, dt);
   if (st) return st;
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
-  b->exec = nullptr;
-  b->graph = nullptr;
+  if ((st = drop_graph(b))) return st;
   // the graph's own descriptors, written once here (after any replay of an
   // earlier graph has drained); eager sweeps never touch them
   if ((st = write_descriptors(b, dt, b->d_prob_graph))) return st;
@@ -605,11 +615,8 @@ int wadg_batch_replay(wadg_batch b, void* stream) {
 int wadg_batch_release_graph(wadg_batch b) {
   if (!b) return fail(WADG_E_INVALID, "batch is NULL");
   DeviceGuard guard(b->device);
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
-  b->exec = nullptr;
-  b->graph = nullptr;
-  return WADG_OK;
+  if (!guard.ok) return fail(WADG_E_DEVICE, "cannot select the batch's device");
+  return drop_graph(b);
 }
 
 }  // extern "C"

@@ -3,9 +3,9 @@ of a batch advanced by one launch per LSRK stage equals the same problem
 advanced alone (bitwise: the same per-item arithmetic) and the oracle (to
 the FP64 bar); results are bitwise independent of the schedule and of the
 autotuner's choice; a captured HIP graph replays the eager sweep exactly,
-replay after replay, with eager work and synchronisations between them; and
-the full 1000-problem workload matches the single-problem path on sampled
-problems."""
+replay after replay, with eager work and synchronisations between them, and
+a recapture or release waits for replays still queued; and the full
+1000-problem workload matches the single-problem path on sampled problems."""
 
 import numpy as np
 import pytest
@@ -169,6 +169,39 @@ def test_graph_keeps_its_dt_when_eager_calls_change_it(W, small):
         for a, b in zip(batch.download(Qg), batch.download(want_a)):
             assert np.array_equal(a, b)
         for a, b in zip(batch.download(Qe), batch.download(want_b)):
+            assert np.array_equal(a, b)
+    finally:
+        batch.release_graph()
+
+
+def test_recapture_and_release_with_replays_queued(W, small):
+    """A new capture replaces a graph whose replays are still queued on
+    another stream, and a release frees one with a replay queued: both wait
+    for the device to drain, so every queued replay runs whole."""
+    import torch
+    _print_case(test="batch-graph-recapture")
+    probs, batch = small
+    dts = [p.dt for p in probs]
+    want2 = batch.upload([p.Q0 for p in probs])
+    batch.integrate(want2, dts, 2)
+    want4 = batch.upload([p.Q0 for p in probs])
+    batch.integrate(want4, dts, 4)
+    torch.cuda.synchronize()
+    Qg, wg = batch.upload([p.Q0 for p in probs]), batch.workspace()
+    Qh, wh = batch.upload([p.Q0 for p in probs]), batch.workspace()
+    side = torch.cuda.Stream()
+    try:
+        batch.capture(Qg, wg, dts, 1)
+        batch.replay(stream=side)
+        batch.replay(stream=side)                  # queued, not waited for
+        batch.capture(Qh, wh, dts, 2)              # replaces the graph
+        batch.replay(stream=side)
+        batch.replay(stream=side)
+        batch.release_graph()                      # with a replay queued
+        torch.cuda.synchronize()
+        for a, b in zip(batch.download(Qg), batch.download(want2)):
+            assert np.array_equal(a, b)
+        for a, b in zip(batch.download(Qh), batch.download(want4)):
             assert np.array_equal(a, b)
     finally:
         batch.release_graph()
