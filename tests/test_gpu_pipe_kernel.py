@@ -3,12 +3,14 @@ split kernel (bitwise: same arithmetic in the same order) and against the
 oracle, on shapes that exercise its slice runs -- one run per group and
 several, runs of one slice (no prefetch), more runs than slices, a ragged
 last element group, N = 1..3 with quadratures that fit -- in FP64 and
-FP32-bulk; and its selection rules."""
+FP32-bulk; at full size in the benchmark's launch configuration (its
+non-temporal instances), every output value against the split kernel's;
+and its selection rules."""
 
 import numpy as np
 import pytest
 
-from workloads import periodic_quad_mesh, c2_layered
+from workloads import periodic_quad_mesh, c2_layered, make_problem
 from oracle import WADGOracle
 
 pytestmark = pytest.mark.gpu
@@ -60,6 +62,31 @@ def test_pipe_equals_split_bitwise(W, N, dq, K1D, S, nsteps):
     for a, b in zip(out[W.WADG_KERNEL_SPLIT], out[W.WADG_KERNEL_PIPE]):
         assert np.all(np.isfinite(a))
         assert np.array_equal(a, b)
+
+
+def test_pipe_full_size_equals_split_bitwise(W):
+    """wadg128 at full size (256 slices x 10 steps, heterogeneous c^2) as the
+    benchmark runs it: the automatic choice takes the pipelined kernel's
+    non-temporal instances, since a launch's state far exceeds the caches.
+    Every output value, FP64 and FP32-bulk, equals the split kernel's."""
+    import torch
+    _print_case(test="pipe-vs-split-full-size", workload="wadg128")
+    prob = make_problem("wadg128")
+    sol = W.Solver.from_problem(prob)
+    assert sol.kernel_in_use() == W.WADG_KERNEL_PIPE
+    assert sol.kernel_in_use(fp32=True) == W.WADG_KERNEL_PIPE
+    out = {}
+    for kern in (W.WADG_KERNEL_AUTO, W.WADG_KERNEL_SPLIT):
+        sol.set_kernel(kern)
+        Q = sol.upload(prob.Q0)
+        sol.integrate(Q, prob.S, prob.dt, prob.nsteps)
+        Q32 = sol.upload(prob.Q0)
+        sol.integrate_fp32(Q32, prob.S, prob.dt, prob.nsteps)
+        torch.cuda.synchronize()
+        out[kern] = (Q, Q32)
+    for a, b in zip(out[W.WADG_KERNEL_AUTO], out[W.WADG_KERNEL_SPLIT]):
+        assert bool(torch.isfinite(a).all())
+        assert torch.equal(a, b)
 
 
 def test_pipe_matches_oracle(W):
