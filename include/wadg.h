@@ -416,15 +416,19 @@ int wadg_set_schedule(wadg_ctx ctx, int32_t groups_per_tile, int32_t slices_per_
  *     or N = 3 with nq1 <= 5; elsewhere a RESIDENT request falls back to
  *     the streamed kernel for that precision.
  *   WADG_KERNEL_PIPE: LSRK stages only (FP64 and FP32-bulk): one
- *     512-thread workgroup per CU that owns one element group and a run of
- *     its slices, keeps the group's geometry on chip for the whole run and
- *     streams the next slice's input tile into LDS while computing the
- *     current one; ignores wadg_set_schedule.  Needs two input tiles, the
- *     metric planes, the face terms and the two mass-weight planes in LDS
- *     (N <= 3 in FP64, every N in FP32); launches of fewer than two slices,
- *     right-hand sides and the adjoint's launches take the split kernel.
- *     Launches whose state (Q in, Q out and the residual) exceeds 512 MB
- *     store their outputs with the non-temporal cache hint.
+ *     512-thread workgroup per CU (two in FP32 where both fit in LDS) that
+ *     owns one element group and a run of its slices, keeps the group's
+ *     geometry on chip for the whole run, streams the next slice's input tile into LDS while
+ *     computing the current one, and applies one slice's mass inverse and
+ *     update while the next slice's volume and face terms are formed (a
+ *     two-stage pipeline over the slices); ignores wadg_set_schedule.
+ *     Needs two input tiles, the metric planes, the face terms, the
+ *     handed-over load vectors and the pressure mass weights in LDS (FP64:
+ *     N <= 3 with nq1 <= N + 2; FP32: every N, nq1); launches of fewer than
+ *     two slices, right-hand sides and the adjoint's launches take the
+ *     split kernel.  Launches whose state (Q in, Q out and the residual)
+ *     exceeds 512 MB store their outputs and load the residual with the
+ *     non-temporal cache hint.
  *   WADG_KERNEL_AUTO (default): LSRK stages (FP64 and FP32) of two or more
  *     slices take the pipelined kernel where it fits, else the split
  *     kernel; right-hand-side launches the resident kernel where it fits,
