@@ -193,9 +193,9 @@ __device__ __forceinline__ void velocity_component_column(int i, const FP& P,
 
 // The mass inverse of wadg_inverse with every accumulator formed by the
 // same operations in the same order, but all quadrature columns' partial
-// results computed before any is projected back: the columns proceed in
-// parallel instead of one after another, for a wave that has its SIMD to
-// itself.
+// results computed before any is projected back: the columns' independent
+// chains interleave instead of following one another, which hides the
+// latency of each dependent FMA.
 template <typename R, int N, int NQ>
 __device__ __forceinline__ void wadg_inverse_wide(const R (&b)[(N + 1) * (N + 1)],
                                                   const R (&w)[NQ * NQ],
