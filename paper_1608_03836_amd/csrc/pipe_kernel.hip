@@ -34,6 +34,8 @@
 //   -- barrier: face terms of item j in LDS
 //   waves 0..2 add them in face order and hand the load vectors over
 //   -- barrier: load vectors handed over, the next tile in LDS
+// Between the two waves of a SIMD the inverse waves have issue priority,
+// then the pressure volume wave, then the velocity volume waves.
 //
 // A first stage (A = 0) requests no residual; the last stage of a step,
 // whose residual is never read again, is a kernel instance of its own that
@@ -530,6 +532,16 @@ __device__ __forceinline__ void pipe_run(const PipeRun<R>& run, const StageScala
         xm[pp * kWave + lane] = ldr<R>(run.vol, run.gvoff, (unsigned)pp * KP);
     }
   }
+  // Issue priority between the waves of a SIMD (s_setprio): the inverse
+  // waves, which issue each item's stores and residual loads, first; then
+  // the pressure volume wave, the longest role; then the velocity volume
+  // waves; the face waves keep the default.
+  if (wave == 0) __builtin_amdgcn_s_setprio(2);
+  if (wave == 1) __builtin_amdgcn_s_setprio(1);
+  if (wave == 2) __builtin_amdgcn_s_setprio(1);
+  if (wave == 3) __builtin_amdgcn_s_setprio(3);
+  if (wave == 5) __builtin_amdgcn_s_setprio(3);
+  if (wave == 6) __builtin_amdgcn_s_setprio(3);
   if (wave == 0) {
     pipe_volume_role<R, N, NQ, 0, false, BATCH>(run, lane, tq, xm, xf, xb);
   } else if (wave == 1) {
